@@ -1,0 +1,1185 @@
+/*
+ * adg_oracle.c — FP64 CPU oracle: asynchronous discontinuous Galerkin (ADG)
+ * solver for the compressible Euler equations with asynchrony-tolerant (AT)
+ * neighbour traces, SSP-RK3 in time.
+ *
+ * TEST INFRASTRUCTURE ONLY (see adg_oracle.h). Plain C99 + optional OpenMP.
+ *
+ * What it follows, passage by passage (arXiv 2603.28710):
+ *   - conservative Euler system, closure E = p/(gamma-1) + rho|u|^2/2, G = 0
+ *     (Sec. 2, eq. euler-dealii / euler-parameters-dealii);
+ *   - nodal DG weak form on each element, integrated by parts, with the
+ *     element mass matrix on the left (Sec. 2.1, eq. weakform-dealii and
+ *     weakform-compact-dealii);
+ *   - the local Lax-Friedrichs numerical flux with its dissipation parameter
+ *     lambda exactly as printed, i.e. carrying a factor 1/2 (Sec. 2.2,
+ *     eq. lfflux and lfflux-lambda);
+ *   - interior / PE-boundary classification of faces under a block domain
+ *     decomposition (Sec. 2.4, Fig. Domain-decomposition);
+ *   - delayed neighbour data bounded by a maximum delay L (Sec. 3,
+ *     eq. euler-adg-compact and delayed-flux), the communication-avoiding
+ *     schedules (Sec. 3.1 Alg. caa-std, Sec. 3.3 Alg. caa-at);
+ *   - AT coefficients from the moment constraints, with the stage-fractional
+ *     delay of the naive RK coupling (Sec. 3.2, eq. at-flux-constraints,
+ *     Table at-flux-coeffs).
+ * Readings where the paper is silent (time integrator SSP-RK3, what is delayed,
+ * delay draws, warm-up, learned correction) are the ones listed in the design
+ * notes; each is marked "reading" below.
+ */
+#include "adg_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXN 8 /* max nodes or Gauss points per direction */
+#define MAXV 5
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Legendre polynomials, Gauss and Gauss-Lobatto-Legendre rules             */
+/* ------------------------------------------------------------------------ */
+
+/* P_n(x) and P_{n-1}(x) by the three-term recurrence */
+static void legendre_pair(int n, double x, double* pn, double* pnm1) {
+  double a = 1.0, b = x;
+  if (n == 0) {
+    *pn = 1.0;
+    *pnm1 = 0.0;
+    return;
+  }
+  for (int k = 2; k <= n; ++k) {
+    double c = ((2.0 * k - 1.0) * x * b - (k - 1.0) * a) / k;
+    a = b;
+    b = c;
+  }
+  *pn = b;
+  *pnm1 = a;
+}
+
+static void sort_pairs(int n, double* x, double* w) {
+  for (int i = 1; i < n; ++i)
+    for (int j = i; j > 0 && x[j - 1] > x[j]; --j) {
+      double t = x[j];
+      x[j] = x[j - 1];
+      x[j - 1] = t;
+      t = w[j];
+      w[j] = w[j - 1];
+      w[j - 1] = t;
+    }
+}
+
+/* Gauss-Legendre: the n roots of P_n, weights 2 / ((1-x^2) P_n'(x)^2) */
+void orc_gauss(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = cos(ORC_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double pn, pm;
+      legendre_pair(n, z, &pn, &pm);
+      double dp = n * (z * pn - pm) / (z * z - 1.0);
+      double dz = pn / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    double pn, pm;
+    legendre_pair(n, z, &pn, &pm);
+    double dp = n * (z * pn - pm) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  sort_pairs(n, x, w);
+}
+
+/* Gauss-Lobatto-Legendre with n points (N = n-1): the end points and the roots
+ * of P_N'; weights 2 / (N (N+1) P_N(x)^2). */
+void orc_gll(int n, double* x, double* w) {
+  int N = n - 1;
+  for (int i = 0; i < n; ++i) {
+    double z = -cos(ORC_PI * i / N);
+    if (i > 0 && i < N) {
+      for (int it = 0; it < 100; ++it) {
+        double pn, pm;
+        legendre_pair(N, z, &pn, &pm);
+        double d1 = N * (z * pn - pm) / (z * z - 1.0);           /* P_N'  */
+        double d2 = (2.0 * z * d1 - N * (N + 1.0) * pn) / (1.0 - z * z); /* P_N'' */
+        double dz = d1 / d2;
+        z -= dz;
+        if (fabs(dz) < 1e-16) break;
+      }
+    }
+    double pn, pm;
+    legendre_pair(N, z, &pn, &pm);
+    x[i] = z;
+    w[i] = 2.0 / (N * (N + 1.0) * pn * pn);
+  }
+  sort_pairs(n, x, w);
+}
+
+/* Lagrange basis on `nodes` and its derivative, evaluated at x (product form) */
+void orc_lagrange(int n, const double* nodes, double x, double* phi, double* dphi) {
+  for (int j = 0; j < n; ++j) {
+    double v = 1.0;
+    for (int m = 0; m < n; ++m)
+      if (m != j) v *= (x - nodes[m]) / (nodes[j] - nodes[m]);
+    if (phi) phi[j] = v;
+    if (dphi) {
+      double d = 0.0;
+      for (int i = 0; i < n; ++i) {
+        if (i == j) continue;
+        double t = 1.0 / (nodes[j] - nodes[i]);
+        for (int m = 0; m < n; ++m)
+          if (m != j && m != i) t *= (x - nodes[m]) / (nodes[j] - nodes[m]);
+        d += t;
+      }
+      dphi[j] = d;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* small dense linear algebra                                               */
+/* ------------------------------------------------------------------------ */
+
+/* solve A x = b (n x n, row-major, overwritten) by Gaussian elimination with
+ * partial pivoting; returns 0 on success */
+static int dense_solve(int n, double* A, double* b) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(A[r * n + c]) > fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0) return -1;
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) {
+        double t = A[c * n + k];
+        A[c * n + k] = A[piv * n + k];
+        A[piv * n + k] = t;
+      }
+      double t = b[c];
+      b[c] = b[piv];
+      b[piv] = t;
+    }
+    for (int r = c + 1; r < n; ++r) {
+      double f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double s = b[r];
+    for (int k = r + 1; k < n; ++k) s -= A[r * n + k] * b[k];
+    b[r] = s / A[r * n + r];
+  }
+  return 0;
+}
+
+/* inverse by Gauss-Jordan elimination with partial pivoting */
+static int dense_inverse(int n, const double* A, double* Ainv) {
+  double* W = (double*)malloc(sizeof(double) * n * 2 * n);
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < 2 * n; ++c) W[r * 2 * n + c] = c < n ? A[r * n + c] : (c - n == r ? 1.0 : 0.0);
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(W[r * 2 * n + c]) > fabs(W[piv * 2 * n + c])) piv = r;
+    if (W[piv * 2 * n + c] == 0.0) {
+      free(W);
+      return -1;
+    }
+    for (int k = 0; k < 2 * n; ++k) {
+      double t = W[c * 2 * n + k];
+      W[c * 2 * n + k] = W[piv * 2 * n + k];
+      W[piv * 2 * n + k] = t;
+    }
+    double d = W[c * 2 * n + c];
+    for (int k = 0; k < 2 * n; ++k) W[c * 2 * n + k] /= d;
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = W[r * 2 * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < 2 * n; ++k) W[r * 2 * n + k] -= f * W[c * 2 * n + k];
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) Ainv[r * n + c] = W[r * 2 * n + n + c];
+  free(W);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* AT weights (Sec. 3.2, eq. at-flux-constraints)                           */
+/* ------------------------------------------------------------------------ */
+
+/* Coefficients c_j of the levels at delays l_j = tau + j (in units of the time
+ * step), j = 0..nlev-1, from sum_j c_j (-l_j)^z / z! = [z == 0], z < nlev.
+ * With tau = k this is Table at-flux-coeffs; tau = k + c_m is the naive
+ * stage-fractional coupling. */
+int orc_at_weights(int nlev, double tau, double* c) {
+  double A[MAXN * MAXN], b[MAXN];
+  if (nlev < 1 || nlev > MAXN) return -1;
+  for (int z = 0; z < nlev; ++z) {
+    double fact = 1.0;
+    for (int i = 2; i <= z; ++i) fact *= i;
+    for (int j = 0; j < nlev; ++j) A[z * nlev + j] = pow(-(tau + j), z) / fact;
+    b[z] = z == 0 ? 1.0 : 0.0;
+  }
+  if (dense_solve(nlev, A, b)) return -1;
+  for (int j = 0; j < nlev; ++j) c[j] = b[j];
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* delay draws (reading: one draw per step, receiving subdomain, face dir)  */
+/* ------------------------------------------------------------------------ */
+
+/* SplitMix64 (Steele, Lea, Flood 2014): state advances by the golden gamma,
+ * output is the variant-13 style finaliser. Draw i of the stream seeded with
+ * `seed` is the finaliser applied to seed + (i+1) * gamma. */
+uint64_t orc_splitmix64_draw(uint64_t seed, uint64_t index) {
+  uint64_t z = seed + (index + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* ------------------------------------------------------------------------ */
+/* solver                                                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  orc_cfg c;
+  int D, P, Q, V, Pd, Qd, Fq, Fn, nf;
+  int64_t E, nsub;
+  int64_t nc[3];
+  double h[3], detJ, detJf[3];
+  double xg[MAXN], wg[MAXN], xl[MAXN], wl[MAXN];
+  double *phiV, *dphiV, *wV;  /* volume: [Qd][Pd], [D][Qd][Pd], [Qd] */
+  double *phiF, *wF;          /* faces: [nf][Fq][Pd], [Fq] */
+  double *phiFN;              /* face nodes: [nf][Fn][Pd] */
+  double *lagF;               /* face nodes -> face Gauss points: [Fq][Fn] */
+  double* Minv;               /* inverse reference mass matrix [Pd][Pd] */
+  double *u, *ua, *ub, *kb, *Fnum;
+  double* hist;
+  int R, Qh;
+  int64_t n;
+  double t;
+  /* learned predictor */
+  int has_mlp, nin, nh, nout;
+  float* mlp;
+  int64_t acc, rej;
+} orc_solver;
+
+static const int K_MLP = 4;   /* past levels the learned predictor reads */
+static const int NH_MLP = 64; /* hidden width */
+
+/* SSP-RK3 in Shu-Osher form: out = a u^n + b (u_in + dt L(u_in)), stage time c */
+static const double SSP_A[3] = {0.0, 0.75, 1.0 / 3.0};
+static const double SSP_B[3] = {1.0, 0.25, 2.0 / 3.0};
+static const double SSP_C[3] = {0.0, 1.0, 0.5};
+
+static int64_t elem_of(const orc_solver* s, int64_t i, int64_t j, int64_t k) {
+  return i + s->nc[0] * (j + s->nc[1] * k);
+}
+
+static void elem_ijk(const orc_solver* s, int64_t e, int64_t* ijk) {
+  ijk[0] = e % s->nc[0];
+  ijk[1] = (e / s->nc[0]) % s->nc[1];
+  ijk[2] = e / (s->nc[0] * s->nc[1]);
+}
+
+/* neighbour across face f = 2a + side (side 0: -a, side 1: +a), periodic */
+static int64_t neighbour(const orc_solver* s, int64_t e, int f) {
+  int64_t ijk[3];
+  elem_ijk(s, e, ijk);
+  int a = f / 2;
+  int64_t d = (f & 1) ? 1 : -1;
+  ijk[a] = (ijk[a] + d + s->nc[a]) % s->nc[a];
+  return elem_of(s, ijk[0], ijk[1], ijk[2]);
+}
+
+int64_t orc_subdomain(void* vs, int64_t e) {
+  orc_solver* s = (orc_solver*)vs;
+  int64_t ijk[3], sid = 0, mul = 1;
+  elem_ijk(s, e, ijk);
+  for (int a = 0; a < 3; ++a) {
+    int64_t per = s->nc[a] / s->c.parts[a];
+    sid += mul * (ijk[a] / per);
+    mul *= s->c.parts[a];
+  }
+  return sid;
+}
+
+static void* xmalloc(size_t n) {
+  void* p = calloc(1, n ? n : 1);
+  if (!p) {
+    fprintf(stderr, "oracle: out of memory (%zu bytes)\n", n);
+    abort();
+  }
+  return p;
+}
+
+void* orc_create(const orc_cfg* cfg) {
+  orc_solver* s = (orc_solver*)xmalloc(sizeof(orc_solver));
+  s->c = *cfg;
+  int D = cfg->dim;
+  if (D < 2 || D > 3 || cfg->p < 1 || cfg->p > 5) {
+    free(s);
+    return NULL;
+  }
+  s->D = D;
+  s->P = cfg->p + 1;
+  s->Q = cfg->nq > 0 ? cfg->nq : cfg->p + 2;
+  s->V = D + 2;
+  s->Pd = 1;
+  s->Qd = 1;
+  for (int k = 0; k < D; ++k) {
+    s->Pd *= s->P;
+    s->Qd *= s->Q;
+  }
+  s->Fq = s->Qd / s->Q;
+  s->Fn = s->Pd / s->P;
+  s->nf = 2 * D;
+  s->E = 1;
+  s->nsub = 1;
+  s->detJ = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    s->nc[k] = k < D ? cfg->cells[k] : 1;
+    if (k >= D) s->c.parts[k] = 1;
+    if (s->c.parts[k] < 1 || s->nc[k] % s->c.parts[k]) {
+      free(s);
+      return NULL;
+    }
+    s->E *= s->nc[k];
+    s->nsub *= s->c.parts[k];
+    s->h[k] = k < D ? (cfg->hi[k] - cfg->lo[k]) / cfg->cells[k] : 2.0;
+    if (k < D) s->detJ *= 0.5 * s->h[k];
+  }
+  for (int a = 0; a < D; ++a) {
+    s->detJf[a] = 1.0;
+    for (int k = 0; k < D; ++k)
+      if (k != a) s->detJf[a] *= 0.5 * s->h[k];
+  }
+  orc_gauss(s->Q, s->xg, s->wg);
+  orc_gll(s->P, s->xl, s->wl);
+
+  int P = s->P, Q = s->Q, Pd = s->Pd, Qd = s->Qd;
+  double lq[MAXN][MAXN], dlq[MAXN][MAXN]; /* [q][j] */
+  for (int q = 0; q < Q; ++q) orc_lagrange(P, s->xl, s->xg[q], lq[q], dlq[q]);
+
+  /* volume tables */
+  s->phiV = (double*)xmalloc(sizeof(double) * Qd * Pd);
+  s->dphiV = (double*)xmalloc(sizeof(double) * D * Qd * Pd);
+  s->wV = (double*)xmalloc(sizeof(double) * Qd);
+  for (int q = 0; q < Qd; ++q) {
+    int qi[3] = {q % Q, (q / Q) % Q, q / (Q * Q)};
+    double w = 1.0;
+    for (int k = 0; k < D; ++k) w *= s->wg[qi[k]];
+    s->wV[q] = w;
+    for (int i = 0; i < Pd; ++i) {
+      int ii[3] = {i % P, (i / P) % P, i / (P * P)};
+      double v = 1.0;
+      for (int k = 0; k < D; ++k) v *= lq[qi[k]][ii[k]];
+      s->phiV[q * Pd + i] = v;
+      for (int d = 0; d < D; ++d) {
+        double g = 1.0;
+        for (int k = 0; k < D; ++k) g *= (k == d) ? dlq[qi[k]][ii[k]] : lq[qi[k]][ii[k]];
+        s->dphiV[(d * Qd + q) * Pd + i] = g;
+      }
+    }
+  }
+
+  /* face tables: face Gauss points and face nodes in the remaining axes,
+   * lowest remaining axis fastest */
+  int Fq = s->Fq, Fn = s->Fn, nf = s->nf;
+  s->phiF = (double*)xmalloc(sizeof(double) * nf * Fq * Pd);
+  s->phiFN = (double*)xmalloc(sizeof(double) * nf * Fn * Pd);
+  s->wF = (double*)xmalloc(sizeof(double) * Fq);
+  s->lagF = (double*)xmalloc(sizeof(double) * Fq * Fn);
+  for (int f = 0; f < nf; ++f) {
+    int a = f / 2;
+    double xa = (f & 1) ? 1.0 : -1.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      int npt = pass == 0 ? Fq : Fn;
+      const double* pts = pass == 0 ? s->xg : s->xl;
+      int nper = pass == 0 ? Q : P;
+      for (int fq = 0; fq < npt; ++fq) {
+        double xi[3] = {0, 0, 0};
+        int r = fq;
+        for (int k = 0; k < D; ++k) {
+          if (k == a) {
+            xi[k] = xa;
+          } else {
+            xi[k] = pts[r % nper];
+            r /= nper;
+          }
+        }
+        double l[3][MAXN];
+        for (int k = 0; k < D; ++k) orc_lagrange(P, s->xl, xi[k], l[k], NULL);
+        for (int i = 0; i < Pd; ++i) {
+          int ii[3] = {i % P, (i / P) % P, i / (P * P)};
+          double v = 1.0;
+          for (int k = 0; k < D; ++k) v *= l[k][ii[k]];
+          if (pass == 0)
+            s->phiF[(f * Fq + fq) * Pd + i] = v;
+          else
+            s->phiFN[(f * Fn + fq) * Pd + i] = v;
+        }
+      }
+    }
+  }
+  for (int fq = 0; fq < Fq; ++fq) {
+    int qi[2] = {fq % Q, fq / Q};
+    double w = 1.0;
+    for (int k = 0; k < D - 1; ++k) w *= s->wg[qi[k]];
+    s->wF[fq] = w;
+    for (int j = 0; j < Fn; ++j) {
+      int jj[2] = {j % P, j / P};
+      double v = 1.0;
+      for (int k = 0; k < D - 1; ++k) v *= lq[qi[k]][jj[k]];
+      s->lagF[fq * Fn + j] = v;
+    }
+  }
+
+  /* reference mass matrix by quadrature, then its inverse */
+  double* M = (double*)xmalloc(sizeof(double) * Pd * Pd);
+  for (int i = 0; i < Pd; ++i)
+    for (int j = 0; j < Pd; ++j) {
+      double m = 0.0;
+      for (int q = 0; q < Qd; ++q) m += s->wV[q] * s->phiV[q * Pd + i] * s->phiV[q * Pd + j];
+      M[i * Pd + j] = m;
+    }
+  s->Minv = (double*)xmalloc(sizeof(double) * Pd * Pd);
+  if (dense_inverse(Pd, M, s->Minv)) {
+    free(M);
+    orc_destroy(s);
+    return NULL;
+  }
+  free(M);
+
+  size_t nd = (size_t)s->E * s->V * Pd;
+  s->u = (double*)xmalloc(sizeof(double) * nd);
+  s->ua = (double*)xmalloc(sizeof(double) * nd);
+  s->ub = (double*)xmalloc(sizeof(double) * nd);
+  s->kb = (double*)xmalloc(sizeof(double) * nd);
+  s->Fnum = (double*)xmalloc(sizeof(double) * (size_t)s->E * nf * Fq * s->V);
+
+  /* history depth: L + levels needed (reading of the warm-up and ring depth) */
+  int lev = cfg->levels < 1 ? 1 : cfg->levels;
+  switch (cfg->ghost) {
+    case 0: s->Qh = 1; s->R = 0; break;
+    case 1: s->Qh = 1; s->R = cfg->L + 1; break;
+    case 2: s->Qh = lev; s->R = cfg->L + lev; break;
+    default: s->Qh = lev > K_MLP ? lev : K_MLP; s->R = cfg->L + s->Qh; break;
+  }
+  if (s->R > 0) s->hist = (double*)xmalloc(sizeof(double) * nd * s->R);
+  s->nin = 3 * s->V + 1;
+  s->nh = NH_MLP;
+  s->nout = s->V;
+  return s;
+}
+
+void orc_destroy(void* vs) {
+  orc_solver* s = (orc_solver*)vs;
+  if (!s) return;
+  free(s->phiV); free(s->dphiV); free(s->wV);
+  free(s->phiF); free(s->wF); free(s->phiFN); free(s->lagF);
+  free(s->Minv);
+  free(s->u); free(s->ua); free(s->ub); free(s->kb); free(s->Fnum);
+  free(s->hist); free(s->mlp);
+  free(s);
+}
+
+int64_t orc_ndof(void* vs) {
+  orc_solver* s = (orc_solver*)vs;
+  return s->E * s->V * s->Pd;
+}
+
+int64_t orc_nface_sides(void* vs) {
+  orc_solver* s = (orc_solver*)vs;
+  int64_t c = 0;
+  for (int64_t e = 0; e < s->E; ++e)
+    for (int f = 0; f < s->nf; ++f)
+      if (orc_subdomain(s, e) != orc_subdomain(s, neighbour(s, e, f))) ++c;
+  return c;
+}
+
+void orc_set_state(void* vs, const double* u) {
+  orc_solver* s = (orc_solver*)vs;
+  memcpy(s->u, u, sizeof(double) * orc_ndof(s));
+}
+
+void orc_get_state(void* vs, double* u) {
+  orc_solver* s = (orc_solver*)vs;
+  memcpy(u, s->u, sizeof(double) * orc_ndof(s));
+}
+
+void orc_time(void* vs, int64_t* n, double* t) {
+  orc_solver* s = (orc_solver*)vs;
+  if (n) *n = s->n;
+  if (t) *t = s->t;
+}
+
+/* ------------------------------------------------------------------------ */
+/* physics (Sec. 2, eq. euler-parameters-dealii; Sec. 2.2, eq. lfflux)      */
+/* ------------------------------------------------------------------------ */
+
+static double pressure(int D, double g, const double* w) {
+  double m2 = 0.0;
+  for (int k = 0; k < D; ++k) m2 += w[1 + k] * w[1 + k];
+  return (g - 1.0) * (w[D + 1] - 0.5 * m2 / w[0]);
+}
+
+/* flux tensor column a: F(w) e_a */
+static void flux_dir(int D, double g, const double* w, int a, double* F) {
+  double p = pressure(D, g, w);
+  double ua = w[1 + a] / w[0];
+  F[0] = w[1 + a];
+  for (int k = 0; k < D; ++k) F[1 + k] = w[1 + k] * ua + (k == a ? p : 0.0);
+  F[D + 1] = (w[D + 1] + p) * ua;
+}
+
+/* numerical flux dotted with n = sigma e_a, seen from the side holding wm */
+static void num_flux(const orc_solver* s, const double* wm, const double* wp, int a, double sigma,
+                     double* out) {
+  int D = s->D, V = s->V;
+  double g = s->c.gamma;
+  double Fm[MAXV], Fp[MAXV];
+  flux_dir(D, g, wm, a, Fm);
+  flux_dir(D, g, wp, a, Fp);
+  double lam;
+  double pm = pressure(D, g, wm), pp = pressure(D, g, wp);
+  double cm2 = g * pm / wm[0], cp2 = g * pp / wp[0];
+  if (s->c.flux == 1) {
+    double am = fabs(wm[1 + a] / wm[0]) + sqrt(cm2);
+    double ap = fabs(wp[1 + a] / wp[0]) + sqrt(cp2);
+    lam = am > ap ? am : ap;
+  } else {
+    double um2 = 0.0, up2 = 0.0;
+    for (int k = 0; k < D; ++k) {
+      um2 += (wm[1 + k] / wm[0]) * (wm[1 + k] / wm[0]);
+      up2 += (wp[1 + k] / wp[0]) * (wp[1 + k] / wp[0]);
+    }
+    double sm = sqrt(um2 + cm2), sp = sqrt(up2 + cp2);
+    lam = 0.5 * (sm > sp ? sm : sp);
+  }
+  for (int v = 0; v < V; ++v) out[v] = 0.5 * (Fm[v] + Fp[v]) * sigma + 0.5 * lam * (wm[v] - wp[v]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* delays (reading: per step n, receiving subdomain, face direction)        */
+/* ------------------------------------------------------------------------ */
+
+static int raw_delay(const orc_solver* s, int64_t n, int64_t sub, int dir) {
+  int L = s->c.L;
+  switch (s->c.delay_kind) {
+    case 0: return L;
+    case 1: {
+      uint64_t idx = ((uint64_t)n * (uint64_t)s->nsub + (uint64_t)sub) * (uint64_t)s->nf + (uint64_t)dir;
+      return (int)(orc_splitmix64_draw(s->c.seed, idx) % (uint64_t)(L + 1));
+    }
+    default: {
+      if (s->c.ghost == 1) {
+        /* Alg. caa-std: communicate when n % L == 0, delay counts silent steps */
+        return L > 0 ? (int)(n % L) : 0;
+      }
+      /* Alg. caa-at: communicate for Qh steps, then L silent steps */
+      int64_t period = L + s->Qh;
+      int64_t r = n % period;
+      return r < s->Qh ? 0 : (int)(r - s->Qh + 1);
+    }
+  }
+}
+
+/* effective delay after the warm-up clamp: no level older than step 0 */
+int orc_delay(void* vs, int64_t n, int64_t sub, int dir) {
+  orc_solver* s = (orc_solver*)vs;
+  if (s->c.ghost == 0) return 0;
+  if (n < s->Qh - 1) return 0;
+  int k = raw_delay(s, n, sub, dir);
+  int64_t cap = n - s->Qh + 1;
+  return k < cap ? k : (int)cap;
+}
+
+/* ------------------------------------------------------------------------ */
+/* traces                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* w at face Gauss point fq of face f of element e, dense over all basis functions */
+static void trace_at(const orc_solver* s, const double* u, int64_t e, int f, int fq, double* w) {
+  const double* ph = s->phiF + ((size_t)f * s->Fq + fq) * s->Pd;
+  const double* ue = u + (size_t)e * s->V * s->Pd;
+  for (int v = 0; v < s->V; ++v) {
+    double a = 0.0;
+    for (int i = 0; i < s->Pd; ++i) a += ph[i] * ue[v * s->Pd + i];
+    w[v] = a;
+  }
+}
+
+static void trace_node(const orc_solver* s, const double* u, int64_t e, int f, int j, double* w) {
+  const double* ph = s->phiFN + ((size_t)f * s->Fn + j) * s->Pd;
+  const double* ue = u + (size_t)e * s->V * s->Pd;
+  for (int v = 0; v < s->V; ++v) {
+    double a = 0.0;
+    for (int i = 0; i < s->Pd; ++i) a += ph[i] * ue[v * s->Pd + i];
+    w[v] = a;
+  }
+}
+
+static const double* level_state(const orc_solver* s, int64_t lev) {
+  return s->hist + (size_t)(lev % s->R) * s->E * s->V * s->Pd;
+}
+
+/* ---- learned predictor: inference in the kernel's precision ------------ */
+
+/* round a binary32 value to bfloat16, nearest-even (finite inputs) */
+static float to_bf16(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  u &= 0xFFFF0000u;
+  float r;
+  memcpy(&r, &u, 4);
+  return r;
+}
+
+/* features of one face node from K levels T[j][v] (j = 0 newest) and tau:
+ * backward differences of orders 1..3, each normalised by its max over the
+ * variables, then tau/4. S3 (returned) scales the output back. */
+void orc_learned_features(void* vs, const double* T, double tau, double* x, double* S3) {
+  orc_solver* s = (orc_solver*)vs;
+  int V = s->V;
+  double d[3][MAXV], S[3] = {0, 0, 0};
+  for (int v = 0; v < V; ++v) {
+    double t0 = T[0 * V + v], t1 = T[1 * V + v], t2 = T[2 * V + v], t3 = T[3 * V + v];
+    d[0][v] = t0 - t1;
+    d[1][v] = (t0 - 2.0 * t1) + t2;
+    d[2][v] = ((t0 - 3.0 * t1) + 3.0 * t2) - t3;
+    for (int o = 0; o < 3; ++o)
+      if (fabs(d[o][v]) > S[o]) S[o] = fabs(d[o][v]);
+  }
+  for (int o = 0; o < 3; ++o) S[o] += 1e-300;
+  for (int o = 0; o < 3; ++o)
+    for (int v = 0; v < V; ++v) x[o * V + v] = d[o][v] / S[o];
+  x[3 * V] = 0.25 * tau;
+  *S3 = S[2];
+}
+
+static void mlp_bf16_forward(const orc_solver* s, const double* x, double* y) {
+  int nin = s->nin, nh = s->nh, nout = s->nout;
+  const float* W1 = s->mlp;
+  const float* b1 = W1 + nh * nin;
+  const float* W2 = b1 + nh;
+  const float* b2 = W2 + nout * nh;
+  double hb[128];
+  for (int h = 0; h < nh; ++h) {
+    double z = 0.0;
+    for (int i = 0; i < nin; ++i) z += (double)to_bf16(W1[h * nin + i]) * (double)to_bf16((float)x[i]);
+    float zf = (float)(z + (double)b1[h]);
+    double a = 0.5 * (double)zf * (1.0 + erf((double)zf / sqrt(2.0)));
+    hb[h] = (double)to_bf16((float)a);
+  }
+  for (int o = 0; o < nout; ++o) {
+    double z = 0.0;
+    for (int h = 0; h < nh; ++h) z += (double)to_bf16(W2[o * nh + h]) * hb[h];
+    y[o] = (double)(float)(z + (double)b2[o]);
+  }
+}
+
+/* ghost of face-side (e, f) at face Gauss points: g[fq][v] */
+static void ghost_face(orc_solver* s, const double* uin, int64_t e, int f, int stage, double* g) {
+  int V = s->V, Fq = s->Fq;
+  int64_t nb = neighbour(s, e, f);
+  int fn = f ^ 1;
+  int k = orc_delay(s, s->n, orc_subdomain(s, e), f);
+  if (k == 0) {
+    for (int fq = 0; fq < Fq; ++fq) trace_at(s, uin, nb, fn, fq, g + fq * V);
+    return;
+  }
+  if (s->c.ghost == 1) {
+    const double* old = level_state(s, s->n - k);
+    for (int fq = 0; fq < Fq; ++fq) trace_at(s, old, nb, fn, fq, g + fq * V);
+    return;
+  }
+  int lev = s->c.levels;
+  double tau = k + SSP_C[stage];
+  double c[MAXN];
+  orc_at_weights(lev, tau, c);
+  if (s->c.ghost == 2) {
+    double w[MAXV];
+    for (int fq = 0; fq < Fq; ++fq) {
+      for (int v = 0; v < V; ++v) g[fq * V + v] = 0.0;
+      for (int j = 0; j < lev; ++j) {
+        trace_at(s, level_state(s, s->n - k - j), nb, fn, fq, w);
+        for (int v = 0; v < V; ++v) g[fq * V + v] += c[j] * w[v];
+      }
+    }
+    return;
+  }
+  /* LEARNED: AT at the face nodes plus the predicted correction, accepted
+   * for the whole face only if every |correction| <= tol (reading) */
+  int Fn = s->Fn;
+  double gn[64 * MAXV], dn[64 * MAXV];
+  double T[8 * MAXV];
+  double maxd = 0.0;
+  for (int j = 0; j < Fn; ++j) {
+    for (int l = 0; l < K_MLP; ++l) trace_node(s, level_state(s, s->n - k - l), nb, fn, j, T + l * V);
+    for (int v = 0; v < V; ++v) {
+      double a = 0.0;
+      for (int l = 0; l < lev; ++l) a += c[l] * T[l * V + v];
+      gn[j * V + v] = a;
+    }
+    double x[32], y[MAXV], S3;
+    orc_learned_features(s, T, tau, x, &S3);
+    if (s->has_mlp) {
+      mlp_bf16_forward(s, x, y);
+    } else {
+      for (int v = 0; v < V; ++v) y[v] = 0.0;
+    }
+    for (int v = 0; v < V; ++v) {
+      dn[j * V + v] = S3 * y[v];
+      if (fabs(dn[j * V + v]) > maxd || dn[j * V + v] != dn[j * V + v]) maxd = fabs(dn[j * V + v]);
+    }
+  }
+  int accept = s->has_mlp && maxd <= s->c.learned_tol;
+#pragma omp atomic
+  s->acc += accept;
+#pragma omp atomic
+  s->rej += !accept;
+  if (accept)
+    for (int j = 0; j < Fn; ++j)
+      for (int v = 0; v < V; ++v) gn[j * V + v] += dn[j * V + v];
+  for (int fq = 0; fq < Fq; ++fq)
+    for (int v = 0; v < V; ++v) {
+      double a = 0.0;
+      for (int j = 0; j < Fn; ++j) a += s->lagF[fq * Fn + j] * gn[j * V + v];
+      g[fq * V + v] = a;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* right-hand side (Sec. 2.1, eq. weakform-dealii, weakform-compact-dealii) */
+/* ------------------------------------------------------------------------ */
+
+static int is_pe_face(orc_solver* s, int64_t e, int64_t nb) {
+  return orc_subdomain(s, e) != orc_subdomain(s, nb);
+}
+
+/* numerical flux n.F^ at every face Gauss point of every element face.
+ * A face between two elements of one subdomain is evaluated once and given
+ * to both sides with opposite sign. A PE-boundary face gives each side the
+ * flux with its own (possibly old or extrapolated) picture of the other. */
+static void face_fluxes(orc_solver* s, const double* uin, int stage, int use_ghosts) {
+  int D = s->D, V = s->V, Fq = s->Fq, nf = s->nf;
+  int64_t E = s->E;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < E; ++e) {
+    double wm[MAXV], wp[MAXV], G[MAXV];
+    double gA[64 * MAXV], gB[64 * MAXV];
+    for (int a = 0; a < D; ++a) {
+      int fR = 2 * a + 1, fL = 2 * a;
+      int64_t e2 = neighbour(s, e, fR);
+      double* FR = s->Fnum + ((size_t)e * nf + fR) * Fq * V;
+      double* FL = s->Fnum + ((size_t)e2 * nf + fL) * Fq * V;
+      int pe = use_ghosts && s->c.ghost != 0 && is_pe_face(s, e, e2);
+      if (pe) {
+        ghost_face(s, uin, e, fR, stage, gA);  /* e's picture of e2 */
+        ghost_face(s, uin, e2, fL, stage, gB); /* e2's picture of e */
+      }
+      for (int fq = 0; fq < Fq; ++fq) {
+        trace_at(s, uin, e, fR, fq, wm);
+        trace_at(s, uin, e2, fL, fq, wp);
+        if (!pe) {
+          num_flux(s, wm, wp, a, 1.0, G);
+          for (int v = 0; v < V; ++v) {
+            FR[fq * V + v] = G[v];
+            FL[fq * V + v] = -G[v];
+          }
+        } else {
+          num_flux(s, wm, gA + fq * V, a, 1.0, FR + fq * V);
+          num_flux(s, wp, gB + fq * V, a, -1.0, FL + fq * V);
+        }
+      }
+    }
+  }
+}
+
+/* dudt = M_e^{-1} [ (grad phi, F(w)) - <phi, n.F^> ] for element e */
+static void element_rhs(const orc_solver* s, const double* uin, int64_t e, double* dudt) {
+  int D = s->D, V = s->V, Pd = s->Pd, Qd = s->Qd, Fq = s->Fq, nf = s->nf;
+  double g = s->c.gamma;
+  const double* ue = uin + (size_t)e * V * Pd;
+  double R[MAXV * 512];
+  for (int i = 0; i < V * Pd; ++i) R[i] = 0.0;
+  for (int q = 0; q < Qd; ++q) {
+    double w[MAXV];
+    for (int v = 0; v < V; ++v) {
+      double a = 0.0;
+      for (int i = 0; i < Pd; ++i) a += s->phiV[q * Pd + i] * ue[v * Pd + i];
+      w[v] = a;
+    }
+    double F[3][MAXV];
+    for (int a = 0; a < D; ++a) flux_dir(D, g, w, a, F[a]);
+    double sc = s->wV[q] * s->detJ;
+    for (int i = 0; i < Pd; ++i)
+      for (int a = 0; a < D; ++a) {
+        double gi = sc * (2.0 / s->h[a]) * s->dphiV[(a * Qd + q) * Pd + i];
+        for (int v = 0; v < V; ++v) R[v * Pd + i] += gi * F[a][v];
+      }
+  }
+  for (int f = 0; f < nf; ++f) {
+    const double* Fn = s->Fnum + ((size_t)e * nf + f) * Fq * V;
+    double jf = s->detJf[f / 2];
+    for (int fq = 0; fq < Fq; ++fq) {
+      double sc = s->wF[fq] * jf;
+      const double* ph = s->phiF + ((size_t)f * Fq + fq) * Pd;
+      for (int i = 0; i < Pd; ++i)
+        for (int v = 0; v < V; ++v) R[v * Pd + i] -= sc * ph[i] * Fn[fq * V + v];
+    }
+  }
+  for (int v = 0; v < V; ++v)
+    for (int i = 0; i < Pd; ++i) {
+      double a = 0.0;
+      for (int j = 0; j < Pd; ++j) a += s->Minv[i * Pd + j] * R[v * Pd + j];
+      dudt[v * Pd + i] = a / s->detJ;
+    }
+}
+
+static void full_rhs(orc_solver* s, const double* uin, int stage, int use_ghosts, double* dudt) {
+  face_fluxes(s, uin, stage, use_ghosts);
+  size_t es = (size_t)s->V * s->Pd;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < s->E; ++e) element_rhs(s, uin, e, dudt + e * es);
+}
+
+void orc_rhs(void* vs, const double* u, double* dudt) {
+  full_rhs((orc_solver*)vs, u, 0, 0, dudt);
+}
+
+/* one SSP-RK3 stage (sync, all faces live) for a list of elements */
+void orc_stage_elements(void* vs, int stage, double dt, const double* u_in, const double* u_n, int64_t ne,
+                        const int64_t* elems, double* out) {
+  orc_solver* s = (orc_solver*)vs;
+  int D = s->D, V = s->V, Pd = s->Pd, Fq = s->Fq, nf = s->nf;
+  size_t es = (size_t)V * Pd;
+#pragma omp parallel for schedule(static)
+  for (int64_t idx = 0; idx < ne; ++idx) {
+    int64_t e = elems[idx];
+    double wm[MAXV], wp[MAXV], G[MAXV], kk[MAXV * 512];
+    for (int a = 0; a < D; ++a)
+      for (int side = 0; side < 2; ++side) {
+        int f = 2 * a + side;
+        int64_t nb = neighbour(s, e, f);
+        double* F = s->Fnum + ((size_t)e * nf + f) * Fq * V;
+        for (int fq = 0; fq < Fq; ++fq) {
+          /* canonical orientation: left element first, then sign */
+          if (side == 1) {
+            trace_at(s, u_in, e, f, fq, wm);
+            trace_at(s, u_in, nb, f ^ 1, fq, wp);
+            num_flux(s, wm, wp, a, 1.0, G);
+            for (int v = 0; v < V; ++v) F[fq * V + v] = G[v];
+          } else {
+            trace_at(s, u_in, nb, f ^ 1, fq, wm);
+            trace_at(s, u_in, e, f, fq, wp);
+            num_flux(s, wm, wp, a, 1.0, G);
+            for (int v = 0; v < V; ++v) F[fq * V + v] = -G[v];
+          }
+        }
+      }
+    element_rhs(s, u_in, e, kk);
+    for (size_t i = 0; i < es; ++i) {
+      double un = u_n[e * es + i];
+      out[idx * es + i] = SSP_A[stage] * un + SSP_B[stage] * (u_in[e * es + i] + dt * kk[i]);
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* time stepping                                                            */
+/* ------------------------------------------------------------------------ */
+
+static int check_state(const orc_solver* s) {
+  int V = s->V, Pd = s->Pd, bad = 0;
+  for (int64_t e = 0; e < s->E && !bad; ++e)
+    for (int i = 0; i < Pd; ++i) {
+      double w[MAXV];
+      for (int v = 0; v < V; ++v) {
+        w[v] = s->u[(e * V + v) * Pd + i];
+        if (!isfinite(w[v])) return -4;
+      }
+      if (w[0] <= 0.0 || pressure(s->D, s->c.gamma, w) <= 0.0) bad = 1;
+    }
+  return bad ? -5 : 0;
+}
+
+int orc_step(void* vs, int64_t nsteps, double dt) {
+  orc_solver* s = (orc_solver*)vs;
+  size_t nd = (size_t)orc_ndof(s);
+  for (int64_t it = 0; it < nsteps; ++it) {
+    if (s->R > 0) memcpy(s->hist + (size_t)(s->n % s->R) * nd, s->u, sizeof(double) * nd);
+    double* in[3] = {s->u, s->ua, s->ub};
+    double* outp[3] = {s->ua, s->ub, s->u};
+    for (int m = 0; m < 3; ++m) {
+      full_rhs(s, in[m], m, 1, s->kb);
+      double a = SSP_A[m], b = SSP_B[m];
+      const double* ui = in[m];
+      double* uo = outp[m];
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < (int64_t)nd; ++i) uo[i] = a * s->u[i] + b * (ui[i] + dt * s->kb[i]);
+    }
+    s->n += 1;
+    s->t += dt;
+  }
+  return check_state(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* exact solutions, projection, norms                                       */
+/* ------------------------------------------------------------------------ */
+
+static void exact_state(const orc_solver* s, int problem, const double* prm, const double* x, double t,
+                        double* w) {
+  int D = s->D;
+  double g = s->c.gamma;
+  if (problem == ORC_VORTEX) {
+    double x0 = prm ? prm[0] : 5.0, y0 = prm ? prm[1] : 5.0, beta = prm ? prm[2] : 5.0;
+    double mx = prm ? prm[3] : 1.0, my = prm ? prm[4] : 1.0;
+    double Lx = s->c.hi[0] - s->c.lo[0], Ly = s->c.hi[1] - s->c.lo[1];
+    double dx = x[0] - x0 - mx * t, dy = x[1] - y0 - my * t;
+    dx -= Lx * floor((dx + 0.5 * Lx) / Lx);
+    dy -= Ly * floor((dy + 0.5 * Ly) / Ly);
+    double r2 = dx * dx + dy * dy;
+    double ex = exp(1.0 - r2);
+    double u = mx - beta * ex * dy / (2.0 * ORC_PI);
+    double v = my + beta * ex * dx / (2.0 * ORC_PI);
+    double rho = pow(1.0 - (g - 1.0) * beta * beta * ex * ex / (16.0 * g * ORC_PI * ORC_PI), 1.0 / (g - 1.0));
+    double p = pow(rho, g);
+    w[0] = rho;
+    w[1] = rho * u;
+    w[2] = rho * v;
+    for (int k = 2; k < D; ++k) w[1 + k] = 0.0;
+    w[D + 1] = p / (g - 1.0) + 0.5 * rho * (u * u + v * v);
+  } else if (problem == ORC_DENSITY_WAVE) {
+    double A = prm ? prm[0] : 0.2, p = prm ? prm[4] : 1.0;
+    double u[3] = {prm ? prm[1] : 1.0, prm ? prm[2] : 1.0, prm ? prm[3] : 1.0};
+    double arg = 0.0, u2 = 0.0;
+    for (int k = 0; k < D; ++k) {
+      arg += x[k] - u[k] * t;
+      u2 += u[k] * u[k];
+    }
+    double rho = 1.0 + A * sin(2.0 * ORC_PI * arg);
+    w[0] = rho;
+    for (int k = 0; k < D; ++k) w[1 + k] = rho * u[k];
+    w[D + 1] = p / (g - 1.0) + 0.5 * rho * u2;
+  } else {
+    double rho = prm ? prm[0] : 1.0, p = prm ? prm[4] : 1.0;
+    double u[3] = {prm ? prm[1] : 0.3, prm ? prm[2] : -0.2, prm ? prm[3] : 0.1};
+    double u2 = 0.0;
+    w[0] = rho;
+    for (int k = 0; k < D; ++k) {
+      w[1 + k] = rho * u[k];
+      u2 += u[k] * u[k];
+    }
+    w[D + 1] = p / (g - 1.0) + 0.5 * rho * u2;
+  }
+}
+
+static void qp_position(const orc_solver* s, int64_t e, int q, double* x) {
+  int64_t ijk[3];
+  elem_ijk(s, e, ijk);
+  int Q = s->Q;
+  int qi[3] = {q % Q, (q / Q) % Q, q / (Q * Q)};
+  for (int k = 0; k < s->D; ++k) x[k] = s->c.lo[k] + s->h[k] * (ijk[k] + 0.5 * (s->xg[qi[k]] + 1.0));
+}
+
+/* L2 projection: M_e u_e = (phi, w_exact) with the Gauss rule */
+void orc_init_problem(void* vs, int problem, const double* params) {
+  orc_solver* s = (orc_solver*)vs;
+  int V = s->V, Pd = s->Pd, Qd = s->Qd;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < s->E; ++e) {
+    double b[MAXV * 512];
+    for (int i = 0; i < V * Pd; ++i) b[i] = 0.0;
+    for (int q = 0; q < Qd; ++q) {
+      double x[3], w[MAXV];
+      qp_position(s, e, q, x);
+      exact_state(s, problem, params, x, 0.0, w);
+      for (int i = 0; i < Pd; ++i)
+        for (int v = 0; v < V; ++v) b[v * Pd + i] += s->wV[q] * s->phiV[q * Pd + i] * w[v];
+    }
+    for (int v = 0; v < V; ++v)
+      for (int i = 0; i < Pd; ++i) {
+        double a = 0.0;
+        for (int j = 0; j < Pd; ++j) a += s->Minv[i * Pd + j] * b[v * Pd + j];
+        s->u[(e * V + v) * Pd + i] = a;
+      }
+  }
+  s->n = 0;
+  s->t = 0.0;
+  s->acc = s->rej = 0;
+}
+
+/* quadrature L2 norms of (w_h - w_exact): density, momentum (vector), energy */
+void orc_error_norms(void* vs, int problem, const double* params, double t, double out[3]) {
+  orc_solver* s = (orc_solver*)vs;
+  int D = s->D, V = s->V, Pd = s->Pd, Qd = s->Qd;
+  double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+#pragma omp parallel for reduction(+ : e0, e1, e2) schedule(static)
+  for (int64_t e = 0; e < s->E; ++e) {
+    const double* ue = s->u + (size_t)e * V * Pd;
+    for (int q = 0; q < Qd; ++q) {
+      double x[3], we[MAXV], wh[MAXV];
+      qp_position(s, e, q, x);
+      exact_state(s, problem, params, x, t, we);
+      for (int v = 0; v < V; ++v) {
+        double a = 0.0;
+        for (int i = 0; i < Pd; ++i) a += s->phiV[q * Pd + i] * ue[v * Pd + i];
+        wh[v] = a - we[v];
+      }
+      double sc = s->wV[q] * s->detJ;
+      e0 += sc * wh[0] * wh[0];
+      for (int k = 0; k < D; ++k) e1 += sc * wh[1 + k] * wh[1 + k];
+      e2 += sc * wh[D + 1] * wh[D + 1];
+    }
+  }
+  out[0] = sqrt(e0);
+  out[1] = sqrt(e1);
+  out[2] = sqrt(e2);
+}
+
+/* integral of every conserved variable over the box, by quadrature */
+void orc_integrals(void* vs, double* out) {
+  orc_solver* s = (orc_solver*)vs;
+  int V = s->V, Pd = s->Pd, Qd = s->Qd;
+  for (int v = 0; v < V; ++v) {
+    double acc = 0.0;
+#pragma omp parallel for reduction(+ : acc) schedule(static)
+    for (int64_t e = 0; e < s->E; ++e) {
+      const double* ue = s->u + ((size_t)e * V + v) * Pd;
+      for (int q = 0; q < Qd; ++q) {
+        double a = 0.0;
+        for (int i = 0; i < Pd; ++i) a += s->phiV[q * Pd + i] * ue[i];
+        acc += s->wV[q] * s->detJ * a;
+      }
+    }
+    out[v] = acc;
+  }
+}
+
+/* reading of the CFL number: dt = cfl * min h / (p^1.5 * max(|u| + c)) */
+double orc_stable_dt(void* vs, double cfl) {
+  orc_solver* s = (orc_solver*)vs;
+  int D = s->D, V = s->V, Pd = s->Pd;
+  double smax = 0.0;
+  for (int64_t e = 0; e < s->E; ++e)
+    for (int i = 0; i < Pd; ++i) {
+      double w[MAXV];
+      for (int v = 0; v < V; ++v) w[v] = s->u[(e * V + v) * Pd + i];
+      double u2 = 0.0;
+      for (int k = 0; k < D; ++k) u2 += (w[1 + k] / w[0]) * (w[1 + k] / w[0]);
+      double c = sqrt(s->c.gamma * pressure(D, s->c.gamma, w) / w[0]);
+      double sp = sqrt(u2) + c;
+      if (sp > smax) smax = sp;
+    }
+  double hmin = s->h[0];
+  for (int k = 1; k < D; ++k)
+    if (s->h[k] < hmin) hmin = s->h[k];
+  return cfl * hmin / (pow((double)s->c.p, 1.5) * smax);
+}
+
+/* ------------------------------------------------------------------------ */
+/* MLP reference: W1[nh][nin], b1[nh], W2[nout][nh], b2[nout]; exact GELU  */
+/* ------------------------------------------------------------------------ */
+
+int orc_mlp_nparams(int nin, int nh, int nout) { return nh * nin + nh + nout * nh + nout; }
+
+static double gelu(double z) { return 0.5 * z * (1.0 + erf(z / sqrt(2.0))); }
+static double gelu_d(double z) {
+  return 0.5 * (1.0 + erf(z / sqrt(2.0))) + z * exp(-0.5 * z * z) / sqrt(2.0 * ORC_PI);
+}
+
+void orc_mlp_forward(const double* w, int nin, int nh, int nout, int64_t n, const double* x, double* y) {
+  const double *W1 = w, *b1 = w + nh * nin, *W2 = b1 + nh, *b2 = W2 + nout * nh;
+  for (int64_t s = 0; s < n; ++s) {
+    double hbuf[1024];
+    for (int h = 0; h < nh; ++h) {
+      double z = b1[h];
+      for (int i = 0; i < nin; ++i) z += W1[h * nin + i] * x[s * nin + i];
+      hbuf[h] = gelu(z);
+    }
+    for (int o = 0; o < nout; ++o) {
+      double z = b2[o];
+      for (int h = 0; h < nh; ++h) z += W2[o * nh + h] * hbuf[h];
+      y[s * nout + o] = z;
+    }
+  }
+}
+
+/* mean squared error over n samples and nout outputs, and its gradient */
+double orc_mlp_loss_grad(const double* w, int nin, int nh, int nout, int64_t n, const double* x,
+                         const double* y, double* grad) {
+  const double *W1 = w, *b1 = w + nh * nin, *W2 = b1 + nh, *b2 = W2 + nout * nh;
+  int np = orc_mlp_nparams(nin, nh, nout);
+  double *gW1 = grad, *gb1 = grad + nh * nin, *gW2 = gb1 + nh, *gb2 = gW2 + nout * nh;
+  for (int i = 0; i < np; ++i) grad[i] = 0.0;
+  double loss = 0.0, scale = 1.0 / ((double)n * nout);
+  for (int64_t s = 0; s < n; ++s) {
+    double z[1024], a[1024], dy[64], dh[1024];
+    for (int h = 0; h < nh; ++h) {
+      double t = b1[h];
+      for (int i = 0; i < nin; ++i) t += W1[h * nin + i] * x[s * nin + i];
+      z[h] = t;
+      a[h] = gelu(t);
+    }
+    for (int o = 0; o < nout; ++o) {
+      double t = b2[o];
+      for (int h = 0; h < nh; ++h) t += W2[o * nh + h] * a[h];
+      double r = t - y[s * nout + o];
+      loss += r * r * scale;
+      dy[o] = 2.0 * r * scale;
+    }
+    for (int h = 0; h < nh; ++h) dh[h] = 0.0;
+    for (int o = 0; o < nout; ++o) {
+      gb2[o] += dy[o];
+      for (int h = 0; h < nh; ++h) {
+        gW2[o * nh + h] += dy[o] * a[h];
+        dh[h] += dy[o] * W2[o * nh + h];
+      }
+    }
+    for (int h = 0; h < nh; ++h) {
+      double dz = dh[h] * gelu_d(z[h]);
+      gb1[h] += dz;
+      for (int i = 0; i < nin; ++i) gW1[h * nin + i] += dz * x[s * nin + i];
+    }
+  }
+  return loss;
+}
+
+/* Adam (Kingma & Ba 2015) with bias correction; t counts from 1 */
+void orc_adam(double* w, double* m, double* v, const double* g, int np, double lr, double b1, double b2,
+              double eps, int64_t t) {
+  double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+  for (int i = 0; i < np; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    w[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+  }
+}
+
+void orc_set_predictor(void* vs, const float* w) {
+  orc_solver* s = (orc_solver*)vs;
+  int np = orc_mlp_nparams(s->nin, s->nh, s->nout);
+  if (!s->mlp) s->mlp = (float*)xmalloc(sizeof(float) * np);
+  if (w) {
+    memcpy(s->mlp, w, sizeof(float) * np);
+    s->has_mlp = 1;
+  } else {
+    s->has_mlp = 0;
+  }
+}
+
+void orc_learned_stats(void* vs, int64_t* accepted, int64_t* rejected) {
+  orc_solver* s = (orc_solver*)vs;
+  *accepted = s->acc;
+  *rejected = s->rej;
+}

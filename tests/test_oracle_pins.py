@@ -1,0 +1,369 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by
+mathematics (closed forms, exact rules, printed tables, published generator
+streams, convergence orders, invariants). CPU only.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from tests import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    out = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for ln in f:
+            ln = ln.strip()
+            if ln and not ln.startswith("#"):
+                out.append(ln.split())
+    return out
+
+
+# ---------------------------------------------------------------- quadrature
+
+@pytest.mark.parametrize("n,nodes,weights", [
+    (2, [-1, 1], [1, 1]),
+    (3, [-1, 0, 1], [1 / 3, 4 / 3, 1 / 3]),
+    (4, [-1, -1 / math.sqrt(5), 1 / math.sqrt(5), 1], [1 / 6, 5 / 6, 5 / 6, 1 / 6]),
+    (5, [-1, -math.sqrt(3 / 7), 0, math.sqrt(3 / 7), 1], [1 / 10, 49 / 90, 32 / 45, 49 / 90, 1 / 10]),
+])
+def test_gll_closed_forms(oracle_mod, n, nodes, weights):
+    x, w = oracle_mod.gll(n)
+    np.testing.assert_allclose(x, nodes, atol=1e-15)
+    np.testing.assert_allclose(w, weights, atol=1e-15)
+
+
+@pytest.mark.parametrize("n", range(1, 8))
+def test_gauss_exact_to_degree_2n_minus_1(oracle_mod, n):
+    x, w = oracle_mod.gauss(n)
+    assert np.all(np.diff(x) > 0)
+    for k in range(2 * n):
+        exact = 2.0 / (k + 1) if k % 2 == 0 else 0.0
+        assert abs(np.sum(w * x ** k) - exact) < 1e-14
+    # degree 2n is no longer integrated exactly
+    assert abs(np.sum(w * x ** (2 * n)) - 2.0 / (2 * n + 1)) > 1e-6
+
+
+def test_gauss_two_point_closed_form(oracle_mod):
+    x, w = oracle_mod.gauss(2)
+    np.testing.assert_allclose(x, [-1 / math.sqrt(3), 1 / math.sqrt(3)], atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_lagrange_cardinal_unity_derivative(oracle_mod, n):
+    nodes, _ = oracle_mod.gll(n)
+    for i, xi in enumerate(nodes):
+        phi, _ = oracle_mod.lagrange(nodes, xi)
+        np.testing.assert_array_equal(phi, np.eye(n)[i])
+    for x in np.linspace(-1, 1, 7):
+        phi, dphi = oracle_mod.lagrange(nodes, x)
+        assert abs(phi.sum() - 1) < 1e-14
+        assert abs(dphi.sum()) < 1e-12
+        h = 1e-6
+        pp, _ = oracle_mod.lagrange(nodes, x + h)
+        pm, _ = oracle_mod.lagrange(nodes, x - h)
+        np.testing.assert_allclose(dphi, (pp - pm) / (2 * h), atol=1e-7)
+
+
+# ------------------------------------------------------------------ AT weights
+
+def test_at_weights_match_paper_table(oracle_mod):
+    for row in _rows("at_flux_coeffs.txt"):
+        order, k = int(row[0]), int(row[1])
+        expect = [float(v) for v in row[2:]]
+        got = oracle_mod.at_weights(order, k)
+        np.testing.assert_allclose(got, expect, atol=1e-12)
+
+
+def test_at_weights_fractional_stage_delay(oracle_mod):
+    # naive RK coupling: tau = k + c_m; tau = 1/2 gives the quadratic
+    # extrapolation weights (15/8, -5/4, 3/8)
+    np.testing.assert_allclose(oracle_mod.at_weights(3, 0.5), [1.875, -1.25, 0.375], atol=1e-14)
+
+
+@pytest.mark.parametrize("nlev", [1, 2, 3, 4])
+@pytest.mark.parametrize("tau", [0.0, 0.5, 1.0, 2.5, 4.0])
+def test_at_weights_reproduce_polynomials(oracle_mod, nlev, tau):
+    c = oracle_mod.at_weights(nlev, tau)
+    t = -(tau + np.arange(nlev))
+    for deg in range(nlev):
+        for coef in (1.0, -0.7):
+            f = lambda s: coef * s ** deg + 0.3
+            assert abs(np.dot(c, f(t)) - f(0.0)) < 1e-10 * (1 + abs(tau)) ** deg
+
+
+def test_at_reduces_to_standard_at_zero_delay(oracle_mod):
+    np.testing.assert_allclose(oracle_mod.at_weights(3, 0.0), [1, 0, 0], atol=1e-15)
+
+
+# ------------------------------------------------------------- delay draws
+
+def test_splitmix64_published_streams(oracle_mod):
+    for row in _rows("splitmix64_reference.txt"):
+        seed, idx, val = int(row[0]), int(row[1]), int(row[2])
+        assert oracle_mod.splitmix64_draw(seed, idx) == val
+
+
+def test_uniform_delays_in_range_and_spread(oracle_mod):
+    O = oracle_mod
+    o = O.Oracle(dim=2, p=1, cells=(8, 8, 1), parts=(4, 4, 1), hi=(1, 1, 1), ghost=O.AT,
+                 delay_kind=O.UNIFORM, L=3, levels=3, seed=7)
+    counts = np.zeros(4)
+    for n in range(2, 400):
+        for s in range(16):
+            for d in range(4):
+                k = o.delay(n, s, d)
+                assert 0 <= k <= min(3, n - 2)
+                if n >= 5:
+                    counts[k] += 1
+    expected = counts.sum() / 4
+    chi2 = ((counts - expected) ** 2 / expected).sum()
+    assert chi2 < 16.3  # p = 0.001 for 3 degrees of freedom
+
+
+def test_warmup_clamp(oracle_mod):
+    O = oracle_mod
+    o = O.Oracle(dim=2, p=1, cells=(4, 4, 1), parts=(2, 2, 1), hi=(1, 1, 1), ghost=O.AT,
+                 delay_kind=O.FIXED, L=3, levels=3)
+    assert [o.delay(n, 0, 0) for n in range(8)] == [0, 0, 0, 1, 2, 3, 3, 3]
+    o = O.Oracle(dim=2, p=1, cells=(4, 4, 1), parts=(2, 2, 1), hi=(1, 1, 1), ghost=O.STALE,
+                 delay_kind=O.FIXED, L=2, levels=1)
+    assert [o.delay(n, 0, 0) for n in range(5)] == [0, 1, 2, 2, 2]
+
+
+def _iterative_schedule(nsteps, comm):
+    """The flag/counter loop of Alg. caa-std / caa-at: k resets on
+    communicating steps and grows by one on silent steps."""
+    ks, k = [], 0
+    for n in range(nsteps):
+        if comm(n):
+            k = 0
+        else:
+            k += 1
+        ks.append(k)
+    return ks
+
+
+@pytest.mark.parametrize("L", [2, 4, 10])
+def test_caa_std_schedule_is_algorithm(oracle_mod, L):
+    O = oracle_mod
+    o = O.Oracle(dim=2, p=1, cells=(4, 4, 1), parts=(2, 2, 1), hi=(1, 1, 1), ghost=O.STALE,
+                 delay_kind=O.CAA, L=L, levels=1)
+    ref = _iterative_schedule(60, lambda n: n % L == 0)
+    assert [o.delay(n, 1, 2) for n in range(60)] == ref
+
+
+@pytest.mark.parametrize("L,Np", [(4, 2), (10, 2), (3, 1)])
+def test_caa_at_schedule_is_algorithm(oracle_mod, L, Np):
+    O = oracle_mod
+    o = O.Oracle(dim=2, p=1, cells=(4, 4, 1), parts=(2, 2, 1), hi=(1, 1, 1), ghost=O.AT,
+                 delay_kind=O.CAA, L=L, levels=Np + 1)
+    ref = _iterative_schedule(80, lambda n: n % (L + Np + 1) < Np + 1)
+    assert [o.delay(n, 3, 1) for n in range(80)] == ref
+
+
+# ------------------------------------------------------------ problem sizes
+
+def test_dof_convention_matches_paper_table(oracle_mod):
+    O = oracle_mod
+    for row in _rows("problem_sizes.txt"):
+        dim, G, NE, dofs = int(row[0]), int(row[1]), float(row[2]), float(row[3])
+        assert NE * 3 ** dim * (dim + 2) == pytest.approx(dofs, rel=0.03)
+        if dim == 2 and G <= 5:
+            n = 2 ** (G + 2)
+            o = O.Oracle(dim=2, p=2, cells=(n, n, 1), hi=(10, 10, 1))
+            assert o.ndof == int(dofs) and o.E == int(NE)
+    o = O.Oracle(dim=3, p=2, cells=(20, 16, 10), hi=(1, 1, 1))  # 3200 elements
+    assert o.ndof == 432000
+
+
+# ---------------------------------------------------------- whole operator
+
+MODES = [("sync", 0, 0, 0), ("stale_fixed", 1, 0, 2), ("at_uniform", 2, 1, 3), ("at_caa", 2, 2, 2),
+         ("learned_nonet", 3, 1, 2)]
+
+
+@pytest.mark.parametrize("name,ghost,kind,L", MODES)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_free_stream_preserved_every_mode(oracle_mod, name, ghost, kind, L, dim):
+    O = oracle_mod
+    cells = (6, 6, 6 if dim == 3 else 1)
+    parts = (3, 2, 2 if dim == 3 else 1)
+    o = O.Oracle(dim=dim, p=2, cells=cells, parts=parts, hi=(1, 2, 1), ghost=ghost, delay_kind=kind,
+                 L=L, levels=3, seed=3)
+    o.init_problem(O.CONSTANT)
+    u0 = o.state()
+    assert np.abs(o.rhs(u0)).max() < 1e-12
+    assert o.step(8, 1e-3) == 0
+    np.testing.assert_allclose(o.state(), u0, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("parts", [(1, 1, 1), (4, 2, 1)])
+def test_sync_conservation_to_roundoff(oracle_mod, parts):
+    O = oracle_mod
+    o = O.Oracle(dim=2, p=3, cells=(8, 8, 1), parts=parts, hi=(10, 10, 1))
+    o.init_problem(O.VORTEX)
+    o.set_state(o.state() + inputs.perturbation(o.ndof, 11, 1e-2))
+    I0 = o.integrals()
+    dt = 0.5 * o.stable_dt(0.1)
+    assert o.step(20, dt) == 0
+    I1 = o.integrals()
+    assert np.all(np.abs(I1 - I0) <= 1e-13 * np.abs(I0).max())
+
+
+def _sweep(O, dim, p, ns, ghost=0, kind=0, L=0, cfl=0.1, tend=0.2, problem=None, r=1.0,
+           parts=(1, 1, 1), hi=(1, 1, 1)):
+    problem = O.DENSITY_WAVE if problem is None else problem
+    errs = []
+    for n in ns:
+        cells = (n, n, n if dim == 3 else 1)
+        o = O.Oracle(dim=dim, p=p, cells=cells, parts=parts, hi=hi, ghost=ghost, delay_kind=kind, L=L,
+                     levels=3)
+        o.init_problem(problem)
+        h = hi[0] / n
+        dt = cfl * h ** r / (max(p, 1) ** 1.5 * 2.75)
+        nst = int(math.ceil(tend / dt))
+        assert o.step(nst, tend / nst) == 0
+        errs.append(o.error_norms(problem, tend))
+    errs = np.array(errs)
+    return errs, np.log2(errs[:-1] / errs[1:])
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_sync_order_p_plus_1_density_wave_2d(oracle_mod, p):
+    errs, slopes = _sweep(oracle_mod, 2, p, (8, 16, 32))
+    assert np.all(slopes[-1] > p + 1 - 0.15)
+
+
+def test_sync_order_3d(oracle_mod):
+    errs, slopes = _sweep(oracle_mod, 3, 1, (4, 8, 16), tend=0.1)
+    assert np.all(slopes[-1] > 1.8)
+
+
+@pytest.mark.slow
+def test_sync_order_p3_with_time_step_scaling(oracle_mod):
+    # RK3 caps the time order at 3; dt ~ h^(4/3) lets p = 3 show order 4
+    errs, slopes = _sweep(oracle_mod, 2, 3, (8, 16, 32), cfl=0.05, tend=0.1, r=4.0 / 3.0)
+    assert np.all(slopes[-1] > 3.7)
+
+
+def test_vortex_exact_solution_convergence(oracle_mod):
+    # The isentropic vortex is an exact travelling solution of the Euler
+    # equations; a wrong formula would stall the error.
+    O = oracle_mod
+    errs, slopes = _sweep(O, 2, 2, (8, 16, 32), problem=O.VORTEX, hi=(10, 10, 1), tend=0.5, cfl=0.1)
+    assert np.all(slopes[-1] > 2.5)
+
+
+def test_ssprk3_third_order_in_time(oracle_mod):
+    # fixed fine space (p = 4), halve dt: successive differences shrink by 2^3
+    O = oracle_mod
+    sols = []
+    for nst in (20, 40, 80):
+        o = O.Oracle(dim=2, p=4, cells=(4, 4, 1), hi=(1, 1, 1))
+        o.init_problem(O.DENSITY_WAVE)
+        o.step(nst, 0.05 / nst * 4)
+        sols.append(o.state())
+    d1 = np.linalg.norm(sols[0] - sols[1])
+    d2 = np.linalg.norm(sols[1] - sols[2])
+    assert 2 ** 2.8 < d1 / d2 < 2 ** 3.2
+
+
+def test_zero_delay_is_bitwise_synchronous(oracle_mod):
+    O = oracle_mod
+    base = dict(dim=2, p=2, cells=(8, 8, 1), parts=(4, 2, 1), hi=(10, 10, 1))
+    ref = O.Oracle(**base)
+    ref.init_problem(O.VORTEX)
+    dt = ref.stable_dt(0.1)
+    ref.step(10, dt)
+    for ghost in (O.STALE, O.AT, O.LEARNED):
+        o = O.Oracle(ghost=ghost, delay_kind=O.FIXED, L=0, levels=3, **base)
+        o.init_problem(O.VORTEX)
+        o.step(10, dt)
+        np.testing.assert_array_equal(o.state(), ref.state())
+
+
+def test_stale_first_order_at_recovers_sync(oracle_mod):
+    O = oracle_mod
+    common = dict(parts=(4, 4, 1), kind=O.UNIFORM, L=2, cfl=0.05)
+    e_sync, s_sync = _sweep(O, 2, 2, (8, 16, 32), ghost=O.SYNC, cfl=0.05, parts=(4, 4, 1))
+    e_stale, s_stale = _sweep(O, 2, 2, (8, 16, 32), ghost=O.STALE, **common)
+    e_at, s_at = _sweep(O, 2, 2, (8, 16, 32), ghost=O.AT, **common)
+    assert 0.7 < s_stale[-1][0] < 1.4          # density error, first order
+    assert s_at[-1][0] > 2.85                   # order p + 1 recovered
+    np.testing.assert_allclose(e_at, e_sync, rtol=0.02)  # curves overlap
+
+
+# ---------------------------------------------------------------- predictor
+
+def test_mlp_gradient_matches_finite_differences(oracle_mod):
+    O = oracle_mod
+    nin, nh, nout = 16, 8, 5
+    npar = O.mlp_nparams(nin, nh, nout)
+    assert npar == nh * nin + nh + nout * nh + nout
+    w = inputs.mlp_weights(npar, 1)
+    x, y = inputs.mlp_batch(12, nin, nout, 2)
+    loss, g = O.mlp_loss_grad(w, nin, nh, nout, x, y)
+    yp = O.mlp_forward(w, nin, nh, nout, x)
+    assert loss == pytest.approx(np.mean((yp - y) ** 2), rel=1e-14)
+    h = 1e-6
+    for i in range(npar):
+        wp = w.copy(); wp[i] += h
+        wm = w.copy(); wm[i] -= h
+        fd = (O.mlp_loss_grad(wp, nin, nh, nout, x, y)[0] - O.mlp_loss_grad(wm, nin, nh, nout, x, y)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i]))
+
+
+def test_mlp_gelu_is_exact_erf_form(oracle_mod):
+    # one hidden unit, identity read-out: y = GELU(z) with z = w x
+    O = oracle_mod
+    w = np.array([1.0, 0.0, 1.0, 0.0])
+    for z in (-3.0, -0.5, 0.0, 0.7, 2.0):
+        y = O.mlp_forward(w, 1, 1, 1, np.array([z]))[0, 0]
+        assert y == pytest.approx(0.5 * z * (1 + math.erf(z / math.sqrt(2))), rel=1e-15, abs=1e-300)
+
+
+def test_adam_first_step_is_signed_lr(oracle_mod):
+    O = oracle_mod
+    w = np.array([1.0, -2.0, 0.5]); m = np.zeros(3); v = np.zeros(3)
+    O.adam(w, m, v, np.array([0.3, -4.0, 1e-3]), 1e-2, 1)
+    np.testing.assert_allclose(w, [1.0 - 1e-2, -2.0 + 1e-2, 0.5 - 1e-2], rtol=1e-6)
+
+
+def test_learned_features_are_backward_differences(oracle_mod):
+    # a cubic-in-time history has third backward difference 3! * a3
+    O = oracle_mod
+    o = O.Oracle(dim=2, p=1, cells=(4, 4, 1), parts=(2, 2, 1), hi=(1, 1, 1), ghost=O.LEARNED,
+                 delay_kind=O.FIXED, L=1)
+    a3 = np.array([0.5, -1.0, 2.0, 0.25])
+    T = np.array([[1.0 + a3[v] * (-j) ** 3 for v in range(4)] for j in range(4)])
+    x, S3 = o.learned_features(T.ravel(), 2.5)
+    assert S3 == pytest.approx(6 * 2.0)
+    np.testing.assert_allclose(x[8:12], 6 * a3 / 12.0)
+    assert x[12] == 0.25 * 2.5
+
+
+def test_learned_silent_net_accepted_bad_net_rejected(oracle_mod):
+    # a net that outputs exactly zero is accepted everywhere and adds nothing;
+    # a net with a huge output is rejected everywhere: both give the AT ghost
+    O = oracle_mod
+    base = dict(dim=2, p=2, cells=(8, 8, 1), parts=(2, 2, 1), hi=(10, 10, 1), delay_kind=O.UNIFORM,
+                L=2, levels=3, seed=5, ghost=O.LEARNED, learned_tol=1e-6)
+    nin, nh, nout = 13, 64, 4
+    npar = O.mlp_nparams(nin, nh, nout)
+    states = []
+    for b2, accept in ((0.0, True), (1e12, False)):
+        w = np.zeros(npar, dtype=np.float32)
+        w[-nout:] = b2
+        o = O.Oracle(**base)
+        o.init_problem(O.VORTEX)
+        o.set_predictor(w)
+        o.step(8, 0.01)
+        acc, rej = o.learned_stats()
+        assert (rej == 0 and acc > 0) if accept else (acc == 0 and rej > 0)
+        states.append(o.state())
+    np.testing.assert_array_equal(states[0], states[1])
