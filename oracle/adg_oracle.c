@@ -472,7 +472,7 @@ void* orc_create(const orc_cfg* cfg) {
     default: s->Qh = lev > K_MLP ? lev : K_MLP; s->R = cfg->L + s->Qh; break;
   }
   if (s->R > 0) s->hist = (double*)xmalloc(sizeof(double) * nd * s->R);
-  s->nin = 3 * s->V + 1;
+  s->nin = 2 * s->V + 2;
   s->nh = NH_MLP;
   s->nout = s->V;
   return s;
@@ -643,47 +643,61 @@ static float to_bf16(float x) {
   return r;
 }
 
-/* features of one face node from K levels T[j][v] (j = 0 newest) and tau:
- * backward differences of orders 1..3, each normalised by its max over the
- * variables, then tau/4. S3 (returned) scales the output back. */
-void orc_learned_features(void* vs, const double* T, double tau, double* x, double* S3) {
+/* features of one face node from K levels T[j][v] (j = 0 newest), the
+ * fractional delay tau and the stage time c_m (reading): the second and third
+ * backward differences, both divided by S2 = max over the variables of the
+ * second difference, then tau/4 and c_m. The second difference carries the
+ * part of the live stage value an RK stage adds beyond the extrapolated
+ * trajectory, the third the extrapolation error itself; S2 (returned) scales
+ * the output back to physical units. */
+void orc_learned_features(void* vs, const double* T, double tau, double cm, double* x, double* S2) {
   orc_solver* s = (orc_solver*)vs;
   int V = s->V;
-  double d[3][MAXV], S[3] = {0, 0, 0};
+  double d2[MAXV], d3[MAXV], S = 0.0;
   for (int v = 0; v < V; ++v) {
     double t0 = T[0 * V + v], t1 = T[1 * V + v], t2 = T[2 * V + v], t3 = T[3 * V + v];
-    d[0][v] = t0 - t1;
-    d[1][v] = (t0 - 2.0 * t1) + t2;
-    d[2][v] = ((t0 - 3.0 * t1) + 3.0 * t2) - t3;
-    for (int o = 0; o < 3; ++o)
-      if (fabs(d[o][v]) > S[o]) S[o] = fabs(d[o][v]);
+    d2[v] = (t0 - 2.0 * t1) + t2;
+    d3[v] = ((t0 - 3.0 * t1) + 3.0 * t2) - t3;
+    if (fabs(d2[v]) > S) S = fabs(d2[v]);
   }
-  for (int o = 0; o < 3; ++o) S[o] += 1e-300;
-  for (int o = 0; o < 3; ++o)
-    for (int v = 0; v < V; ++v) x[o * V + v] = d[o][v] / S[o];
-  x[3 * V] = 0.25 * tau;
-  *S3 = S[2];
+  S += 1e-300;
+  for (int v = 0; v < V; ++v) {
+    x[v] = d2[v] / S;
+    x[V + v] = d3[v] / S;
+  }
+  x[2 * V] = 0.25 * tau;
+  x[2 * V + 1] = cm;
+  *S2 = S;
 }
 
-static void mlp_bf16_forward(const orc_solver* s, const double* x, double* y) {
-  int nin = s->nin, nh = s->nh, nout = s->nout;
-  const float* W1 = s->mlp;
+/* forward pass with inputs, weights and hidden activations rounded to bf16
+ * and everything else in (at least) binary32 precision */
+void orc_mlp_forward_bf16(const float* w, int nin, int nh, int nout, int64_t n, const double* xs, double* ys) {
+  const float* W1 = w;
   const float* b1 = W1 + nh * nin;
   const float* W2 = b1 + nh;
   const float* b2 = W2 + nout * nh;
-  double hb[128];
-  for (int h = 0; h < nh; ++h) {
-    double z = 0.0;
-    for (int i = 0; i < nin; ++i) z += (double)to_bf16(W1[h * nin + i]) * (double)to_bf16((float)x[i]);
-    float zf = (float)(z + (double)b1[h]);
-    double a = 0.5 * (double)zf * (1.0 + erf((double)zf / sqrt(2.0)));
-    hb[h] = (double)to_bf16((float)a);
+  for (int64_t s = 0; s < n; ++s) {
+    const double* x = xs + s * nin;
+    double* y = ys + s * nout;
+    double hb[1024];
+    for (int h = 0; h < nh; ++h) {
+      double z = 0.0;
+      for (int i = 0; i < nin; ++i) z += (double)to_bf16(W1[h * nin + i]) * (double)to_bf16((float)x[i]);
+      float zf = (float)(z + (double)b1[h]);
+      double a = 0.5 * (double)zf * (1.0 + erf((double)zf / sqrt(2.0)));
+      hb[h] = (double)to_bf16((float)a);
+    }
+    for (int o = 0; o < nout; ++o) {
+      double z = 0.0;
+      for (int h = 0; h < nh; ++h) z += (double)to_bf16(W2[o * nh + h]) * hb[h];
+      y[o] = (double)(float)(z + (double)b2[o]);
+    }
   }
-  for (int o = 0; o < nout; ++o) {
-    double z = 0.0;
-    for (int h = 0; h < nh; ++h) z += (double)to_bf16(W2[o * nh + h]) * hb[h];
-    y[o] = (double)(float)(z + (double)b2[o]);
-  }
+}
+
+static void mlp_bf16_forward(const orc_solver* s, const double* x, double* y) {
+  orc_mlp_forward_bf16(s->mlp, s->nin, s->nh, s->nout, 1, x, y);
 }
 
 /* ghost of face-side (e, f) at face Gauss points: g[fq][v] */
@@ -730,7 +744,7 @@ static void ghost_face(orc_solver* s, const double* uin, int64_t e, int f, int s
       gn[j * V + v] = a;
     }
     double x[32], y[MAXV], S3;
-    orc_learned_features(s, T, tau, x, &S3);
+    orc_learned_features(s, T, tau, SSP_C[stage], x, &S3);
     if (s->has_mlp) {
       mlp_bf16_forward(s, x, y);
     } else {

@@ -73,11 +73,12 @@ int orc_mlp_nparams(int nin, int nh, int nout);
 void orc_mlp_forward(const double* w, int nin, int nh, int nout, int64_t n, const double* x, double* y);
 double orc_mlp_loss_grad(const double* w, int nin, int nh, int nout, int64_t n, const double* x,
                          const double* y, double* grad);
+void orc_mlp_forward_bf16(const float* w, int nin, int nh, int nout, int64_t n, const double* x, double* y);
 void orc_adam(double* w, double* m, double* v, const double* g, int np, double lr, double b1,
               double b2, double eps, int64_t t);
 void orc_set_predictor(void* s, const float* w);
 void orc_learned_stats(void* s, int64_t* accepted, int64_t* rejected);
-void orc_learned_features(void* s, const double* T, double tau, double* x, double* S3);
+void orc_learned_features(void* s, const double* T, double tau, double cm, double* x, double* S2);
 
 #ifdef __cplusplus
 }

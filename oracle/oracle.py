@@ -67,13 +67,14 @@ def lib():
         L.orc_stable_dt.restype = C.c_double
         L.orc_mlp_nparams.argtypes = [C.c_int] * 3
         L.orc_mlp_forward.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int64, dp, dp]
+        L.orc_mlp_forward_bf16.argtypes = [C.POINTER(C.c_float), C.c_int, C.c_int, C.c_int, C.c_int64, dp, dp]
         L.orc_mlp_loss_grad.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int64, dp, dp, dp]
         L.orc_mlp_loss_grad.restype = C.c_double
         L.orc_adam.argtypes = [dp, dp, dp, dp, C.c_int, C.c_double, C.c_double, C.c_double,
                                C.c_double, C.c_int64]
         L.orc_set_predictor.argtypes = [vp, C.POINTER(C.c_float)]
         L.orc_learned_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
-        L.orc_learned_features.argtypes = [vp, dp, C.c_double, dp, dp]
+        L.orc_learned_features.argtypes = [vp, dp, C.c_double, C.c_double, dp, dp]
         _lib = L
     return _lib
 
@@ -223,11 +224,11 @@ class Oracle:
         lib().orc_learned_stats(self.ptr, C.byref(a), C.byref(r))
         return a.value, r.value
 
-    def learned_features(self, T, tau):
+    def learned_features(self, T, tau, cm):
         T = np.ascontiguousarray(T, dtype=np.float64)
-        x = np.zeros(3 * self.V + 1); s3 = C.c_double()
-        lib().orc_learned_features(self.ptr, _dp(T), float(tau), _dp(x), C.byref(s3))
-        return x, s3.value
+        x = np.zeros(2 * self.V + 2); s2 = C.c_double()
+        lib().orc_learned_features(self.ptr, _dp(T), float(tau), float(cm), _dp(x), C.byref(s2))
+        return x, s2.value
 
 
 def mlp_nparams(nin, nh, nout):
@@ -240,6 +241,16 @@ def mlp_forward(w, nin, nh, nout, x):
     n = x.size // nin
     y = np.zeros(n * nout)
     lib().orc_mlp_forward(_dp(w), nin, nh, nout, n, _dp(x), _dp(y))
+    return y.reshape(n, nout)
+
+
+def mlp_forward_bf16(w32, nin, nh, nout, x):
+    """forward pass in the precision of the GPU inference (bf16 operands)"""
+    w32 = np.ascontiguousarray(w32, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = x.size // nin
+    y = np.zeros(n * nout)
+    lib().orc_mlp_forward_bf16(w32.ctypes.data_as(C.POINTER(C.c_float)), nin, nh, nout, n, _dp(x), _dp(y))
     return y.reshape(n, nout)
 
 

@@ -335,16 +335,21 @@ def test_adam_first_step_is_signed_lr(oracle_mod):
 
 
 def test_learned_features_are_backward_differences(oracle_mod):
-    # a cubic-in-time history has third backward difference 3! * a3
+    # T(s) = 1 + a2 s^2 + a3 s^3 sampled at s = 0, -1, -2, -3: the second
+    # backward difference is 2 a2 - 6 a3, the third 6 a3 (finite differences
+    # of polynomials); features divide both by max |second difference|
     O = oracle_mod
     o = O.Oracle(dim=2, p=1, cells=(4, 4, 1), parts=(2, 2, 1), hi=(1, 1, 1), ghost=O.LEARNED,
                  delay_kind=O.FIXED, L=1)
+    a2 = np.array([1.0, 0.0, -0.5, 3.0])
     a3 = np.array([0.5, -1.0, 2.0, 0.25])
-    T = np.array([[1.0 + a3[v] * (-j) ** 3 for v in range(4)] for j in range(4)])
-    x, S3 = o.learned_features(T.ravel(), 2.5)
-    assert S3 == pytest.approx(6 * 2.0)
-    np.testing.assert_allclose(x[8:12], 6 * a3 / 12.0)
-    assert x[12] == 0.25 * 2.5
+    T = np.array([[1.0 + a2[v] * (-j) ** 2 + a3[v] * (-j) ** 3 for v in range(4)] for j in range(4)])
+    x, S2 = o.learned_features(T.ravel(), 2.5, 0.5)
+    d2, d3 = 2 * a2 - 6 * a3, 6 * a3
+    assert S2 == pytest.approx(np.abs(d2).max())
+    np.testing.assert_allclose(x[0:4], d2 / S2, rtol=1e-14)
+    np.testing.assert_allclose(x[4:8], d3 / S2, rtol=1e-14)
+    assert x[8] == 0.25 * 2.5 and x[9] == 0.5
 
 
 def test_learned_silent_net_accepted_bad_net_rejected(oracle_mod):
@@ -353,7 +358,7 @@ def test_learned_silent_net_accepted_bad_net_rejected(oracle_mod):
     O = oracle_mod
     base = dict(dim=2, p=2, cells=(8, 8, 1), parts=(2, 2, 1), hi=(10, 10, 1), delay_kind=O.UNIFORM,
                 L=2, levels=3, seed=5, ghost=O.LEARNED, learned_tol=1e-6)
-    nin, nh, nout = 13, 64, 4
+    nin, nh, nout = 10, 64, 4
     npar = O.mlp_nparams(nin, nh, nout)
     states = []
     for b2, accept in ((0.0, True), (1e12, False)):
