@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the asynchronous DG solver with AT neighbour traces on one
+MI355X: DOF-updates per second per SSP-RK3 stage.
+
+A step is one full SSP-RK3 step (3 stages, each: ring publish/ghost traces at
+the PE-boundary faces, then the fused right-hand-side stage kernel) over the
+whole mesh. Inputs are synthetic and resident in HBM before the timed region.
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+# Workloads (synthetic, analytic initial states). The default is the 2D
+# isentropic vortex on the periodic [0,10]^2 box, 256x256 quads, degree 3,
+# 8x8 virtual subdomains, AT extrapolation over 3 past levels, delays drawn
+# uniformly in {0..3} per step, subdomain and face direction.
+WORKLOADS = {
+    "vortex256_p3_at3_uniformL3": dict(
+        cfg=dict(dim=2, degree=3, cells=(256, 256, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
+        asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=0),
+    "vortex16_p2_sync": dict(
+        cfg=dict(dim=2, degree=2, cells=(16, 16, 1), parts=(1, 1, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
+        asy=dict(ghost=0, delay_kind=0, L=0, levels=3, seed=0), problem=0, precision=0),
+    "wave64_p3_at3_fixedL2": dict(
+        cfg=dict(dim=3, degree=3, cells=(64, 64, 64), parts=(4, 4, 4), lo=(0, 0, 0), hi=(1, 1, 1)),
+        asy=dict(ghost=2, delay_kind=0, L=2, levels=3, seed=0), problem=1, precision=0),
+    "vortex1024_p4_at3_uniformL3_fp32": dict(
+        cfg=dict(dim=2, degree=4, cells=(1024, 1024, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
+        asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=1),
+    "vortex1024_p4_at3_uniformL3_fp64": dict(
+        cfg=dict(dim=2, degree=4, cells=(1024, 1024, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
+        asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=0),
+    "wave128_p2_at3_uniformL4": dict(
+        cfg=dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1)),
+        asy=dict(ghost=2, delay_kind=1, L=4, levels=3, seed=0), problem=1, precision=0),
+}
+DEFAULT = "vortex256_p3_at3_uniformL3"
+
+
+def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, async_on):
+    """Minimum HBM bytes of one fused stage launch: the stage input read once,
+    u^n read on stages 2 and 3, the output written (8 B each per DoF,
+    averaged over the 3 stages: 64/3 B per DoF), plus the ghost traces read at
+    PE-boundary faces."""
+    return ndof * 64.0 / 3.0 + (8.0 * nfs_nodes_vars if async_on else 0.0)
+
+
+def algorithmic_flops_per_element(dim, P, Q):
+    """Flops of one element-stage of the sum-factorised operator (FMA = 2):
+    d interpolation sweeps nodes->Gauss points, the Euler flux at every Gauss
+    point, d collocation-derivative sweeps, d transposed interpolation sweeps,
+    the face fluxes on 2d faces (trace interpolation of both sides, LLF flux,
+    lift) and d inverse-mass sweeps, plus the RK combine."""
+    V = dim + 2
+    if dim == 2:
+        interp = V * (P * P * Q + Q * P * Q)
+        Fq, Fn = Q, P
+    else:
+        interp = V * (P * P * P * Q + Q * P * P * Q + Q * Q * P * Q)
+        Fq, Fn = Q * Q, P * P
+    Qd, Pd, nf = Q ** dim, P ** dim, 2 * dim
+    deriv = dim * V * Qd * Q                 # FMAs
+    test = interp                            # FMAs (transposed sweeps)
+    traces = 2 * nf * Fq * V * Fn            # FMAs, both sides at each face Gauss point
+    lift = nf * V * Fn * Fq                  # FMAs
+    minv = dim * V * Pd * P                  # FMAs
+    flux_qp = 12 + dim * (2 * V + 3)         # pressure, 1/rho, d scaled flux columns
+    llf = 60 + 2 * V                         # two normal fluxes, wave speeds, scaling
+    combine = 4 * V * Pd
+    return 2 * (interp + deriv + test + traces + lift + minv) + Qd * flux_qp + nf * Fq * llf + combine
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("adg_rhs.hip",):
+        with open(os.path.join(ROOT, "paper_2603_28710_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"rhs_stage_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha256_16") != source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, target_s=15.0):
+    """The FP64 CPU oracle, untuned, on a bounded sample of the same workload:
+    the full mesh, a few steps (as many as fit in about target_s seconds)."""
+    from oracle import oracle as O
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    if threads <= 0:
+        threads = min(len(os.sched_getaffinity(0)), 16)
+        os.environ["OMP_NUM_THREADS"] = str(threads)
+    c, a = w["cfg"], w["asy"]
+    o = O.Oracle(dim=c["dim"], p=c["degree"], cells=c["cells"], parts=c["parts"], lo=c["lo"], hi=c["hi"],
+                 ghost=a["ghost"], delay_kind=a["delay_kind"], L=a["L"], levels=a["levels"], seed=a["seed"])
+    o.init_problem(w["problem"])
+    dt = o.stable_dt(0.1)
+    t0 = time.perf_counter()
+    o.step(1, dt)
+    t1 = time.perf_counter()
+    n = max(1, min(50, int(target_s / max(t1 - t0, 1e-3)) - 1))
+    t2 = time.perf_counter()
+    o.step(n, dt)
+    t3 = time.perf_counter()
+    return {"value": o.ndof * 3 * n / (t3 - t2), "unit": "DOF-updates/s per RK stage", "cores": threads,
+            "kind": "oracle",
+            "sample": f"full mesh, {n} SSP-RK3 steps after 1 warm-up step ({t3 - t2:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU path is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2603_28710_amd import binding as B
+    from paper_2603_28710_amd.solver import Solver
+
+    w = WORKLOADS[args.workload]
+    c, a = w["cfg"], w["asy"]
+    s = Solver(device="cuda:0", precision=w["precision"], **c, **a)
+    s.init_problem(w["problem"])
+    dt = s.stable_dt(0.1)
+    s.step(args.warmup, dt)
+    torch.cuda.synchronize()
+
+    B.adg_profile(s.h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.step_status(args.steps, dt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if st != 0:
+        raise RuntimeError(B.adg_last_error())
+    rhs_ms, rhs_n = B.adg_profile_read(s.h, B.ADG_KERNEL_RHS)
+    gh_ms, gh_n = B.adg_profile_read(s.h, B.ADG_KERNEL_GHOST)
+    B.adg_profile(s.h, 0)
+
+    sec = t1 - t0
+    stages = 3 * args.steps
+    value = s.ndof * stages / sec
+    nfs = B.adg_delay(s.h, s.time()[0], 0, 0)[1]
+    Fn = (c["degree"] + 1) ** (c["dim"] - 1)
+    async_on = a["ghost"] != 0 and nfs > 0
+    bytes_launch = algorithmic_bytes_per_launch(s.ndof, nfs * s.V * Fn, async_on)
+    avg_s = rhs_ms / max(rhs_n, 1) / 1e3
+    achieved = bytes_launch / avg_s / 1e9
+    P, Q = c["degree"] + 1, c["degree"] + 2
+    flops_launch = algorithmic_flops_per_element(c["dim"], P, Q) * s.E
+    fpeak = FP32_PEAK_TFLOPS if w["precision"] else FP64_PEAK_TFLOPS
+    traffic = load_traffic(args.workload)
+    err = s.error_norms(w["problem"]) if w["problem"] in (0, 1) else None
+
+    out = {
+        "metric": "DOF-updates/s per RK stage",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-contract/f64-state" if w["precision"] else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dim": c["dim"], "degree": c["degree"],
+                   "cells": list(c["cells"][: c["dim"]]), "parts": list(c["parts"][: c["dim"]]),
+                   "ghost": ["sync", "stale", "at", "learned"][a["ghost"]], "levels": a["levels"],
+                   "delay": ["fixed", "uniform", "caa"][a["delay_kind"]], "L": a["L"], "seed": a["seed"],
+                   "dofs": s.ndof, "elements": s.E, "dt": dt, "cfl": 0.1},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "rhs_stage", "avg_launch_us": avg_s * 1e6, "launches": rhs_n,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+        "alu": {"achieved_tflops": flops_launch / avg_s / 1e12, "peak_tflops": fpeak,
+                "frac": flops_launch / avg_s / 1e12 / fpeak, "flops_per_launch": flops_launch},
+        "ghost_kernel": {"avg_launch_us": gh_ms / max(gh_n, 1) * 1e3, "launches": gh_n},
+        "l2_error_vs_exact": err,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

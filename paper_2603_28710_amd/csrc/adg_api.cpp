@@ -1,0 +1,786 @@
+// adg_api.cpp — host runtime behind include/adg.h: configuration checks, the
+// 1D tables (Gauss-Lobatto nodes, Gauss rule, interpolation, collocation
+// derivative, inverse mass), the periodic box and its virtual subdomains, the
+// SSP-RK3 stage loop with its ghost/ring launches, diagnostics and
+// checkpoints. All GPU work goes to the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/adg.h"
+#include "adg_internal.h"
+#include "adg_ctx.h"
+
+using namespace adg;
+
+namespace adg {
+thread_local std::string g_err;
+}
+
+namespace {
+
+// ---------------------------------------------------------------- 1D tables
+
+// Legendre P_n and its derivative by the Bonnet recurrence
+void legendre(int n, double x, double& Pn, double& dPn) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) {
+    Pn = 1.0;
+    dPn = 0.0;
+    return;
+  }
+  for (int k = 1; k < n; ++k) {
+    const double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+    p0 = p1;
+    p1 = p2;
+  }
+  Pn = p1;
+  dPn = n * (p0 - x * p1) / (1.0 - x * x);
+}
+
+// Gauss-Legendre rule: Newton from Tricomi's initial guesses
+void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const double th = M_PI * (4.0 * (n - i) - 1.0) / (4.0 * n + 2.0);
+    double z = (1.0 - (n - 1.0) / (8.0 * n * n * n)) * std::cos(th);
+    for (int it = 0; it < 60; ++it) {
+      double P, dP;
+      legendre(n, z, P, dP);
+      const double dz = P / dP;
+      z -= dz;
+      if (std::fabs(dz) < 1e-17) break;
+    }
+    double P, dP;
+    legendre(n, z, P, dP);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dP * dP);
+  }
+}
+
+// Gauss-Lobatto-Legendre: interior nodes are the zeros of P'_N, one between
+// each pair of consecutive zeros of P_N (Rolle). Safeguarded Newton on
+// q = (1-x^2) P'_N, whose derivative is -N(N+1) P_N, inside that bracket.
+// Weights 2 / (N (N+1) P_N^2).
+void gll_rule(int n, std::vector<double>& x, std::vector<double>& w) {
+  const int N = n - 1;
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  x[0] = -1.0;
+  x[N] = 1.0;
+  std::vector<double> g, gw;
+  if (N >= 2) gauss_rule(N, g, gw);
+  for (int i = 1; i < N; ++i) {
+    double lo = g[i - 1], hi = g[i];
+    auto qf = [&](double z) {
+      double P, dP;
+      legendre(N, z, P, dP);
+      return (1.0 - z * z) * dP;
+    };
+    const double qlo = qf(lo);
+    double z = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+      double P, dP;
+      legendre(N, z, P, dP);
+      const double q = (1.0 - z * z) * dP;
+      if (q == 0.0) break;
+      if ((q > 0) == (qlo > 0))
+        lo = z;
+      else
+        hi = z;
+      const double dq = -N * (N + 1.0) * P;
+      double zn = z - q / dq;
+      if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
+      const double dz = zn - z;
+      z = zn;
+      if (std::fabs(dz) < 1e-17 || hi - lo < 1e-16) break;
+    }
+    x[i] = z;
+  }
+  for (int i = 0; i < n; ++i) {
+    double P, dP;
+    legendre(N, x[i], P, dP);
+    w[i] = 2.0 / (N * (N + 1.0) * P * P);
+  }
+}
+
+// barycentric Lagrange basis on `nodes` evaluated at x
+std::vector<double> bary_eval(const std::vector<double>& nodes, double x) {
+  const int n = (int)nodes.size();
+  std::vector<double> lam(n, 1.0), out(n, 0.0);
+  for (int j = 0; j < n; ++j)
+    for (int m = 0; m < n; ++m)
+      if (m != j) lam[j] /= (nodes[j] - nodes[m]);
+  for (int j = 0; j < n; ++j)
+    if (x == nodes[j]) {
+      out[j] = 1.0;
+      return out;
+    }
+  double den = 0.0;
+  for (int j = 0; j < n; ++j) den += lam[j] / (x - nodes[j]);
+  for (int j = 0; j < n; ++j) out[j] = lam[j] / (x - nodes[j]) / den;
+  return out;
+}
+
+// differentiation matrix D[i][j] = l_j'(x_i) on `nodes` (barycentric form)
+std::vector<double> bary_diff(const std::vector<double>& nodes) {
+  const int n = (int)nodes.size();
+  std::vector<double> lam(n, 1.0), Dm(n * n, 0.0);
+  for (int j = 0; j < n; ++j)
+    for (int m = 0; m < n; ++m)
+      if (m != j) lam[j] /= (nodes[j] - nodes[m]);
+  for (int i = 0; i < n; ++i) {
+    double diag = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (i == j) continue;
+      Dm[i * n + j] = (lam[j] / lam[i]) / (nodes[i] - nodes[j]);
+      diag -= Dm[i * n + j];
+    }
+    Dm[i * n + i] = diag;
+  }
+  return Dm;
+}
+
+// inverse of a symmetric positive definite matrix via Cholesky
+bool spd_inverse(int n, const std::vector<double>& A, std::vector<double>& Ai) {
+  std::vector<double> L(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = A[i * n + j];
+      for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+      if (i == j) {
+        if (s <= 0.0) return false;
+        L[i * n + i] = std::sqrt(s);
+      } else {
+        L[i * n + j] = s / L[j * n + j];
+      }
+    }
+  Ai.assign(n * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    std::vector<double> y(n, 0.0);
+    for (int i = 0; i < n; ++i) {  // L y = e_c
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) s -= L[i * n + k] * y[k];
+      y[i] = s / L[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {  // L^T x = y
+      double s = y[i];
+      for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * Ai[k * n + c];
+      Ai[i * n + c] = s / L[i * n + i];
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+namespace {
+
+const double kSspA[3] = {0.0, 0.75, 1.0 / 3.0};
+const double kSspB[3] = {1.0, 0.25, 2.0 / 3.0};
+const double kSspC[3] = {0.0, 1.0, 0.5};
+
+adg_status check_async(const adg_config& c, const adg_async& a) {
+  (void)c;
+  if (a.ghost < 0 || a.ghost > 3) return fail(ADG_ERR_INVALID, "async.ghost must be 0..3");
+  if (a.delay_kind < 0 || a.delay_kind > 2) return fail(ADG_ERR_INVALID, "async.delay_kind must be 0..2");
+  if (a.L < 0 || a.L > 16) return fail(ADG_ERR_INVALID, "async.L must be in 0..16");
+  if (a.levels < 1 || a.levels > 4) return fail(ADG_ERR_INVALID, "async.levels must be in 1..4");
+  if (a.ghost == 1 && a.delay_kind == 2 && a.L < 1) return fail(ADG_ERR_INVALID, "CAA with STALE needs L >= 1");
+  if (!(a.learned_tol >= 0.0)) return fail(ADG_ERR_INVALID, "async.learned_tol must be >= 0");
+  return ADG_OK;
+}
+
+void depth_of(const adg_async& a, int& R, int& Qh) {
+  switch (a.ghost) {
+    case 0: R = 0; Qh = 1; break;
+    case 1: R = a.L + 1; Qh = 1; break;
+    case 2: R = a.L + a.levels; Qh = a.levels; break;
+    default: Qh = a.levels > kMlpK ? a.levels : kMlpK; R = a.L + Qh; break;
+  }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Async make_async(const adg_ctx_s* c, int stage) {
+  Async A{};
+  A.ghost = c->as.ghost;
+  A.delay_kind = c->as.delay_kind;
+  A.L = c->as.L;
+  A.levels = c->as.levels;
+  A.Qh = c->Qh;
+  A.R = c->R;
+  A.seed = c->as.seed;
+  A.n = c->n;
+  A.n_rel = c->n - c->hist_start;
+  A.stage = stage;
+  A.c_m = kSspC[stage];
+  A.tol = c->as.learned_tol;
+  return A;
+}
+
+double* scratch_d(adg_ctx_s* c, size_t off) { return reinterpret_cast<double*>(c->scratch + off); }
+
+adg_status run_norms(adg_ctx_s* c, int what, int problem, const double* params, const double* u, const double* ref,
+                     int ncomp, int op, double* host_out) {
+  Prm prm{};
+  const double def[3][5] = {{5, 5, 5, 1, 1}, {0.2, 1, 1, 1, 1}, {1, 0.3, -0.2, 0.1, 1}};
+  const int pi = (problem >= 0 && problem <= 2) ? problem : 2;
+  for (int i = 0; i < 5; ++i) prm.v[i] = params ? params[i] : def[pi][i];
+  const int nblk = norms_blocks(c->mesh.E);
+  double* partial = scratch_d(c, c->partial_off);
+  double* red = scratch_d(c, c->red_off);
+  HIP_TRY(launch_norms(c->D, c->p, c->mesh, what, problem, prm, c->t, u, ref, c->d_tab64, partial, nblk, c->stream));
+  HIP_TRY(launch_reduce(partial, nblk, ncomp, op, red, c->stream));
+  HIP_TRY(hipMemcpyAsync(host_out, red, sizeof(double) * ncomp, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return ADG_OK;
+}
+
+adg_status check_state(adg_ctx_s* c) {
+  double r[2];
+  adg_status s = run_norms(c, 3, 0, nullptr, c->u_n, nullptr, 2, 0, r);
+  if (s != ADG_OK) return s;
+  if (r[0] > 0) return fail(ADG_ERR_NONFINITE, "state holds non-finite values at step " + std::to_string(c->n));
+  if (r[1] > 0) return fail(ADG_ERR_NONPHYSICAL, "density or pressure <= 0 at step " + std::to_string(c->n));
+  return ADG_OK;
+}
+
+}  // namespace
+
+// one SSP-RK3 stage: ghost traces (PE faces) then the fused RHS stage
+// ---- event timing --------------------------------------------------------
+constexpr int kProfPairs = 2048;
+
+adg_status adg::prof_fold(adg_ctx_s* c) {
+  auto& P = c->prof;
+  if (!P.used) return ADG_OK;
+  HIP_TRY(hipEventSynchronize(P.ev[2 * (P.used - 1) + 1]));
+  for (int i = 0; i < P.used; ++i) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, P.ev[2 * i], P.ev[2 * i + 1]));
+    P.ms[P.kind[i]] += ms;
+    P.cnt[P.kind[i]] += 1;
+  }
+  P.used = 0;
+  return ADG_OK;
+}
+
+adg_status adg::prof_begin(adg_ctx_s* c, int kind) {
+  auto& P = c->prof;
+  if (!P.on) return ADG_OK;
+  if (P.used == kProfPairs) {
+    adg_status s = prof_fold(c);
+    if (s != ADG_OK) return s;
+  }
+  P.kind[P.used] = kind;
+  HIP_TRY(hipEventRecord(P.ev[2 * P.used], c->stream));
+  return ADG_OK;
+}
+
+adg_status adg::prof_end(adg_ctx_s* c) {
+  auto& P = c->prof;
+  if (!P.on) return ADG_OK;
+  HIP_TRY(hipEventRecord(P.ev[2 * P.used + 1], c->stream));
+  P.used += 1;
+  return ADG_OK;
+}
+
+#define PROF_TRY(x)                \
+  do {                             \
+    adg_status _s = (x);           \
+    if (_s != ADG_OK) return _s;   \
+  } while (0)
+
+static adg_status run_stage(adg_ctx_s* c, int m, double dt, bool learned_collect, long long pair_base) {
+  double* in[3] = {c->u_n, c->u_a, c->u_b};
+  double* out[3] = {c->u_a, c->u_b, c->u_n};
+  Async A = make_async(c, m);
+  double* ghost = scratch_d(c, c->ghost_off);
+  if (A.ghost != 0 && c->mesh.nfs > 0) {
+    PROF_TRY(prof_begin(c, ADG_KERNEL_GHOST));
+    if (A.ghost == 3 || learned_collect) {
+      HIP_TRY(launch_ghost_learned(c->D, c->p, c->mesh, A, in[m], c->u_n, c->ring, ghost, m == 0, c->mlp,
+                                   pair_base, learned_collect, c->stream));
+    } else {
+      HIP_TRY(launch_ghost(c->D, c->p, c->mesh, A, in[m], c->u_n, c->ring, ghost, nullptr, m == 0, nullptr,
+                           c->stream));
+    }
+    PROF_TRY(prof_end(c));
+  }
+  Stage S{kSspA[m], kSspB[m], dt};
+  PROF_TRY(prof_begin(c, ADG_KERNEL_RHS));
+  HIP_TRY(launch_rhs_stage(c->D, c->p, c->cfg.precision, c->mesh, A, S, in[m], c->u_n, out[m], ghost,
+                           c->d_tab64, c->d_tab32, c->stream));
+  PROF_TRY(prof_end(c));
+  return ADG_OK;
+}
+
+adg_status adg::adg_step_impl(adg_ctx c, int64_t n_steps, double dt, bool collect) {
+  if (!c) return fail(ADG_ERR_INVALID, "null context");
+  if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
+  if (n_steps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return fail(ADG_ERR_INVALID, "need n_steps >= 0, dt > 0");
+  if (c->as.ghost != 0 && c->mesh.nfs > 0 && c->R > 0 && !c->ring) return fail(ADG_ERR_UNBOUND, "ring not bound");
+  const int ce = c->cfg.check_every;
+  for (int64_t it = 0; it < n_steps; ++it) {
+    for (int m = 0; m < 3; ++m) {
+      // collection writes one pair slot per PE-boundary face node and stage
+      const long long per = c->mesh.nfs * (long long)c->Fn;
+      const bool col = collect && per > 0 && c->mlp.n_pairs + per <= c->mlp.max_pairs;
+      adg_status s = run_stage(c, m, dt, col, col ? c->mlp.n_pairs : 0);
+      if (s != ADG_OK) return s;
+      if (col) c->mlp.n_pairs += per;
+    }
+    c->n += 1;
+    c->t += dt;
+    if (ce > 0 && (c->n % ce == 0 || it == n_steps - 1)) {
+      adg_status s = check_state(c);
+      if (s != ADG_OK) return s;
+    }
+  }
+  return ADG_OK;
+}
+
+
+// ----------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char* adg_last_error(void) { return adg::g_err.c_str(); }
+
+adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_stream, adg_ctx* out) {
+  if (!cfg || !async || !out) return fail(ADG_ERR_INVALID, "null argument");
+  *out = nullptr;
+  const adg_config& c = *cfg;
+  if (c.dim != 2 && c.dim != 3) return fail(ADG_ERR_INVALID, "dim must be 2 or 3");
+  if (c.degree < 1 || c.degree > 4) return fail(ADG_ERR_INVALID, "degree must be in 1..4");
+  if (c.n_q != 0 && c.n_q != c.degree + 2) return fail(ADG_ERR_INVALID, "n_q must be 0 or degree+2");
+  if (!(c.gamma > 1.0)) return fail(ADG_ERR_INVALID, "gamma must be > 1");
+  if (c.flux != ADG_FLUX_LLF && c.flux != ADG_FLUX_RUSANOV) return fail(ADG_ERR_INVALID, "unknown flux");
+  if (c.integrator != ADG_SSPRK3) return fail(ADG_ERR_INVALID, "only ADG_SSPRK3 is available");
+  if (c.precision != ADG_FP64 && c.precision != ADG_FP32_CONTRACT) return fail(ADG_ERR_INVALID, "unknown precision");
+  if (c.check_every < 0) return fail(ADG_ERR_INVALID, "check_every must be >= 0");
+  for (int k = 0; k < c.dim; ++k) {
+    if (c.cells[k] < 1 || c.parts[k] < 1) return fail(ADG_ERR_INVALID, "cells and parts must be >= 1");
+    if (c.cells[k] % c.parts[k]) return fail(ADG_ERR_INVALID, "cells must be divisible by parts");
+    if (!(c.hi[k] > c.lo[k])) return fail(ADG_ERR_INVALID, "hi must exceed lo");
+  }
+  adg_status st = check_async(c, *async);
+  if (st != ADG_OK) return st;
+  long long E = 1;
+  for (int k = 0; k < c.dim; ++k) E *= c.cells[k];
+  if (E > (1ll << 31)) return fail(ADG_ERR_INVALID, "too many elements");
+
+  adg_ctx_s* x = new adg_ctx_s();
+  x->cfg = c;
+  x->as = *async;
+  x->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  x->D = c.dim;
+  x->p = c.degree;
+  x->P = c.degree + 1;
+  x->Q = c.degree + 2;
+  x->V = c.dim + 2;
+  x->Pd = x->P * x->P * (c.dim == 3 ? x->P : 1);
+  x->Fn = x->Pd / x->P;
+
+  Mesh& M = x->mesh;
+  M.dim = c.dim;
+  M.E = E;
+  M.nsub = 1;
+  M.detJ = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    const bool on = k < c.dim;
+    M.nc[k] = on ? c.cells[k] : 1;
+    M.parts[k] = on ? c.parts[k] : 1;
+    M.m[k] = M.nc[k] / M.parts[k];
+    M.nsub *= M.parts[k];
+    M.lo[k] = on ? c.lo[k] : 0.0;
+    M.hi[k] = on ? c.hi[k] : 1.0;
+    M.h[k] = on ? (c.hi[k] - c.lo[k]) / c.cells[k] : 2.0;
+    if (on) M.detJ *= 0.5 * M.h[k];
+  }
+  for (int a = 0; a < 3; ++a) {
+    M.detJf[a] = 1.0;
+    for (int k = 0; k < c.dim; ++k)
+      if (k != a) M.detJf[a] *= 0.5 * M.h[k];
+  }
+  M.gamma = c.gamma;
+  M.flux = c.flux;
+  int off = 0;
+  for (int f = 0; f < 6; ++f) {
+    M.fs_off[f] = -1;
+    if (f >= 2 * c.dim) continue;
+    const int a = f / 2;
+    if (M.parts[a] < 2) continue;
+    int A = 1;
+    for (int k = 0; k < c.dim; ++k)
+      if (k != a) A *= M.m[k];
+    M.fs_off[f] = off;
+    off += A;
+  }
+  M.fs_sub = off;
+  M.nfs = (long long)off * M.nsub;
+  x->ndof = (size_t)E * x->V * x->Pd;
+  depth_of(x->as, x->R, x->Qh);
+
+  // 1D tables
+  std::vector<double> xg, wg, xl, wl;
+  gauss_rule(x->Q, xg, wg);
+  gll_rule(x->P, xl, wl);
+  const int P = x->P, Q = x->Q;
+  const TabOff to = tab_off(P, Q);
+  x->tab64.assign(to.total, 0.0);
+  double* T = x->tab64.data();
+  for (int q = 0; q < Q; ++q) {
+    std::vector<double> l = bary_eval(xl, xg[q]);
+    for (int j = 0; j < P; ++j) {
+      T[to.B + q * P + j] = l[j];
+      T[to.BT + j * Q + q] = l[j];
+    }
+  }
+  std::vector<double> Dg = bary_diff(xg);  // Dg[q][r] = l^G_r'(x_q)
+  for (int r = 0; r < Q; ++r)
+    for (int q = 0; q < Q; ++q) T[to.DT + r * Q + q] = Dg[q * Q + r];
+  std::vector<double> M1(P * P, 0.0), M1i;
+  for (int i = 0; i < P; ++i)
+    for (int j = 0; j < P; ++j)
+      for (int q = 0; q < Q; ++q) M1[i * P + j] += wg[q] * T[to.B + q * P + i] * T[to.B + q * P + j];
+  if (!spd_inverse(P, M1, M1i)) {
+    delete x;
+    return fail(ADG_ERR_INVALID, "mass matrix not positive definite");
+  }
+  for (int i = 0; i < P * P; ++i) T[to.MI + i] = M1i[i];
+  for (int q = 0; q < Q; ++q) {
+    T[to.WQ + q] = wg[q];
+    T[to.XQ + q] = xg[q];
+  }
+  for (int j = 0; j < P; ++j) {
+    T[to.XL + j] = xl[j];
+    T[to.WL + j] = wl[j];
+  }
+  // buffer plan
+  x->ring_bytes = (size_t)x->R * (size_t)M.nfs * x->V * x->Fn * sizeof(double);
+  size_t s = 0;
+  x->ghost_off = s;
+  s = align256(s + (size_t)M.nfs * x->V * x->Fn * sizeof(double));
+  x->partial_off = s;
+  s = align256(s + 2048 * 6 * sizeof(double));
+  x->red_off = s;
+  s = align256(s + 16 * sizeof(double));
+  x->mlp_off = s;
+  s = align256(s + mlp_scratch_bytes(x->V));
+  x->scratch_bytes = s;
+  mlp_init(x->mlp, x->V);
+  *out = x;
+  return ADG_OK;
+}
+
+adg_status adg_destroy(adg_ctx c) {
+  if (!c) return ADG_OK;
+  for (auto& e : c->prof.ev) hipEventDestroy(e);
+  if (c->d_tab64) {
+    hipStreamSynchronize(c->stream);
+    hipFree(c->d_tab64);
+    hipFree(c->d_tab32);
+  }
+  delete c;
+  return ADG_OK;
+}
+
+adg_status adg_sizes(adg_ctx c, size_t* n_dof, size_t* state_bytes, size_t* ring_bytes, size_t* scratch_bytes) {
+  if (!c) return fail(ADG_ERR_INVALID, "null context");
+  if (n_dof) *n_dof = c->ndof;
+  if (state_bytes) *state_bytes = c->ndof * sizeof(double);
+  if (ring_bytes) *ring_bytes = c->ring_bytes;
+  if (scratch_bytes) *scratch_bytes = c->scratch_bytes;
+  return ADG_OK;
+}
+
+adg_status adg_bind(adg_ctx c, void* u_n, void* u_a, void* u_b, void* ring, void* scratch) {
+  if (!c) return fail(ADG_ERR_INVALID, "null context");
+  if (!u_n || !u_a || !u_b || !scratch) return fail(ADG_ERR_INVALID, "state registers and scratch are required");
+  if (c->ring_bytes && !ring) return fail(ADG_ERR_INVALID, "this asynchrony mode needs a ring buffer");
+  void* ptrs[5] = {u_n, u_a, u_b, ring, scratch};
+  for (void* p : ptrs)
+    if (reinterpret_cast<uintptr_t>(p) % 256) return fail(ADG_ERR_INVALID, "buffers must be 256-byte aligned");
+  if (u_n == u_a || u_n == u_b || u_a == u_b) return fail(ADG_ERR_INVALID, "state registers must be distinct");
+  c->u_n = static_cast<double*>(u_n);
+  c->u_a = static_cast<double*>(u_a);
+  c->u_b = static_cast<double*>(u_b);
+  c->ring = static_cast<double*>(ring);
+  c->ring_cap = ring ? c->ring_bytes : 0;
+  c->scratch = static_cast<char*>(scratch);
+  if (!c->d_tab64) {
+    const int nt = (int)c->tab64.size();
+    std::vector<float> t32(nt);
+    for (int i = 0; i < nt; ++i) t32[i] = (float)c->tab64[i];
+    HIP_TRY(hipMalloc(&c->d_tab64, sizeof(double) * nt));
+    HIP_TRY(hipMalloc(&c->d_tab32, sizeof(float) * nt));
+    HIP_TRY(hipMemcpyAsync(c->d_tab64, c->tab64.data(), sizeof(double) * nt, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->d_tab32, t32.data(), sizeof(float) * nt, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  c->mlp.base = c->scratch + c->mlp_off;
+  c->bound = true;
+  return mlp_on_bind(c);
+}
+
+adg_status adg_upload(adg_ctx c, const double* host, size_t n) {
+  if (!c || !host) return fail(ADG_ERR_INVALID, "null argument");
+  if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
+  if (n != c->ndof) return fail(ADG_ERR_INVALID, "size mismatch: expected " + std::to_string(c->ndof));
+  HIP_TRY(hipMemcpyAsync(c->u_n, host, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->n = 0;
+  c->hist_start = 0;
+  c->t = 0.0;
+  mlp_reset_stats(c);
+  return ADG_OK;
+}
+
+adg_status adg_download(adg_ctx c, double* host, size_t n) {
+  if (!c || !host) return fail(ADG_ERR_INVALID, "null argument");
+  if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
+  if (n != c->ndof) return fail(ADG_ERR_INVALID, "size mismatch: expected " + std::to_string(c->ndof));
+  HIP_TRY(hipMemcpyAsync(host, c->u_n, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return ADG_OK;
+}
+
+adg_status adg_init_problem(adg_ctx c, int32_t problem, const double* params) {
+  if (!c) return fail(ADG_ERR_INVALID, "null context");
+  if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
+  if (problem < 0 || problem > 2) return fail(ADG_ERR_INVALID, "unknown problem");
+  if (problem == ADG_VORTEX && c->D != 2) return fail(ADG_ERR_INVALID, "the vortex is a 2D problem");
+  Prm prm{};
+  const double def[3][5] = {{5, 5, 5, 1, 1}, {0.2, 1, 1, 1, 1}, {1, 0.3, -0.2, 0.1, 1}};
+  for (int i = 0; i < 5; ++i) prm.v[i] = params ? params[i] : def[problem][i];
+  HIP_TRY(launch_init(c->D, c->p, c->mesh, problem, prm, c->u_n, c->d_tab64, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->n = 0;
+  c->hist_start = 0;
+  c->t = 0.0;
+  mlp_reset_stats(c);
+  return ADG_OK;
+}
+
+adg_status adg_set_async(adg_ctx c, const adg_async* a) {
+  if (!c || !a) return fail(ADG_ERR_INVALID, "null argument");
+  adg_status s = check_async(c->cfg, *a);
+  if (s != ADG_OK) return s;
+  int R, Qh;
+  depth_of(*a, R, Qh);
+  const size_t need = (size_t)R * (size_t)c->mesh.nfs * c->V * c->Fn * sizeof(double);
+  if (c->bound && need > c->ring_cap)
+    return fail(ADG_ERR_INVALID, "ring bound at adg_bind is too small for this depth (" + std::to_string(need) +
+                                     " bytes needed)");
+  if (c->bound) HIP_TRY(hipStreamSynchronize(c->stream));
+  c->as = *a;
+  c->R = R;
+  c->Qh = Qh;
+  if (!c->bound) c->ring_bytes = need;
+  c->hist_start = c->n;
+  mlp_reset_stats(c);
+  return ADG_OK;
+}
+
+adg_status adg_step(adg_ctx c, int64_t n_steps, double dt) { return adg_step_impl(c, n_steps, dt, false); }
+
+adg_status adg_delay(adg_ctx c, int64_t n, int32_t sub, int32_t dir, int32_t* k, int64_t* n_face_sides) {
+  if (!c || !k) return fail(ADG_ERR_INVALID, "null argument");
+  if (sub < 0 || sub >= c->mesh.nsub || dir < 0 || dir >= 2 * c->D || n < c->hist_start)
+    return fail(ADG_ERR_INVALID, "subdomain, direction or step out of range");
+  const int64_t keep = c->n;
+  c->n = n;
+  Async A = make_async(c, 0);
+  c->n = keep;
+  *k = delay_of(c->mesh, A, sub, dir);
+  if (n_face_sides) *n_face_sides = c->mesh.nfs;
+  return ADG_OK;
+}
+
+adg_status adg_basis(adg_ctx c, double* gll_x, double* gll_w, double* gauss_x, double* gauss_w) {
+  if (!c) return fail(ADG_ERR_INVALID, "null context");
+  const TabOff to = tab_off(c->P, c->Q);
+  for (int j = 0; j < c->P; ++j) {
+    if (gll_x) gll_x[j] = c->tab64[to.XL + j];
+    if (gll_w) gll_w[j] = c->tab64[to.WL + j];
+  }
+  for (int q = 0; q < c->Q; ++q) {
+    if (gauss_x) gauss_x[q] = c->tab64[to.XQ + q];
+    if (gauss_w) gauss_w[q] = c->tab64[to.WQ + q];
+  }
+  return ADG_OK;
+}
+
+adg_status adg_profile(adg_ctx c, int32_t enable) {
+  if (!c) return fail(ADG_ERR_INVALID, "null context");
+  auto& P = c->prof;
+  if (enable) {
+    if (P.ev.empty()) {
+      P.ev.resize(2 * kProfPairs);
+      P.kind.resize(kProfPairs);
+      for (auto& e : P.ev) HIP_TRY(hipEventCreate(&e));
+    }
+    P.used = 0;
+    P.ms[0] = P.ms[1] = 0.0;
+    P.cnt[0] = P.cnt[1] = 0;
+    P.on = true;
+  } else {
+    adg_status s = prof_fold(c);
+    P.on = false;
+    if (s != ADG_OK) return s;
+  }
+  return ADG_OK;
+}
+
+adg_status adg_profile_read(adg_ctx c, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!c || (kernel != ADG_KERNEL_RHS && kernel != ADG_KERNEL_GHOST)) return fail(ADG_ERR_INVALID, "bad argument");
+  adg_status s = prof_fold(c);
+  if (s != ADG_OK) return s;
+  if (total_ms) *total_ms = c->prof.ms[kernel];
+  if (launches) *launches = c->prof.cnt[kernel];
+  return ADG_OK;
+}
+
+adg_status adg_time(adg_ctx c, int64_t* n, double* t) {
+  if (!c) return fail(ADG_ERR_INVALID, "null context");
+  if (n) *n = c->n;
+  if (t) *t = c->t;
+  return ADG_OK;
+}
+
+adg_status adg_stable_dt(adg_ctx c, double cfl, double* dt) {
+  if (!c || !dt) return fail(ADG_ERR_INVALID, "null argument");
+  if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
+  if (!(cfl > 0.0)) return fail(ADG_ERR_INVALID, "cfl must be > 0");
+  double smax = 0.0;
+  adg_status s = run_norms(c, 4, 0, nullptr, c->u_n, nullptr, 1, 1, &smax);
+  if (s != ADG_OK) return s;
+  if (!(smax > 0.0)) return fail(ADG_ERR_NONPHYSICAL, "no finite positive wave speed in the state");
+  double hmin = c->mesh.h[0];
+  for (int k = 1; k < c->D; ++k) hmin = std::min(hmin, c->mesh.h[k]);
+  *dt = cfl * hmin / (std::pow((double)c->p, 1.5) * smax);
+  return ADG_OK;
+}
+
+adg_status adg_error_norms(adg_ctx c, int32_t problem, const double* params, double out[3]) {
+  if (!c || !out) return fail(ADG_ERR_INVALID, "null argument");
+  if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
+  if (problem < 0 || problem > 2) return fail(ADG_ERR_INVALID, "unknown problem");
+  double r[3];
+  adg_status s = run_norms(c, 0, problem, params, c->u_n, nullptr, 3, 0, r);
+  if (s != ADG_OK) return s;
+  for (int i = 0; i < 3; ++i) out[i] = std::sqrt(r[i]);
+  return ADG_OK;
+}
+
+adg_status adg_diff_norm(adg_ctx c, const double* host_ref, double out[3]) {
+  if (!c || !host_ref || !out) return fail(ADG_ERR_INVALID, "null argument");
+  if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
+  // u_a is free between steps: stage the reference there
+  HIP_TRY(hipMemcpyAsync(c->u_a, host_ref, c->ndof * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  double r[6];
+  adg_status s = run_norms(c, 2, 0, nullptr, c->u_n, c->u_a, 6, 0, r);
+  if (s != ADG_OK) return s;
+  for (int g = 0; g < 3; ++g) out[g] = r[3 + g] > 0 ? std::sqrt(r[g] / r[3 + g]) : std::sqrt(r[g]);
+  return ADG_OK;
+}
+
+adg_status adg_integrals(adg_ctx c, double* out) {
+  if (!c || !out) return fail(ADG_ERR_INVALID, "null argument");
+  if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
+  return run_norms(c, 1, 0, nullptr, c->u_n, nullptr, c->V, 0, out);
+}
+
+// checkpoint blob: header, u_n, ring, predictor weights
+struct BlobHeader {
+  char magic[8];
+  int32_t version, dim, degree, V;
+  int64_t ndof, ring_bytes, nparams;
+  int64_t n, hist_start;
+  double t;
+  int32_t ghost, delay_kind, L, levels;
+  uint64_t seed;
+};
+
+adg_status adg_save(adg_ctx c, void* host_blob, size_t* bytes) {
+  if (!c || !bytes) return fail(ADG_ERR_INVALID, "null argument");
+  const size_t np = (size_t)mlp_nparams(c->V);
+  const size_t need = sizeof(BlobHeader) + c->ndof * sizeof(double) + c->ring_bytes + np * sizeof(float);
+  if (!host_blob) {
+    *bytes = need;
+    return ADG_OK;
+  }
+  if (*bytes < need) return fail(ADG_ERR_INVALID, "blob too small");
+  if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
+  BlobHeader h{};
+  std::memcpy(h.magic, "ADGCKPT", 8);
+  h.version = 1;
+  h.dim = c->D;
+  h.degree = c->p;
+  h.V = c->V;
+  h.ndof = (int64_t)c->ndof;
+  h.ring_bytes = (int64_t)c->ring_bytes;
+  h.nparams = (int64_t)np;
+  h.n = c->n;
+  h.hist_start = c->hist_start;
+  h.t = c->t;
+  h.ghost = c->as.ghost;
+  h.delay_kind = c->as.delay_kind;
+  h.L = c->as.L;
+  h.levels = c->as.levels;
+  h.seed = c->as.seed;
+  char* b = static_cast<char*>(host_blob);
+  std::memcpy(b, &h, sizeof(h));
+  b += sizeof(h);
+  HIP_TRY(hipMemcpyAsync(b, c->u_n, c->ndof * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  b += c->ndof * sizeof(double);
+  if (c->ring_bytes) HIP_TRY(hipMemcpyAsync(b, c->ring, c->ring_bytes, hipMemcpyDeviceToHost, c->stream));
+  b += c->ring_bytes;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  mlp_get_host(c, reinterpret_cast<float*>(b));
+  *bytes = need;
+  return ADG_OK;
+}
+
+adg_status adg_load(adg_ctx c, const void* host_blob, size_t bytes) {
+  if (!c || !host_blob) return fail(ADG_ERR_INVALID, "null argument");
+  if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
+  BlobHeader h;
+  if (bytes < sizeof(h)) return fail(ADG_ERR_INVALID, "blob too small");
+  std::memcpy(&h, host_blob, sizeof(h));
+  const size_t np = (size_t)mlp_nparams(c->V);
+  if (std::memcmp(h.magic, "ADGCKPT", 8) || h.version != 1 || h.dim != c->D || h.degree != c->p ||
+      h.ndof != (int64_t)c->ndof || h.ring_bytes != (int64_t)c->ring_bytes || h.nparams != (int64_t)np)
+    return fail(ADG_ERR_INVALID, "blob does not match this configuration");
+  if (bytes < sizeof(h) + c->ndof * sizeof(double) + c->ring_bytes + np * sizeof(float))
+    return fail(ADG_ERR_INVALID, "blob truncated");
+  adg_async a = c->as;
+  a.ghost = h.ghost;
+  a.delay_kind = h.delay_kind;
+  a.L = h.L;
+  a.levels = h.levels;
+  a.seed = h.seed;
+  adg_status s = adg_set_async(c, &a);
+  if (s != ADG_OK) return s;
+  const char* b = static_cast<const char*>(host_blob) + sizeof(h);
+  HIP_TRY(hipMemcpyAsync(c->u_n, b, c->ndof * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  b += c->ndof * sizeof(double);
+  if (c->ring_bytes) HIP_TRY(hipMemcpyAsync(c->ring, b, c->ring_bytes, hipMemcpyHostToDevice, c->stream));
+  b += c->ring_bytes;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  s = mlp_set_host(c, reinterpret_cast<const float*>(b));
+  if (s != ADG_OK) return s;
+  c->n = h.n;
+  c->hist_start = h.hist_start;
+  c->t = h.t;
+  return ADG_OK;
+}
+
+}  // extern "C"

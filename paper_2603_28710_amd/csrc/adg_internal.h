@@ -1,0 +1,189 @@
+// adg_internal.h — structures shared by the host runtime and the gfx950
+// kernels of the ADG right-hand side. Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace adg {
+
+constexpr int kMaxP = 5;   // nodes per direction (degree <= 4)
+constexpr int kMaxQ = 6;   // Gauss points per direction
+constexpr int kMaxV = 5;
+constexpr int kMlpK = 4;   // past levels read by the learned predictor
+constexpr int kMlpH = 64;  // hidden width
+constexpr int kThreads = 256;
+
+// Offsets into the per-context table (doubles; a float copy has the same
+// offsets). B: interpolation nodes->Gauss [Q][P]; BT: its transpose [P][Q];
+// DT: transposed collocation derivative on the Gauss points [Q][Q]
+// (DT[r][q] = l'_r(x_q) of the Gauss Lagrange basis); MI: inverse 1D mass
+// [P][P]; WQ: Gauss weights; XQ: Gauss points; XL/WL: GLL points/weights.
+struct TabOff {
+  int B, BT, DT, MI, WQ, XQ, XL, WL, total;
+};
+__host__ __device__ constexpr TabOff tab_off(int P, int Q) {
+  return TabOff{0,
+                Q * P,
+                2 * Q * P,
+                2 * Q * P + Q * Q,
+                2 * Q * P + Q * Q + P * P,
+                2 * Q * P + Q * Q + P * P + Q,
+                2 * Q * P + Q * Q + P * P + 2 * Q,
+                2 * Q * P + Q * Q + P * P + 2 * Q + P,
+                2 * Q * P + Q * Q + P * P + 2 * Q + 2 * P};
+}
+
+// Structured periodic box, block partition into virtual subdomains, and the
+// arithmetic enumeration of PE-boundary face-sides (a face-side is a pair
+// (receiving element, face) whose neighbour lies in another subdomain).
+// Face-sides are grouped by receiving subdomain, then by face direction f
+// (f = 2a + side; side 0 is the -a face), then lexicographically over the
+// subdomain-local coordinates of the two other axes (lowest axis fastest).
+struct Mesh {
+  int dim;
+  int nc[3];     // elements per direction (1 beyond dim)
+  int parts[3];  // subdomains per direction
+  int m[3];      // elements per subdomain per direction
+  int nsub;
+  int fs_off[6];  // offset of direction f inside a subdomain block, -1 if no PE faces
+  int fs_sub;     // face-sides per subdomain
+  long long nfs;  // total face-sides
+  long long E;
+  double h[3], lo[3], hi[3];
+  double detJ;       // prod h_k / 2
+  double detJf[3];   // face Jacobian for faces normal to axis a
+  double gamma;
+  int flux;
+};
+
+// Asynchrony parameters for one stage.
+struct Async {
+  int ghost, delay_kind, L, levels;
+  int Qh;   // history levels needed (warm-up)
+  int R;    // ring depth
+  unsigned long long seed;
+  long long n;       // absolute step index
+  long long n_rel;   // steps since the history restarted
+  int stage;
+  double c_m;        // stage time fraction
+  double tol;        // learned accept bound
+};
+
+// parameters of an analytic problem, passed by value
+struct Prm {
+  double v[5];
+};
+
+struct Stage {
+  double a, b, dt;  // out = a u_n + b (u_in + dt k)
+};
+
+// ---- device helpers shared by several kernels -------------------------------
+
+__host__ __device__ inline long long elem_index(const Mesh& M, int i, int j, int k) {
+  return (long long)i + (long long)M.nc[0] * ((long long)j + (long long)M.nc[1] * k);
+}
+
+__host__ __device__ inline void elem_coords(const Mesh& M, long long e, int* c) {
+  c[0] = (int)(e % M.nc[0]);
+  long long r = e / M.nc[0];
+  c[1] = (int)(r % M.nc[1]);
+  c[2] = (int)(r / M.nc[1]);
+}
+
+__host__ __device__ inline int subdomain_of(const Mesh& M, const int* c) {
+  return c[0] / M.m[0] + M.parts[0] * (c[1] / M.m[1] + M.parts[1] * (c[2] / M.m[2]));
+}
+
+// neighbour of element coords c across face f (periodic)
+__host__ __device__ inline long long neighbour(const Mesh& M, const int* c, int f) {
+  int d[3] = {c[0], c[1], c[2]};
+  int a = f >> 1;
+  d[a] += (f & 1) ? 1 : -1;
+  if (d[a] < 0) d[a] += M.nc[a];
+  if (d[a] >= M.nc[a]) d[a] -= M.nc[a];
+  return elem_index(M, d[0], d[1], d[2]);
+}
+
+// face-side index of (element coords c, face f), or -1 if not a PE face
+__host__ __device__ inline long long face_side(const Mesh& M, const int* c, int f) {
+  int a = f >> 1;
+  if (M.parts[a] < 2) return -1;
+  int l = c[a] % M.m[a];
+  if ((f & 1) ? (l != M.m[a] - 1) : (l != 0)) return -1;
+  int o0 = a == 0 ? 1 : 0;
+  int o1 = a == 2 ? 1 : 2;
+  long long li = c[o0] % M.m[o0];
+  if (M.dim == 3) li += (long long)M.m[o0] * (c[o1] % M.m[o1]);
+  return (long long)subdomain_of(M, c) * M.fs_sub + M.fs_off[f] + li;
+}
+
+// inverse of face_side: receiving element coords and face
+__host__ __device__ inline void face_side_decode(const Mesh& M, long long fs, int* c, int* f_out) {
+  int s = (int)(fs / M.fs_sub);
+  int r = (int)(fs - (long long)s * M.fs_sub);
+  int f = 0;
+  for (int g = 0; g < 2 * M.dim; ++g)
+    if (M.fs_off[g] >= 0 && r >= M.fs_off[g]) f = g;
+  int li = r - M.fs_off[f];
+  int a = f >> 1;
+  int o0 = a == 0 ? 1 : 0;
+  int o1 = a == 2 ? 1 : 2;
+  int sc[3] = {s % M.parts[0], (s / M.parts[0]) % M.parts[1], s / (M.parts[0] * M.parts[1])};
+  int l[3] = {0, 0, 0};
+  l[o0] = li % M.m[o0];
+  if (M.dim == 3) l[o1] = li / M.m[o0];
+  l[a] = (f & 1) ? M.m[a] - 1 : 0;
+  for (int k = 0; k < 3; ++k) c[k] = sc[k] * M.m[k] + l[k];
+  *f_out = f;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): draw number `idx` of the stream with
+// state `seed`, i.e. the output finaliser applied to seed + (idx+1)*gamma.
+__host__ __device__ inline unsigned long long splitmix64(unsigned long long seed, unsigned long long idx) {
+  unsigned long long z = seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// delay k for (step, receiving subdomain, face direction) after the warm-up
+// clamp that keeps every level read at or after the history origin
+__host__ __device__ inline int delay_of(const Mesh& M, const Async& A, int sub, int f) {
+  if (A.ghost == 0) return 0;
+  if (A.n_rel < A.Qh - 1) return 0;
+  long long k;
+  if (A.delay_kind == 0) {
+    k = A.L;
+  } else if (A.delay_kind == 1) {
+    unsigned long long idx =
+        ((unsigned long long)A.n * (unsigned long long)M.nsub + (unsigned long long)sub) * (2ull * M.dim) +
+        (unsigned long long)f;
+    k = (long long)(splitmix64(A.seed, idx) % (unsigned long long)(A.L + 1));
+  } else if (A.ghost == 1) {
+    k = A.L > 0 ? A.n % A.L : 0;  // Alg. caa-std
+  } else {
+    long long per = A.L + A.Qh, r = A.n % per;  // Alg. caa-at
+    k = r < A.Qh ? 0 : r - A.Qh + 1;
+  }
+  long long cap = A.n_rel - A.Qh + 1;
+  return (int)(k < cap ? k : cap);
+}
+
+// ---- launchers (defined in the .hip files) ---------------------------------
+
+hipError_t launch_rhs_stage(int dim, int degree, int precision, const Mesh& M, const Async& A, const Stage& S,
+                            const double* u_in, const double* u_n, double* out, const double* ghost,
+                            const double* tab64, const float* tab32, hipStream_t st);
+hipError_t launch_ghost(int dim, int degree, const Mesh& M, const Async& A, const double* u_in, const double* u_n,
+                        double* ring, double* ghost, const float* mlp, int publish, double* stats,
+                        hipStream_t st);
+hipError_t launch_init(int dim, int degree, const Mesh& M, int problem, const Prm& prm, double* u,
+                       const double* tab64, hipStream_t st);
+hipError_t launch_norms(int dim, int degree, const Mesh& M, int what, int problem, const Prm& prm, double t,
+                        const double* u, const double* ref, const double* tab64, double* partial, int nblk,
+                        hipStream_t st);
+hipError_t launch_reduce(const double* partial, int nblk, int ncomp, int op, double* out, hipStream_t st);
+int norms_blocks(long long E);
+
+}  // namespace adg

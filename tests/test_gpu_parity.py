@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs. Tolerance for FP64: relative L2 per variable group
+(density, momentum, energy) <= 1e-11 after the stated steps; bit-exact for
+the integer schedule (tested on the CPU in test_host_abi.py).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from tests import inputs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2603_28710_amd.solver import Solver
+    return Solver
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2603_28710_amd import binding
+    return binding
+
+
+def rel_l2(a, b, dim, p=None, s=None):
+    """max over the groups (density, momentum, energy) of ||a-b|| / ||b||,
+    nodal values of the public layout [E][V][P^d]"""
+    V = dim + 2
+    Pd = (s.P ** dim) if s is not None else (p + 1) ** dim
+    a = a.reshape(-1, V, Pd)
+    b = b.reshape(-1, V, Pd)
+    out = []
+    for sl in (slice(0, 1), slice(1, V - 1), slice(V - 1, V)):
+        num = np.linalg.norm(a[:, sl] - b[:, sl])
+        den = np.linalg.norm(b[:, sl])
+        out.append(num / den if den > 0 else num)
+    return max(out)
+
+
+def _pair(O, S, problem=None, perturb=0.0, seed=0, **cfg):
+    """oracle and GPU solver on the same configuration and initial state"""
+    O_ = O
+    problem = O_.VORTEX if problem is None else problem
+    ocfg = dict(cfg)
+    gcfg = dict(cfg)
+    gcfg["degree"] = gcfg.pop("p")
+    o = O_.Oracle(**ocfg)
+    o.init_problem(problem)
+    if perturb:
+        o.set_state(o.state() + inputs.perturbation(o.ndof, seed, perturb))
+    s = S(**gcfg)
+    s.upload(o.state())
+    return o, s
+
+
+# ------------------------------------------------------------------ sync
+
+def test_vortex_16x16_p2_sync_100_steps(oracle_mod, S):
+    O = oracle_mod
+    cfg = dict(dim=2, p=2, cells=(16, 16, 1), hi=(10, 10, 1))
+    say("case: vortex 16x16 p=2 sync, projection + 100 steps")
+    o = O.Oracle(**cfg)
+    o.init_problem(O.VORTEX)
+    s = S(dim=2, degree=2, cells=(16, 16, 1), hi=(10, 10, 1))
+    s.init_problem(O.VORTEX)
+    assert rel_l2(s.download(), o.state(), 2, s=s) < 1e-13
+    dt = o.stable_dt(0.1)
+    assert abs(s.stable_dt(0.1) - dt) <= 1e-14 * dt
+    s.upload(o.state())
+    assert o.step(100, dt) == 0
+    s.step(100, dt)
+    r = rel_l2(s.download(), o.state(), 2, s=s)
+    say("  rel L2", r)
+    assert r <= TOL
+    np.testing.assert_allclose(s.error_norms(O.VORTEX), o.error_norms(O.VORTEX, 100 * dt), rtol=1e-9)
+    assert s.time()[0] == 100
+
+
+@pytest.mark.parametrize("dim,p,cells", [
+    (2, 1, (13, 11, 1)), (2, 2, (13, 11, 1)), (2, 3, (13, 11, 1)), (2, 4, (13, 11, 1)),
+    (3, 1, (5, 4, 3)), (3, 2, (5, 4, 3)), (3, 3, (5, 4, 3)), (3, 4, (3, 3, 2)),
+])
+def test_sync_every_degree_ragged_tiles(oracle_mod, S, dim, p, cells):
+    O = oracle_mod
+    say(f"case: density wave dim={dim} p={p} cells={cells} sync, perturbed, 10 steps")
+    o, s = _pair(O, S, problem=O.DENSITY_WAVE, perturb=1e-3, seed=p, dim=dim, p=p, cells=cells,
+                 hi=(1, 1, 1))
+    dt = 0.5 * o.stable_dt(0.1)
+    o.step(10, dt)
+    s.step(10, dt)
+    r = rel_l2(s.download(), o.state(), dim, s=s)
+    say("  rel L2", r)
+    assert r <= TOL
+
+
+@pytest.mark.parametrize("flux", [0, 1])
+def test_single_rhs_stage_matches_oracle_elements(oracle_mod, S, flux):
+    # stage 0 output (u_a register) against the oracle's per-element stage
+    O = oracle_mod
+    say(f"case: one stage, flux={flux}")
+    o, s = _pair(O, S, perturb=1e-2, seed=3, dim=2, p=3, cells=(12, 10, 1), parts=(3, 2, 1),
+                 hi=(10, 10, 1), flux=flux)
+    u0 = o.state()
+    dt = o.stable_dt(0.1)
+    s.step(1, dt)
+    ua = s.u[1].cpu().numpy()
+    ref = o.stage_elements(0, dt, u0, u0, np.arange(o.E))
+    assert rel_l2(ua, ref, 2, s=s) <= 1e-13
+
+
+# ----------------------------------------------------------------- async
+
+ASYNC_MODES = [
+    ("stale_fixed2", 1, 0, 2, 1), ("stale_uniform3", 1, 1, 3, 1), ("stale_caa4", 1, 2, 4, 1),
+    ("at3_fixed1", 2, 0, 1, 3), ("at3_uniform3", 2, 1, 3, 3), ("at3_caa3", 2, 2, 3, 3),
+    ("at2_uniform2", 2, 1, 2, 2), ("at4_uniform2", 2, 1, 2, 4),
+]
+
+
+@pytest.mark.parametrize("name,ghost,kind,L,levels", ASYNC_MODES)
+def test_async_modes_vortex_2d(oracle_mod, S, name, ghost, kind, L, levels):
+    O = oracle_mod
+    say(f"case: vortex 2D p=3 36x20 parts 4x2 {name}, 30 steps")
+    o, s = _pair(O, S, dim=2, p=3, cells=(36, 20, 1), parts=(4, 2, 1), hi=(10, 10, 1), ghost=ghost,
+                 delay_kind=kind, L=L, levels=levels, seed=7)
+    dt = 0.5 * o.stable_dt(0.1)
+    o.step(30, dt)
+    s.step(30, dt)
+    r = rel_l2(s.download(), o.state(), 2, s=s)
+    say("  rel L2", r)
+    assert r <= TOL
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_async_at_uniform_3d(oracle_mod, S, seed):
+    O = oracle_mod
+    say(f"case: density wave 3D p=2 8^3 parts 2^3 AT uniform L=2 seed={seed}, 12 steps")
+    o, s = _pair(O, S, problem=O.DENSITY_WAVE, dim=3, p=2, cells=(8, 8, 8), parts=(2, 2, 2), hi=(1, 1, 1),
+                 ghost=2, delay_kind=1, L=2, levels=3, seed=seed)
+    dt = o.stable_dt(0.1)
+    o.step(12, dt)
+    s.step(12, dt)
+    r = rel_l2(s.download(), o.state(), 3, s=s)
+    say("  rel L2", r)
+    assert r <= TOL
+
+
+def test_zero_delay_bitwise_equals_sync(oracle_mod, S):
+    O = oracle_mod
+    say("case: AT with L=0 vs sync, bitwise")
+    base = dict(dim=2, degree=3, cells=(32, 32, 1), parts=(4, 4, 1), hi=(10, 10, 1))
+    a = S(**base)
+    a.init_problem(O.VORTEX)
+    b = S(ghost=2, delay_kind=0, L=0, levels=3, **base)
+    b.init_problem(O.VORTEX)
+    dt = a.stable_dt(0.1)
+    a.step(20, dt)
+    b.step(20, dt)
+    np.testing.assert_array_equal(a.download(), b.download())
+
+
+def test_deterministic_repeat(oracle_mod, S):
+    O = oracle_mod
+    say("case: two AT uniform runs, bitwise")
+    cfg = dict(dim=2, degree=3, cells=(64, 64, 1), parts=(8, 8, 1), hi=(10, 10, 1), ghost=2, delay_kind=1,
+               L=3, levels=3, seed=1)
+    outs = []
+    for _ in range(2):
+        s = S(**cfg)
+        s.init_problem(O.VORTEX)
+        s.step(25, 0.002)
+        outs.append(s.download())
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
+def test_checkpoint_resume_bitwise(oracle_mod, S):
+    O = oracle_mod
+    say("case: save after 7 steps, resume, bitwise")
+    cfg = dict(dim=2, degree=2, cells=(24, 24, 1), parts=(4, 4, 1), hi=(10, 10, 1), ghost=2, delay_kind=1,
+               L=3, levels=3, seed=4)
+    s = S(**cfg)
+    s.init_problem(O.VORTEX)
+    s.step(7, 0.003)
+    blob = s.save()
+    s.step(9, 0.003)
+    a = s.download()
+    t = S(**cfg)
+    t.load(blob)
+    assert t.time()[0] == 7
+    t.step(9, 0.003)
+    np.testing.assert_array_equal(t.download(), a)
+
+
+@pytest.mark.parametrize("ghost,kind,L", [(0, 0, 0), (1, 1, 3), (2, 1, 3), (2, 2, 2)])
+def test_free_stream_every_mode(oracle_mod, S, ghost, kind, L):
+    O = oracle_mod
+    say(f"case: free stream 3D ghost={ghost} kind={kind}")
+    s = S(dim=3, degree=3, cells=(8, 8, 8), parts=(2, 2, 2), hi=(1, 1, 1), ghost=ghost, delay_kind=kind, L=L,
+          levels=3)
+    s.init_problem(O.CONSTANT)
+    u0 = s.download()
+    s.step(10, 1e-3)
+    np.testing.assert_allclose(s.download(), u0, rtol=0, atol=1e-13)
+
+
+def test_sync_conservation(oracle_mod, S):
+    O = oracle_mod
+    say("case: sync conservation 2D p=3 with subdomains")
+    s = S(dim=2, degree=3, cells=(32, 32, 1), parts=(4, 4, 1), hi=(10, 10, 1))
+    s.init_problem(O.VORTEX)
+    I0 = np.array(s.integrals())
+    s.step(50, s.stable_dt(0.1))
+    I1 = np.array(s.integrals())
+    assert np.all(np.abs(I1 - I0) <= 1e-13 * np.abs(I0).max())
+
+
+def test_nonfinite_state_reported(oracle_mod, S, B):
+    O = oracle_mod
+    say("case: NaN in the state is reported by the periodic check")
+    s = S(dim=2, degree=2, cells=(8, 8, 1), hi=(10, 10, 1), check_every=1)
+    s.init_problem(O.VORTEX)
+    u = s.download()
+    u[5] = np.nan
+    s.upload(u)
+    assert s.step_status(1, 1e-3) == B.ADG_ERR_NONFINITE
+    s2 = S(dim=2, degree=2, cells=(8, 8, 1), hi=(10, 10, 1), check_every=1)
+    s2.init_problem(O.VORTEX)
+    u = s2.download()
+    u[0:9] = -1.0  # negative density at every node of element 0
+    s2.upload(u)
+    assert s2.step_status(1, 1e-5) in (B.ADG_ERR_NONPHYSICAL, B.ADG_ERR_NONFINITE)

@@ -1,0 +1,187 @@
+"""The learned ghost-trace predictor on the GPU, through the C ABI.
+
+- FP32 training gradients against the oracle's FP64 backward on seeded pairs
+  (relative <= 1e-4 of the largest component).
+- BF16 matrix-core inference against the oracle's forward in the kernel's
+  precision (bf16 operands) and against the exact FP64 forward.
+- The LEARNED ghost mode with fixed weights against the oracle running the
+  same weights (relative L2 <= 1e-11), and the AT fallback invariant.
+- Training on solver-generated traces and what it gains over plain AT.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from tests import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _solver(**kw):
+    from paper_2603_28710_amd.solver import Solver
+    return Solver(**kw)
+
+
+def _pairs(n, V, seed, scale=1.0):
+    nin = 2 * V + 2
+    x, y = inputs.mlp_batch(n, nin, V, seed)
+    rec = np.zeros((n, nin + V + 1), dtype=np.float32)
+    rec[:, :nin] = x * scale
+    rec[:, nin:nin + V] = y
+    rec[:, nin + V] = 1.0
+    return rec
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gradient_matches_oracle(oracle_mod, dim):
+    O = oracle_mod
+    V = dim + 2
+    nin, nh = 2 * V + 2, 64
+    say(f"case: predictor gradient dim={dim}")
+    s = _solver(dim=dim, degree=2, cells=(4, 4, 4 if dim == 3 else 1), parts=(2, 2, 2 if dim == 3 else 1),
+                hi=(1, 1, 1), ghost=3, delay_kind=1, L=2)
+    npar = s.predictor_nparams()
+    assert npar == O.mlp_nparams(nin, nh, V)
+    w = inputs.mlp_weights(npar, 5, 0.2).astype(np.float32)
+    s.predictor_set(w)
+    s.predictor_bind(3000)
+    rec = _pairs(3000, V, 9)
+    s.predictor_load_pairs(rec)
+    loss, g = s.predictor_grad(100, 2500)
+    lo, go = O.mlp_loss_grad(w.astype(np.float64), nin, nh, V, rec[100:2600, :nin].astype(np.float64),
+                             rec[100:2600, nin:nin + V].astype(np.float64))
+    say("  loss", loss, lo, "max |dg|", np.abs(g - go).max(), "max |g|", np.abs(go).max())
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
+    assert np.abs(g - go).max() <= 1e-4 * np.abs(go).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_bf16_inference_matches_oracle(oracle_mod, dim):
+    O = oracle_mod
+    V = dim + 2
+    nin, nh = 2 * V + 2, 64
+    say(f"case: predictor bf16 inference dim={dim}")
+    s = _solver(dim=dim, degree=2, cells=(4, 4, 4 if dim == 3 else 1), parts=(2, 2, 2 if dim == 3 else 1),
+                hi=(1, 1, 1), ghost=3, delay_kind=1, L=2)
+    w = inputs.mlp_weights(s.predictor_nparams(), 6, 0.3).astype(np.float32)
+    s.predictor_set(w)
+    s.predictor_bind(4096)
+    rec = _pairs(4096, V, 10)
+    s.predictor_load_pairs(rec)
+    y = s.predictor_infer(0, 4000).astype(np.float64)
+    x = rec[:4000, :nin].astype(np.float64)
+    yb = O.mlp_forward_bf16(w, nin, nh, V, x)
+    yf = O.mlp_forward(w.astype(np.float64), nin, nh, V, x)
+    eb = np.abs(y - yb).max() / np.abs(yb).max()
+    ef = np.linalg.norm(y - yf) / np.linalg.norm(yf)
+    say("  vs bf16 emulation", eb, " vs fp64", ef)
+    assert eb <= 2e-2 and np.median(np.abs(y - yb)) <= 1e-4 * np.abs(yb).max()
+    assert ef <= 2e-2
+
+
+def test_learned_mode_parity_with_oracle(oracle_mod):
+    O = oracle_mod
+    say("case: learned ghosts with fixed weights vs oracle, 3D p=2 8^3 parts 2^3, 14 steps")
+    cfg = dict(dim=3, cells=(8, 8, 8), parts=(2, 2, 2), hi=(1, 1, 1), ghost=3, delay_kind=1, L=3, levels=3, seed=2,
+               learned_tol=1e-6)
+    o = O.Oracle(p=2, **cfg)
+    o.init_problem(O.DENSITY_WAVE)
+    s = _solver(degree=2, **cfg)
+    w = inputs.mlp_weights(s.predictor_nparams(), 7, 0.2).astype(np.float32)
+    s.predictor_set(w)
+    o.set_predictor(w)
+    s.upload(o.state())
+    dt = o.stable_dt(0.1)
+    o.step(14, dt)
+    s.step(14, dt)
+    a, b = s.download(), o.state()
+    r = np.linalg.norm(a - b) / np.linalg.norm(b)
+    acc_o, rej_o = o.learned_stats()
+    rate, judged = s.predictor_stats()
+    say("  rel L2", r, "gpu accept", rate, judged, "oracle", acc_o, rej_o)
+    assert r <= 1e-11
+    assert judged == acc_o + rej_o and abs(rate * judged - acc_o) <= max(1, 1e-3 * judged)
+
+
+def test_learned_fallback_rejects_bad_net_equals_at(oracle_mod):
+    O = oracle_mod
+    say("case: learned mode with an output far above the bound falls back to AT everywhere")
+    cfg = dict(dim=2, degree=3, cells=(32, 32, 1), parts=(4, 4, 1), hi=(10, 10, 1), delay_kind=1, L=3, levels=3,
+               seed=3)
+    s = _solver(ghost=3, learned_tol=1e-6, **cfg)
+    w = np.zeros(s.predictor_nparams(), dtype=np.float32)
+    w[-4:] = 1e20  # output bias: corrections of S3 * 1e20
+    s.predictor_set(w)
+    s.init_problem(O.VORTEX)
+    o = O.Oracle(p=3, ghost=3, learned_tol=1e-6, **{k: v for k, v in cfg.items() if k != "degree"})
+    o.init_problem(O.VORTEX)
+    o.set_predictor(w)
+    s.upload(o.state())
+    dt = o.stable_dt(0.1)
+    s.step(12, dt)
+    o.step(12, dt)
+    rate, judged = s.predictor_stats()
+    assert judged > 0 and rate == 0.0
+    a, b = s.download(), o.state()
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 1e-11
+
+
+def test_train_on_solver_traces_beats_at(oracle_mod):
+    """Collect (features, live-minus-AT) pairs from the solver, train on the
+    GPU, then measure on fresh pairs how much of AT's trace error remains,
+    and compare final states against the synchronous run."""
+    O = oracle_mod
+    say("case: collect / train / evaluate, 3D density wave 16^3 p=2, parts 4^3, L=4")
+    cfg = dict(dim=3, degree=2, cells=(16, 16, 16), parts=(4, 4, 4), hi=(1, 1, 1), delay_kind=1, L=4, levels=3,
+               seed=0)
+    s = _solver(ghost=3, **cfg)
+    s.init_problem(O.DENSITY_WAVE)
+    dt = s.stable_dt(0.1)
+    s.predictor_bind(700_000)
+    n = s.predictor_collect(60, dt)
+    say("  pairs", n)
+    assert n > 100_000
+    loss = s.predictor_train(epochs=6, batch=1024, lr=2e-3, seed=1)
+    say("  final loss", loss)
+    # held-out pairs from later steps: the trained net should remove most of
+    # AT's (scaled) trace error
+    w = s.predictor_get()
+    t = _solver(ghost=3, **cfg)
+    t.init_problem(O.DENSITY_WAVE)
+    t.step(60, dt)
+    t.predictor_bind(200_000)
+    m = t.predictor_collect(10, dt)
+    t.predictor_set(w)
+    pairs = t.pairs.cpu().numpy()
+    V, nin = 5, 12
+    off = (-t.pairs.data_ptr()) % 256
+    rec = np.frombuffer(pairs.tobytes()[off:off + m * (nin + V + 1) * 4], dtype=np.float32).reshape(m, nin + V + 1)
+    keep = np.nonzero(rec[:, nin + V] > 0)[0][:4096]
+    assert len(keep) > 1000
+    first = int(keep[0])
+    cnt = int(min(4096, keep[-1] - first + 1))
+    y = t.predictor_infer(first, cnt)
+    tgt = rec[first:first + cnt, nin:nin + V]
+    wgt = rec[first:first + cnt, nin + V:nin + V + 1]
+    resid = float(np.sum(wgt * (y - tgt) ** 2) / np.sum(wgt * tgt ** 2))
+    say("  remaining fraction of AT's squared trace error", resid)
+    assert resid < 0.25
+    # final state against the synchronous run: learned closer than AT
+    runs = {}
+    for ghost in (0, 2, 3):
+        r = _solver(ghost=ghost, **cfg)
+        if ghost == 3:
+            r.predictor_set(w)
+        r.init_problem(O.DENSITY_WAVE)
+        r.step(80, dt)
+        runs[ghost] = r.download()
+    d_at = np.linalg.norm(runs[2] - runs[0])
+    d_le = np.linalg.norm(runs[3] - runs[0])
+    say("  ||AT - sync||", d_at, " ||learned - sync||", d_le)
+    assert d_le < d_at

@@ -1,0 +1,118 @@
+"""CPU tests of the C-ABI library: it loads, exports every entry point that
+include/adg.h declares, validates configurations, sizes its buffers, and
+computes the same delay schedule and PE face-side count as the oracle
+(integer results, compared exactly). No compute call is made here.
+"""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2603_28710_amd import binding
+    return binding
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "adg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(adg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(B):
+    names = _declared()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(B.lib, n), n
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(dim=4), "dim"),
+    (dict(degree=0), "degree"),
+    (dict(degree=5), "degree"),
+    (dict(n_q=7, degree=2), "n_q"),
+    (dict(cells=(10, 10, 1), parts=(3, 1, 1)), "divisible"),
+    (dict(gamma=1.0), "gamma"),
+    (dict(flux=7), "flux"),
+    (dict(precision=3), "precision"),
+    (dict(lo=(1, 0, 0), hi=(1, 1, 1)), "hi"),
+])
+def test_create_rejects_bad_config(B, kw, msg):
+    with pytest.raises(B.AdgError) as ei:
+        B.adg_create(B.make_config(**kw), B.make_async())
+    assert ei.value.code == B.ADG_ERR_INVALID and msg in str(ei.value)
+
+
+@pytest.mark.parametrize("kw", [dict(ghost=5), dict(delay_kind=4), dict(L=17), dict(levels=0),
+                                dict(levels=5), dict(ghost=1, delay_kind=2, L=0)])
+def test_create_rejects_bad_async(B, kw):
+    with pytest.raises(B.AdgError):
+        B.adg_create(B.make_config(), B.make_async(**kw))
+
+
+def test_unbound_calls_fail_cleanly(B):
+    h = B.adg_create(B.make_config(), B.make_async())
+    assert B.adg_step(h, 1, 1e-3) == B.ADG_ERR_UNBOUND
+    with pytest.raises(B.AdgError):
+        B.adg_stable_dt(h, 0.1)
+    B.adg_destroy(h)
+
+
+@pytest.mark.parametrize("dim,p,cells,parts,ghost,L,levels,R", [
+    (2, 3, (256, 256, 1), (8, 8, 1), 2, 3, 3, 6),
+    (2, 2, (16, 16, 1), (1, 1, 1), 0, 0, 3, 0),
+    (3, 3, (16, 16, 16), (4, 4, 4), 2, 2, 3, 5),
+    (3, 2, (16, 16, 16), (2, 4, 8), 3, 4, 3, 8),
+    (2, 4, (12, 8, 1), (3, 1, 1), 1, 2, 1, 3),
+])
+def test_sizes_match_oracle_face_sides(B, oracle_mod, dim, p, cells, parts, ghost, L, levels, R):
+    h = B.adg_create(B.make_config(dim=dim, degree=p, cells=cells, parts=parts, hi=(1, 1, 1)),
+                     B.make_async(ghost=ghost, delay_kind=0, L=L, levels=levels))
+    ndof, sb, rb, scb = B.adg_sizes(h)
+    o = oracle_mod.Oracle(dim=dim, p=p, cells=cells, parts=parts, hi=(1, 1, 1))
+    assert ndof == o.ndof and sb == 8 * ndof
+    nfs = o.n_face_sides()
+    _, nfs_lib = B.adg_delay(h, 0, 0, 0)
+    assert nfs_lib == nfs
+    V, Fn = dim + 2, (p + 1) ** (dim - 1)
+    assert rb == R * nfs * V * Fn * 8
+    assert scb >= nfs * V * Fn * 8
+    B.adg_destroy(h)
+
+
+@pytest.mark.parametrize("ghost,kind,L,levels", [
+    (1, 0, 3, 1), (1, 1, 3, 1), (1, 2, 4, 1), (2, 0, 2, 3), (2, 1, 3, 3), (2, 2, 4, 3), (2, 2, 10, 3),
+    (2, 1, 2, 2), (3, 1, 4, 3), (3, 2, 3, 3),
+])
+def test_delay_schedule_identical_to_oracle(B, oracle_mod, ghost, kind, L, levels):
+    O = oracle_mod
+    cfg = dict(dim=3, cells=(8, 8, 8), parts=(2, 4, 2))
+    h = B.adg_create(B.make_config(degree=1, hi=(1, 1, 1), **cfg),
+                     B.make_async(ghost=ghost, delay_kind=kind, L=L, levels=levels, seed=12345))
+    o = O.Oracle(p=1, hi=(1, 1, 1), ghost=ghost, delay_kind=kind, L=L, levels=levels, seed=12345, **cfg)
+    for n in range(0, 60):
+        for s in range(16):
+            for d in range(6):
+                assert B.adg_delay(h, n, s, d)[0] == o.delay(n, s, d)
+    B.adg_destroy(h)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_library_rules_match_closed_forms_and_oracle(B, oracle_mod, p):
+    import math
+    import numpy as np
+    h = B.adg_create(B.make_config(degree=p), B.make_async())
+    xl, wl, xg, wg = B.adg_basis(h, p + 1, p + 2)
+    closed = {1: [-1, 1], 2: [-1, 0, 1], 3: [-1, -1 / math.sqrt(5), 1 / math.sqrt(5), 1],
+              4: [-1, -math.sqrt(3 / 7), 0, math.sqrt(3 / 7), 1]}
+    np.testing.assert_allclose(xl, closed[p], atol=1e-15)
+    ox, ow = oracle_mod.gll(p + 1)
+    np.testing.assert_allclose(wl, ow, atol=1e-15)
+    gx, gw = oracle_mod.gauss(p + 2)
+    np.testing.assert_allclose(xg, gx, atol=1e-15)
+    np.testing.assert_allclose(wg, gw, atol=1e-15)
+    B.adg_destroy(h)
