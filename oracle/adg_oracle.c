@@ -645,29 +645,32 @@ static float to_bf16(float x) {
 
 /* features of one face node from K levels T[j][v] (j = 0 newest), the
  * fractional delay tau and the stage time c_m (reading): the second and third
- * backward differences, both divided by S2 = max over the variables of the
- * second difference, then tau/4 and c_m. The second difference carries the
- * part of the live stage value an RK stage adds beyond the extrapolated
- * trajectory, the third the extrapolation error itself; S2 (returned) scales
- * the output back to physical units. */
-void orc_learned_features(void* vs, const double* T, double tau, double cm, double* x, double* S2) {
+ * backward differences, both divided by S = S2 + S3 (the largest magnitudes
+ * over the variables of the second and of the third difference), then tau/4
+ * and c_m. The second difference carries the part of the live stage value an
+ * RK stage adds beyond the extrapolated trajectory, the third the
+ * extrapolation error itself; S2 alone vanishes where the history has an
+ * inflection, S2 + S3 does not for a smooth history. S (returned) scales the
+ * output back to physical units. */
+void orc_learned_features(void* vs, const double* T, double tau, double cm, double* x, double* Sout) {
   orc_solver* s = (orc_solver*)vs;
   int V = s->V;
-  double d2[MAXV], d3[MAXV], S = 0.0;
+  double d2[MAXV], d3[MAXV], S2 = 0.0, S3 = 0.0;
   for (int v = 0; v < V; ++v) {
     double t0 = T[0 * V + v], t1 = T[1 * V + v], t2 = T[2 * V + v], t3 = T[3 * V + v];
     d2[v] = (t0 - 2.0 * t1) + t2;
     d3[v] = ((t0 - 3.0 * t1) + 3.0 * t2) - t3;
-    if (fabs(d2[v]) > S) S = fabs(d2[v]);
+    if (fabs(d2[v]) > S2) S2 = fabs(d2[v]);
+    if (fabs(d3[v]) > S3) S3 = fabs(d3[v]);
   }
-  S += 1e-300;
+  double S = (S2 + S3) + 1e-300;
   for (int v = 0; v < V; ++v) {
     x[v] = d2[v] / S;
     x[V + v] = d3[v] / S;
   }
   x[2 * V] = 0.25 * tau;
   x[2 * V + 1] = cm;
-  *S2 = S;
+  *Sout = S;
 }
 
 /* forward pass with inputs, weights and hidden activations rounded to bf16

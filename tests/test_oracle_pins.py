@@ -337,18 +337,18 @@ def test_adam_first_step_is_signed_lr(oracle_mod):
 def test_learned_features_are_backward_differences(oracle_mod):
     # T(s) = 1 + a2 s^2 + a3 s^3 sampled at s = 0, -1, -2, -3: the second
     # backward difference is 2 a2 - 6 a3, the third 6 a3 (finite differences
-    # of polynomials); features divide both by max |second difference|
+    # of polynomials); features divide both by max|second| + max|third|
     O = oracle_mod
     o = O.Oracle(dim=2, p=1, cells=(4, 4, 1), parts=(2, 2, 1), hi=(1, 1, 1), ghost=O.LEARNED,
                  delay_kind=O.FIXED, L=1)
     a2 = np.array([1.0, 0.0, -0.5, 3.0])
     a3 = np.array([0.5, -1.0, 2.0, 0.25])
     T = np.array([[1.0 + a2[v] * (-j) ** 2 + a3[v] * (-j) ** 3 for v in range(4)] for j in range(4)])
-    x, S2 = o.learned_features(T.ravel(), 2.5, 0.5)
+    x, S = o.learned_features(T.ravel(), 2.5, 0.5)
     d2, d3 = 2 * a2 - 6 * a3, 6 * a3
-    assert S2 == pytest.approx(np.abs(d2).max())
-    np.testing.assert_allclose(x[0:4], d2 / S2, rtol=1e-14)
-    np.testing.assert_allclose(x[4:8], d3 / S2, rtol=1e-14)
+    assert S == pytest.approx(np.abs(d2).max() + np.abs(d3).max())
+    np.testing.assert_allclose(x[0:4], d2 / S, rtol=1e-14)
+    np.testing.assert_allclose(x[4:8], d3 / S, rtol=1e-14)
     assert x[8] == 0.25 * 2.5 and x[9] == 0.5
 
 
