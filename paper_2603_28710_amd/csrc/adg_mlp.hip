@@ -4,9 +4,9 @@
 // neighbour traces T_0..T_3 (T_0 = level n-k) and the fractional delay
 // tau = k + c_m to a correction of the AT extrapolation (eq. at-flux) at that
 // node. Features: the second and third backward differences of the traces,
-// both divided by S2 = the largest |second difference| over the variables,
-// then tau/4 and the stage time c_m. The output times S2 is the correction
-// (it estimates the live stage value minus the AT trace). The trace
+// both divided by S = max|second| + max|third| over the variables, then
+// tau/4 and the stage time c_m. The output times S is the correction (it
+// estimates the live stage value minus the AT trace). The trace
 // used is AT + correction when every |correction| on the face is at most the
 // accept bound, and AT otherwise (AT stays the fallback and the judge).
 //
@@ -193,15 +193,16 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
         for (int v = 0; v < V; ++v) at[v] += wl * T[lv][v];
       }
       // second and third backward differences (no contraction: the features
-      // are bit-reproducible), both scaled by S2 = max |second difference|
-      double d2[V], d3[V], S = 0.0;
+      // are bit-reproducible), both scaled by S = max|second| + max|third|
+      double d2[V], d3[V], S2 = 0.0, S3s = 0.0;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         d2[v] = __dadd_rn(__dsub_rn(T[0][v], __dmul_rn(2.0, T[1][v])), T[2][v]);
         d3[v] = __dsub_rn(__dadd_rn(__dsub_rn(T[0][v], __dmul_rn(3.0, T[1][v])), __dmul_rn(3.0, T[2][v])), T[3][v]);
-        S = fabs(d2[v]) > S ? fabs(d2[v]) : S;
+        S2 = fabs(d2[v]) > S2 ? fabs(d2[v]) : S2;
+        S3s = fabs(d3[v]) > S3s ? fabs(d3[v]) : S3s;
       }
-      S += 1e-300;
+      const double S = __dadd_rn(__dadd_rn(S2, S3s), 1e-300);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         x[v] = (float)(d2[v] / S);

@@ -238,3 +238,32 @@ def test_nonfinite_state_reported(oracle_mod, S, B):
     u[0:9] = -1.0  # negative density at every node of element 0
     s2.upload(u)
     assert s2.step_status(1, 1e-5) in (B.ADG_ERR_NONPHYSICAL, B.ADG_ERR_NONFINITE)
+
+
+def test_fp32_contraction_within_1e6_of_fp64(oracle_mod, S):
+    # the mixed-precision workload at reduced size: vortex 128^2, degree 4,
+    # 8x8 subdomains, AT3 with uniform delays in {0..3}; FP32 contractions,
+    # FP64 state. Error against the FP64 path and the oracle every 50 steps.
+    O = oracle_mod
+    say("case: FP32 contractions vs FP64, vortex 128^2 p=4 AT3 uniform L=3, 100 steps")
+    cfg = dict(dim=2, cells=(128, 128, 1), parts=(8, 8, 1), hi=(10, 10, 1), ghost=2, delay_kind=1, L=3, levels=3,
+               seed=0)
+    o = O.Oracle(p=4, **cfg)
+    o.init_problem(O.VORTEX)
+    s64 = S(degree=4, precision=0, **cfg)
+    s32 = S(degree=4, precision=1, **cfg)
+    s64.upload(o.state())
+    s32.upload(o.state())
+    dt = o.stable_dt(0.1)
+    for chunk in range(2):
+        o.step(50, dt)
+        s64.step(50, dt)
+        s32.step(50, dt)
+        ref = o.state()
+        r64 = rel_l2(s64.download(), ref, 2, s=s64)
+        r32 = rel_l2(s32.download(), ref, 2, s=s32)
+        r3264 = rel_l2(s32.download(), s64.download(), 2, s=s32)
+        say(f"  after {50 * (chunk + 1)} steps: fp64 vs oracle {r64:.2e}, fp32 vs oracle {r32:.2e}, "
+            f"fp32 vs fp64 {r3264:.2e}")
+        assert r64 <= TOL
+        assert r32 <= 1e-6 and r3264 <= 1e-6
