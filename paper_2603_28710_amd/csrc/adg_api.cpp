@@ -463,6 +463,17 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
     T[to.XL + j] = xl[j];
     T[to.WL + j] = wl[j];
   }
+  // inverse mass folded into the transposed interpolation: BTM = MI * BT,
+  // and the inverse mass applied to the face traces: columns 0 and P-1 of MI
+  for (int i = 0; i < P; ++i) {
+    for (int q = 0; q < Q; ++q) {
+      double a = 0.0;
+      for (int j = 0; j < P; ++j) a += M1i[i * P + j] * T[to.BT + j * Q + q];
+      T[to.BTM + i * Q + q] = a;
+    }
+    T[to.MC + i] = M1i[i * P + 0];
+    T[to.MC + P + i] = M1i[i * P + (P - 1)];
+  }
   // buffer plan
   x->ring_bytes = (size_t)x->R * (size_t)M.nfs * x->V * x->Fn * sizeof(double);
   size_t s = 0;

@@ -17,9 +17,12 @@ constexpr int kThreads = 256;
 // offsets). B: interpolation nodes->Gauss [Q][P]; BT: its transpose [P][Q];
 // DT: transposed collocation derivative on the Gauss points [Q][Q]
 // (DT[r][q] = l'_r(x_q) of the Gauss Lagrange basis); MI: inverse 1D mass
-// [P][P]; WQ: Gauss weights; XQ: Gauss points; XL/WL: GLL points/weights.
+// [P][P]; WQ: Gauss weights; XQ: Gauss points; XL/WL: GLL points/weights;
+// BTM = MI * BT [P][Q] (test functions followed by the inverse mass);
+// MC: the first and last columns of MI, [2][P] (inverse mass applied to the
+// trace of a face at -1 / +1).
 struct TabOff {
-  int B, BT, DT, MI, WQ, XQ, XL, WL, total;
+  int B, BT, DT, MI, WQ, XQ, XL, WL, BTM, MC, total;
 };
 __host__ __device__ constexpr TabOff tab_off(int P, int Q) {
   return TabOff{0,
@@ -30,7 +33,9 @@ __host__ __device__ constexpr TabOff tab_off(int P, int Q) {
                 2 * Q * P + Q * Q + P * P + Q,
                 2 * Q * P + Q * Q + P * P + 2 * Q,
                 2 * Q * P + Q * Q + P * P + 2 * Q + P,
-                2 * Q * P + Q * Q + P * P + 2 * Q + 2 * P};
+                2 * Q * P + Q * Q + P * P + 2 * Q + 2 * P,
+                3 * Q * P + Q * Q + P * P + 2 * Q + 2 * P,
+                3 * Q * P + Q * Q + P * P + 2 * Q + 4 * P};
 }
 
 // Structured periodic box, block partition into virtual subdomains, and the

@@ -1,31 +1,29 @@
-// adg_rhs.hip — gfx950 kernels of one SSP-RK3 stage of the ADG right-hand side.
+// adg_rhs.hip — the fused SSP-RK3 stage of the DG right-hand side on gfx950.
 //
-// rhs_stage: one workgroup owns NE consecutive elements (x fastest) and does,
-// entirely in LDS/registers,
-//   1. interpolation of the stage input from the P^d Gauss-Lobatto nodes to the
-//      Q^d Gauss points, d sum-factorised sweeps (Sec. 2.1, eq. weakform-dealii);
-//   2. the Euler flux at every Gauss point, scaled by w_q |J| 2/h_a, tested
-//      against grad phi with a collocation derivative sweep per direction
-//      followed by d transposed interpolation sweeps (volume term);
-//   3. the numerical flux of eq. lfflux at the Q^(d-1) Gauss points of each
-//      face from the element's own face nodes and the neighbour's face nodes
-//      (live, or the ghost trace at PE-boundary faces), lifted back to the
-//      face nodes (surface term; only face nodes see it with Gauss-Lobatto
-//      nodes);
-//   4. the inverse mass matrix M_e^{-1} = |J|^{-1} (M1^{-1} (x) ... (x) M1^{-1})
-//      as d sweeps (eq. weakform-compact-dealii);
-//   5. the Shu-Osher SSP-RK3 combine out = a u_n + b (u_in + dt k), in FP64.
-// T = double (FP64 path) or float (FP32-contraction path: steps 1-4 in FP32).
+// One workgroup (256 threads) owns NE consecutive elements (x fastest) and
+// computes, in LDS and registers, k = M_e^{-1} L_h(u_in) for each of them
+// (Sec. 2.1, eq. weakform-dealii / weakform-compact-dealii), then the
+// Shu-Osher combine out = a u_n + b (u_in + dt k) in FP64.
 //
-// Interior faces are evaluated by both neighbours with one instruction
-// stream on identical operands in a canonical (left, right) order, so the two
-// sides receive bitwise opposite fluxes and the synchronous scheme conserves
-// to summation round-off.
+//   volume:  interpolation of u_in from the P^d Gauss-Lobatto nodes to the
+//            Q^d Gauss points (d sweeps with B); the Euler flux columns F_a at
+//            every point, scaled by w_q 2/h_a; the transposed collocation
+//            derivative along each axis, summed; then d sweeps with
+//            BTM = M1^{-1} B^T, which test against the basis and apply the
+//            inverse mass in one pass (|J| cancels).
+//   faces:   for each axis a, both faces: the element's own face-node values
+//            and the neighbour's (its live values, or the ghost trace at a
+//            PE-boundary face) are interpolated to the Q^(d-1) face points,
+//            the local Lax-Friedrichs flux of eq. lfflux / lfflux-lambda is
+//            evaluated in canonical (left, right) order and scaled by
+//            -w_f 2/h_a; d-1 sweeps with BTM lift it, and the inverse mass
+//            along a turns the face trace into the column of M1^{-1} at that
+//            face: k += MC_side (x) lifted flux.
 //
-// ghost: per PE-boundary face-side node, publishes the neighbour's step-start
-// trace into the ring (stage 0) and builds the trace the receiving element
-// uses: live, delayed (standard flux), or the AT extrapolation of eq. at-flux
-// with weights from eq. at-flux-constraints at tau = k + c_m.
+// Both neighbours of an interior face evaluate the flux with one instruction
+// stream on identical operands in the same order, so their contributions are
+// bitwise opposite and the synchronous scheme conserves to round-off.
+// T = double (FP64 path) or float (FP32 contractions; combine in FP64).
 #include "adg_internal.h"
 
 namespace adg {
@@ -43,14 +41,18 @@ struct Dims {
   static constexpr int nf = 2 * D;
   static constexpr int SZP = V * Pd;
   static constexpr int SZQ = V * Qd;
-  static constexpr int SZNB = V * nf * Fn;
-  static constexpr int SZFL = V * nf * Fq;
+  // faces handled per pass (both faces of an axis when the buffers fit)
+  static constexpr int NS = (2 * V * 2 * (Fn + Fq) + (D == 3 ? 2 * V * 2 * Q * P : 0)) <= 2 * SZQ ? 2 : 1;
+  static constexpr int TR = 2 * NS * V * Fn;  // own + neighbour face nodes
+  static constexpr int TQ = 2 * NS * V * Fq;  // own + neighbour face points
+  static constexpr int TM = D == 3 ? 2 * NS * V * Q * P : 0;
+  static_assert(TR + TQ + TM <= 2 * SZQ, "face buffers exceed the LDS plan");
 };
 
 template <typename T, int D, int P, int Q>
 __host__ __device__ constexpr int rhs_elems_per_block() {
   using Dm = Dims<D, P, Q>;
-  constexpr int per = (2 * Dm::SZP + 3 * Dm::SZQ) * (int)sizeof(T);
+  constexpr int per = (2 * Dm::SZP + 2 * Dm::SZQ) * (int)sizeof(T) + Dm::nf * 12;
   constexpr int tabb = tab_off(P, Q).total * (int)sizeof(T);
   int ne = kThreads / Dm::Pd;
   if (ne < 1) ne = 1;
@@ -58,9 +60,16 @@ __host__ __device__ constexpr int rhs_elems_per_block() {
   return ne;
 }
 
+template <typename T, int D, int P, int Q>
+__host__ __device__ constexpr size_t rhs_smem_bytes(int NE) {
+  using Dm = Dims<D, P, Q>;
+  return (size_t)NE * Dm::nf * 12 + (size_t)(NE * (2 * Dm::SZP + 2 * Dm::SZQ) + tab_off(P, Q).total) * sizeof(T);
+}
+
 // Apply the 1D operator A (NO x NI, row-major) along axis AX of nvec tensors
 // stored back to back with extents (S0, S1, S2) (S_AX == NI); the result has
-// extent NO along AX. One thread per line; A is uniform across the block.
+// extent NO along AX. One thread per line; A is uniform across the block, so
+// its entries come through the scalar cache.
 template <typename T, int NI, int NO, int S0, int S1, int S2, int AX, bool ACC>
 __device__ __forceinline__ void sweep(const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ A,
                                       int nvec) {
@@ -101,7 +110,7 @@ __device__ __forceinline__ void sweep(const T* __restrict__ in, T* __restrict__ 
   }
 }
 
-// index of face-local node j on face f (other axes ascending, lowest fastest)
+// node index of face-local node j on face f (other axes ascending, lowest fastest)
 template <int D, int P>
 __device__ __forceinline__ int face_node(int f, int j) {
   const int a = f >> 1, s = (f & 1) ? P - 1 : 0;
@@ -112,43 +121,20 @@ __device__ __forceinline__ int face_node(int f, int j) {
   return j0 + P * (j1 + P * s);
 }
 
-// value at face Gauss point fq from the P^(d-1) face-node values t
-template <typename T, int D, int P, int Q>
-__device__ __forceinline__ T face_interp(const T* t, const T* B, int fq) {
-  if (D == 2) {
-    T acc = B[fq * P] * t[0];
-#pragma unroll
-    for (int j = 1; j < P; ++j) acc = fmx(B[fq * P + j], t[j], acc);
-    return acc;
-  } else {
-    const int q0 = fq % Q, q1 = fq / Q;
-    T acc = 0;
-#pragma unroll
-    for (int j1 = 0; j1 < P; ++j1) {
-      T r = B[q0 * P] * t[P * j1];
-#pragma unroll
-      for (int j0 = 1; j0 < P; ++j0) r = fmx(B[q0 * P + j0], t[j0 + P * j1], r);
-      acc = j1 == 0 ? B[q1 * P] * r : fmx(B[q1 * P + j1], r, acc);
-    }
-    return acc;
-  }
-}
-
-template <typename T, int D>
-__device__ __forceinline__ T pressure_of(const T* w, T gm1) {
-  T m2 = w[1] * w[1];
-#pragma unroll
-  for (int k = 1; k < D; ++k) m2 = fmx(w[1 + k], w[1 + k], m2);
-  return gm1 * (w[D + 1] - (T)0.5 * m2 / w[0]);
-}
-
-// n.F^ for n = +e_a with left state wl and right state wr (eq. lfflux)
+// n.F^ for n = +e_a with left state wl and right state wr (eq. lfflux,
+// lambda of eq. lfflux-lambda, or the Rusanov speed for kind 1)
 template <typename T, int D>
 __device__ __forceinline__ void num_flux(const T* wl, const T* wr, int a, T gamma, int kind, T* G) {
   constexpr int V = D + 2;
   const T gm1 = gamma - (T)1;
-  const T pl = pressure_of<T, D>(wl, gm1), pr = pressure_of<T, D>(wr, gm1);
   const T il = (T)1 / wl[0], ir = (T)1 / wr[0];
+  T ml2 = wl[1] * wl[1], mr2 = wr[1] * wr[1];
+#pragma unroll
+  for (int k = 1; k < D; ++k) {
+    ml2 = fmx(wl[1 + k], wl[1 + k], ml2);
+    mr2 = fmx(wr[1 + k], wr[1 + k], mr2);
+  }
+  const T pl = gm1 * (wl[D + 1] - (T)0.5 * ml2 * il), pr = gm1 * (wr[D + 1] - (T)0.5 * mr2 * ir);
   const T ual = wl[1 + a] * il, uar = wr[1 + a] * ir;
   T Fl[V], Fr[V];
   Fl[0] = wl[1 + a];
@@ -160,19 +146,13 @@ __device__ __forceinline__ void num_flux(const T* wl, const T* wr, int a, T gamm
   }
   Fl[D + 1] = (wl[D + 1] + pl) * ual;
   Fr[D + 1] = (wr[D + 1] + pr) * uar;
-  T lam;
   const T cl2 = gamma * pl * il, cr2 = gamma * pr * ir;
+  T lam;
   if (kind == 1) {
     const T sl = fabs(ual) + sqrt(cl2), sr = fabs(uar) + sqrt(cr2);
     lam = sl > sr ? sl : sr;
   } else {
-    T ul2 = (wl[1] * il) * (wl[1] * il), ur2 = (wr[1] * ir) * (wr[1] * ir);
-#pragma unroll
-    for (int k = 1; k < D; ++k) {
-      ul2 += (wl[1 + k] * il) * (wl[1 + k] * il);
-      ur2 += (wr[1 + k] * ir) * (wr[1 + k] * ir);
-    }
-    const T sl = ul2 + cl2, sr = ur2 + cr2;
+    const T sl = ml2 * il * il + cl2, sr = mr2 * ir * ir + cr2;
     lam = (T)0.5 * sqrt(sl > sr ? sl : sr);
   }
   const T hl = (T)0.5 * lam;
@@ -183,9 +163,9 @@ __device__ __forceinline__ void num_flux(const T* wl, const T* wr, int a, T gamm
 // logical block index: the hardware deals consecutive blocks round-robin to
 // the 8 XCDs; remap so each XCD walks a contiguous range of elements and its
 // L2 holds the neighbours it reads
-__device__ __forceinline__ long long xcd_block() {
-  const long long nb = gridDim.x, i = blockIdx.x;
-  const long long per = nb / 8, rem = nb % 8, x = i % 8, k = i / 8;
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, i = blockIdx.x;
+  const int per = nb / 8, rem = nb % 8, x = i % 8, k = i / 8;
   return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
 }
 
@@ -195,41 +175,60 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
                                                              double* out, const double* __restrict__ ghost,
                                                              const T* __restrict__ tab) {
   using Dm = Dims<D, P, Q>;
-  constexpr int V = Dm::V, Pd = Dm::Pd, Qd = Dm::Qd, Fn = Dm::Fn, Fq = Dm::Fq, nf = Dm::nf;
+  constexpr int V = Dm::V, Pd = Dm::Pd, Qd = Dm::Qd, Fn = Dm::Fn, Fq = Dm::Fq, nf = Dm::nf, NS = Dm::NS;
   constexpr TabOff to = tab_off(P, Q);
-  static_assert(Dm::SZNB + Dm::SZFL <= 3 * Dm::SZQ, "face buffers exceed LDS plan");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sU = reinterpret_cast<T*>(smem_raw);
+  long long* sOff = reinterpret_cast<long long*>(smem_raw);
+  int* sKind = reinterpret_cast<int*>(sOff + NE * nf);
+  T* sU = reinterpret_cast<T*>(smem_raw + NE * nf * 12);
   T* sR = sU + NE * Dm::SZP;
-  T* sW = sR + NE * Dm::SZP;
-  T* sX = sW + NE * Dm::SZQ;
-  T* sY = sX + NE * Dm::SZQ;
-  T* sT = sY + NE * Dm::SZQ;
+  T* sB1 = sR + NE * Dm::SZP;
+  T* sB2 = sB1 + NE * Dm::SZQ;
+  T* sT = sB2 + NE * Dm::SZQ;
 
-  const long long e0 = xcd_block() * NE;
+  const long long e0 = (long long)xcd_block() * NE;
   const int ne = (int)(M.E - e0 < NE ? M.E - e0 : NE);
   const int tid = threadIdx.x;
+  const bool use_ghost = A.ghost != 0 && M.nfs > 0;
 
+  // where each face's neighbour values come from (once per element face)
+  for (int t = tid; t < ne * nf; t += kThreads) {
+    const int le = t / nf, f = t - le * nf;
+    const unsigned e = (unsigned)(e0 + le);
+    int c[3];
+    c[0] = (int)(e % (unsigned)M.nc[0]);
+    const unsigned r = e / (unsigned)M.nc[0];
+    c[1] = (int)(r % (unsigned)M.nc[1]);
+    c[2] = (int)(r / (unsigned)M.nc[1]);
+    const long long fs = use_ghost ? face_side(M, c, f) : -1;
+    if (fs >= 0) {
+      sOff[t] = fs * V * Fn;
+      sKind[t] = 1;
+    } else {
+      sOff[t] = neighbour(M, c, f) * V * Pd;
+      sKind[t] = 0;
+    }
+  }
   for (int i = tid; i < to.total; i += kThreads) sT[i] = tab[i];
   const double* gin = u_in + e0 * Dm::SZP;
   for (int i = tid; i < ne * Dm::SZP; i += kThreads) sU[i] = (T)gin[i];
   __syncthreads();
 
-  // 1. interpolation to the Gauss points
+  // ---- volume: interpolation to the Gauss points (result in sB1)
   if constexpr (D == 2) {
-    sweep<T, P, Q, P, P, 1, 0, false>(sU, sX, tab + to.B, ne * V);
+    sweep<T, P, Q, P, P, 1, 0, false>(sU, sB2, tab + to.B, ne * V);
     __syncthreads();
-    sweep<T, P, Q, Q, P, 1, 1, false>(sX, sW, tab + to.B, ne * V);
+    sweep<T, P, Q, Q, P, 1, 1, false>(sB2, sB1, tab + to.B, ne * V);
   } else {
-    sweep<T, P, Q, P, P, P, 0, false>(sU, sX, tab + to.B, ne * V);
+    sweep<T, P, Q, P, P, P, 0, false>(sU, sB1, tab + to.B, ne * V);
     __syncthreads();
-    sweep<T, P, Q, Q, P, P, 1, false>(sX, sY, tab + to.B, ne * V);
+    sweep<T, P, Q, Q, P, P, 1, false>(sB1, sB2, tab + to.B, ne * V);
     __syncthreads();
-    sweep<T, P, Q, Q, Q, P, 2, false>(sY, sW, tab + to.B, ne * V);
+    sweep<T, P, Q, Q, Q, P, 2, false>(sB2, sB1, tab + to.B, ne * V);
   }
   __syncthreads();
 
-  // 2. volume flux at the Gauss points, scaled by w_q |J| 2/h_a
+  // Euler flux columns at the Gauss points, scaled by w_q 2/h_a (registers)
   constexpr int QPT = (NE * Qd + kThreads - 1) / kThreads;
   T F[QPT][D][V];
   const T gamma = (T)M.gamma, gm1 = gamma - (T)1;
@@ -240,14 +239,17 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
       const int le = idx / Qd, q = idx - le * Qd;
       T w[V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) w[v] = sW[(le * V + v) * Qd + q];
+      for (int v = 0; v < V; ++v) w[v] = sB1[(le * V + v) * Qd + q];
       T wq = sT[to.WQ + q % Q] * sT[to.WQ + (q / Q) % Q];
       if (D == 3) wq *= sT[to.WQ + q / (Q * Q)];
-      const T p = pressure_of<T, D>(w, gm1);
       const T iv = (T)1 / w[0];
+      T m2 = w[1] * w[1];
+#pragma unroll
+      for (int c = 1; c < D; ++c) m2 = fmx(w[1 + c], w[1 + c], m2);
+      const T p = gm1 * (w[D + 1] - (T)0.5 * m2 * iv);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        const T sc = wq * (T)(M.detJ * 2.0 / M.h[a]);
+        const T sc = wq * (T)(2.0 / M.h[a]);
         const T ua = w[1 + a] * iv;
         F[k][a][0] = sc * w[1 + a];
 #pragma unroll
@@ -256,7 +258,8 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
       }
     }
   }
-  // collocation derivative (transposed) along each axis, summed into sY
+  __syncthreads();
+  // transposed collocation derivative along each axis, summed into sB2
 #pragma unroll
   for (int a = 0; a < D; ++a) {
 #pragma unroll
@@ -265,154 +268,139 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
       if (idx < ne * Qd) {
         const int le = idx / Qd, q = idx - le * Qd;
 #pragma unroll
-        for (int v = 0; v < V; ++v) sX[(le * V + v) * Qd + q] = F[k][a][v];
+        for (int v = 0; v < V; ++v) sB1[(le * V + v) * Qd + q] = F[k][a][v];
       }
     }
     __syncthreads();
     if (D == 2) {
       if (a == 0)
-        sweep<T, Q, Q, Q, Q, 1, 0, false>(sX, sY, tab + to.DT, ne * V);
+        sweep<T, Q, Q, Q, Q, 1, 0, false>(sB1, sB2, tab + to.DT, ne * V);
       else
-        sweep<T, Q, Q, Q, Q, 1, 1, true>(sX, sY, tab + to.DT, ne * V);
+        sweep<T, Q, Q, Q, Q, 1, 1, true>(sB1, sB2, tab + to.DT, ne * V);
     } else {
       if (a == 0)
-        sweep<T, Q, Q, Q, Q, Q, 0, false>(sX, sY, tab + to.DT, ne * V);
+        sweep<T, Q, Q, Q, Q, Q, 0, false>(sB1, sB2, tab + to.DT, ne * V);
       else if (a == 1)
-        sweep<T, Q, Q, Q, Q, Q, 1, true>(sX, sY, tab + to.DT, ne * V);
+        sweep<T, Q, Q, Q, Q, Q, 1, true>(sB1, sB2, tab + to.DT, ne * V);
       else
-        sweep<T, Q, Q, Q, Q, Q, 2, true>(sX, sY, tab + to.DT, ne * V);
+        sweep<T, Q, Q, Q, Q, Q, 2, true>(sB1, sB2, tab + to.DT, ne * V);
     }
     __syncthreads();
   }
-  // transposed interpolation back to the nodes: residual in sR
+  // test functions and inverse mass in one: BTM sweeps, k_volume in sR
   if constexpr (D == 2) {
-    sweep<T, Q, P, Q, Q, 1, 0, false>(sY, sX, tab + to.BT, ne * V);
+    sweep<T, Q, P, Q, Q, 1, 0, false>(sB2, sB1, tab + to.BTM, ne * V);
     __syncthreads();
-    sweep<T, Q, P, P, Q, 1, 1, false>(sX, sR, tab + to.BT, ne * V);
+    sweep<T, Q, P, P, Q, 1, 1, false>(sB1, sR, tab + to.BTM, ne * V);
   } else {
-    sweep<T, Q, P, Q, Q, Q, 0, false>(sY, sX, tab + to.BT, ne * V);
+    sweep<T, Q, P, Q, Q, Q, 0, false>(sB2, sB1, tab + to.BTM, ne * V);
     __syncthreads();
-    sweep<T, Q, P, P, Q, Q, 1, false>(sX, sW, tab + to.BT, ne * V);
+    sweep<T, Q, P, P, Q, Q, 1, false>(sB1, sB2, tab + to.BTM, ne * V);
     __syncthreads();
-    sweep<T, Q, P, P, P, Q, 2, false>(sW, sR, tab + to.BT, ne * V);
+    sweep<T, Q, P, P, P, Q, 2, false>(sB2, sR, tab + to.BTM, ne * V);
   }
   __syncthreads();
 
-  // 3. surface term. Neighbour face nodes (live or ghost) into sNB.
-  T* sNB = sW;
-  T* sFL = sW + NE * Dm::SZNB;
-  const bool use_ghost = A.ghost != 0 && M.nfs > 0;
-  for (int i = tid; i < ne * Dm::SZNB; i += kThreads) {
-    const int j = i % Fn;
-    const int r = i / Fn;
-    const int v = r % V;
-    const int r2 = r / V;
-    const int f = r2 % nf, le = r2 / nf;
-    int c[3];
-    elem_coords(M, e0 + le, c);
-    const long long fs = use_ghost ? face_side(M, c, f) : -1;
-    double val;
-    if (fs >= 0) {
-      val = ghost[(fs * V + v) * Fn + j];
-    } else {
-      const long long nb = neighbour(M, c, f);
-      val = u_in[(nb * V + v) * Pd + face_node<D, P>(f ^ 1, j)];
-    }
-    sNB[i] = (T)val;
-  }
-  __syncthreads();
-  for (int i = tid; i < ne * nf * Fq; i += kThreads) {
-    const int fq = i % Fq;
-    const int r = i / Fq;
-    const int f = r % nf, le = r / nf;
-    const int a = f >> 1, side = f & 1;
-    T wo[V], wn[V], t[Fn];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-#pragma unroll
-      for (int j = 0; j < Fn; ++j) t[j] = sU[(le * V + v) * Pd + face_node<D, P>(f, j)];
-      wo[v] = face_interp<T, D, P, Q>(t, sT + to.B, fq);
-#pragma unroll
-      for (int j = 0; j < Fn; ++j) t[j] = sNB[((le * nf + f) * V + v) * Fn + j];
-      wn[v] = face_interp<T, D, P, Q>(t, sT + to.B, fq);
-    }
-    // canonical (left, right) operands, one call site for both sides
-    T wl[V], wr[V], G[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      wl[v] = side ? wo[v] : wn[v];
-      wr[v] = side ? wn[v] : wo[v];
-    }
-    num_flux<T, D>(wl, wr, a, gamma, M.flux, G);
-    T ws = sT[to.WQ + fq % Q];
-    if (D == 3) ws *= sT[to.WQ + fq / Q];
-    ws *= (T)M.detJf[a];
-    const T sg = side ? (T)1 : (T)-1;
-#pragma unroll
-    for (int v = 0; v < V; ++v) sFL[((le * nf + f) * V + v) * Fq + fq] = sg * (G[v] * ws);
-  }
-  __syncthreads();
-  // lift: R_i -= sum over the faces through node i of phi_i . flux
-  for (int i = tid; i < ne * Dm::SZP; i += kThreads) {
-    const int node = i % Pd;
-    const int r = i / Pd;
-    const int v = r % V, le = r / V;
-    const int nc[3] = {node % P, (node / P) % P, node / (P * P)};
-    T acc = 0;
-    bool any = false;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-#pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        if (nc[a] != (side ? P - 1 : 0)) continue;
-        const int f = 2 * a + side;
-        const int o0 = a == 0 ? 1 : 0, o1 = a == 2 ? 1 : 2;
-        const int j0 = nc[o0], j1 = D == 3 ? nc[o1] : 0;
-        const T* fl = sFL + ((le * nf + f) * V + v) * Fq;
-        T s = 0;
-        if (D == 2) {
-#pragma unroll
-          for (int q = 0; q < Q; ++q) s = fmx(sT[to.B + q * P + j0], fl[q], s);
-        } else {
-#pragma unroll
-          for (int q1 = 0; q1 < Q; ++q1) {
-            T r1 = 0;
-#pragma unroll
-            for (int q0 = 0; q0 < Q; ++q0) r1 = fmx(sT[to.B + q0 * P + j0], fl[q0 + Q * q1], r1);
-            s = fmx(sT[to.B + q1 * P + j1], r1, s);
-          }
-        }
-        acc += s;
-        any = true;
+  // ---- faces, NS faces of one axis per pass
+  // layouts: sTr [side][le][s][v][Fn], sTq [side][le][s][v][Fq],
+  // sTm (3D interpolation intermediate) [side][le][s][v][Q*P]
+  T* sTr = sB1;
+  T* sTq = sTr + NE * Dm::TR;
+  T* sTm = sTq + NE * Dm::TQ;
+  const int HALF_R = ne * NS * V * Fn, HALF_Q = ne * NS * V * Fq;  // start of the neighbour half
+#pragma unroll 1
+  for (int pass = 0; pass < nf / NS; ++pass) {
+    const int a = (pass * NS) >> 1;
+    const int s0 = (pass * NS) & 1;
+    // gather own (side 0) and neighbour (side 1) face-node values
+    for (int i = tid; i < 2 * ne * NS * V * Fn; i += kThreads) {
+      const int side = i / (ne * NS * V * Fn);
+      const int r = i - side * (ne * NS * V * Fn);
+      const int j = r % Fn;
+      const int r2 = r / Fn;
+      const int v = r2 % V;
+      const int r3 = r2 / V;
+      const int s = r3 % NS + s0, le = r3 / NS;
+      const int f = 2 * a + s;
+      T val;
+      if (side == 0) {
+        val = sU[(le * V + v) * Pd + face_node<D, P>(f, j)];
+      } else {
+        const int t = le * nf + f;
+        const long long o = sOff[t];
+        val = sKind[t] ? (T)ghost[o + v * Fn + j] : (T)u_in[o + v * Pd + face_node<D, P>(f ^ 1, j)];
       }
+      sTr[side * HALF_R + r] = val;
     }
-    if (any) sR[i] -= acc;
+    __syncthreads();
+    // interpolation to the face points (both sides at once)
+    if constexpr (D == 2) {
+      sweep<T, P, Q, P, 1, 1, 0, false>(sTr, sTq, tab + to.B, 2 * ne * NS * V);
+    } else {
+      sweep<T, P, Q, P, P, 1, 0, false>(sTr, sTm, tab + to.B, 2 * ne * NS * V);
+      __syncthreads();
+      sweep<T, P, Q, Q, P, 1, 1, false>(sTm, sTq, tab + to.B, 2 * ne * NS * V);
+    }
+    __syncthreads();
+    // numerical flux at every face point, in place of the own values
+    for (int i = tid; i < ne * NS * Fq; i += kThreads) {
+      const int fq = i % Fq;
+      const int r = i / Fq;
+      const int s = r % NS + s0, le = r / NS;
+      const int base = ((le * NS + (s - s0)) * V) * Fq + fq;
+      T wo[V], wn[V], wl[V], wr[V], G[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        wo[v] = sTq[base + v * Fq];
+        wn[v] = sTq[HALF_Q + base + v * Fq];
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        wl[v] = s ? wo[v] : wn[v];
+        wr[v] = s ? wn[v] : wo[v];
+      }
+      num_flux<T, D>(wl, wr, a, gamma, M.flux, G);
+      T ws = sT[to.WQ + fq % Q];
+      if (D == 3) ws *= sT[to.WQ + fq / Q];
+      ws *= (T)(2.0 / M.h[a]);
+      const T sg = s ? (T)-1 : (T)1;  // -(n.e_a): the face term enters with a minus sign
+#pragma unroll
+      for (int v = 0; v < V; ++v) sTq[base + v * Fq] = sg * (G[v] * ws);
+    }
+    __syncthreads();
+    // lift with BTM to the face nodes (own half only), result in sTr
+    if constexpr (D == 2) {
+      sweep<T, Q, P, Q, 1, 1, 0, false>(sTq, sTr, tab + to.BTM, ne * NS * V);
+    } else {
+      sweep<T, Q, P, Q, Q, 1, 0, false>(sTq, sTm, tab + to.BTM, ne * NS * V);
+      __syncthreads();
+      sweep<T, Q, P, P, Q, 1, 1, false>(sTm, sTr, tab + to.BTM, ne * NS * V);
+    }
+    __syncthreads();
+    // inverse mass along a: k += MC_side[i_a] * lifted(j)
+    for (int i = tid; i < ne * Dm::SZP; i += kThreads) {
+      const int node = i % Pd;
+      const int r = i / Pd;
+      const int v = r % V, le = r / V;
+      const int nc[3] = {node % P, (node / P) % P, node / (P * P)};
+      const int o0 = a == 0 ? 1 : 0, o1 = a == 2 ? 1 : 2;
+      const int j = D == 2 ? nc[o0] : nc[o0] + P * nc[o1];
+      T acc = sR[i];
+#pragma unroll
+      for (int ss = 0; ss < NS; ++ss) {
+        const int s = ss + s0;
+        acc = fmx(sT[to.MC + s * P + nc[a]], sTr[((le * NS + ss) * V + v) * Fn + j], acc);
+      }
+      sR[i] = acc;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
-  // 4. inverse mass: d sweeps of M1^{-1}
-  T* sK;
-  if constexpr (D == 2) {
-    sweep<T, P, P, P, P, 1, 0, false>(sR, sX, tab + to.MI, ne * V);
-    __syncthreads();
-    sweep<T, P, P, P, P, 1, 1, false>(sX, sY, tab + to.MI, ne * V);
-    sK = sY;
-  } else {
-    sweep<T, P, P, P, P, P, 0, false>(sR, sX, tab + to.MI, ne * V);
-    __syncthreads();
-    sweep<T, P, P, P, P, P, 1, false>(sX, sY, tab + to.MI, ne * V);
-    __syncthreads();
-    sweep<T, P, P, P, P, P, 2, false>(sY, sX, tab + to.MI, ne * V);
-    sK = sX;
-  }
-  __syncthreads();
-
-  // 5. SSP-RK3 combine in FP64
-  const double idet = 1.0 / M.detJ;
+  // ---- SSP-RK3 combine in FP64
   double* gout = out + e0 * Dm::SZP;
   const double* gn = u_n + e0 * Dm::SZP;
   for (int i = tid; i < ne * Dm::SZP; i += kThreads) {
-    const double k = (double)sK[i] * idet;
+    const double k = (double)sR[i];
     const double ui = sizeof(T) == 8 ? (double)sU[i] : gin[i];
     const double y = ui + S.dt * k;
     gout[i] = S.a == 0.0 ? S.b * y : S.a * gn[i] + S.b * y;
@@ -424,8 +412,7 @@ static hipError_t launch_rhs_t(const Mesh& M, const Async& A, const Stage& S, co
                                double* out, const double* ghost, const T* tab, hipStream_t st) {
   constexpr int P = p + 1, Q = p + 2;
   constexpr int NE = rhs_elems_per_block<T, D, P, Q>();
-  using Dm = Dims<D, P, Q>;
-  const size_t smem = (size_t)(NE * (2 * Dm::SZP + 3 * Dm::SZQ) + tab_off(P, Q).total) * sizeof(T);
+  const size_t smem = rhs_smem_bytes<T, D, P, Q>(NE);
   const long long nblk = (M.E + NE - 1) / NE;
   hipLaunchKernelGGL((rhs_stage_kernel<T, D, P, Q, NE>), dim3((unsigned)nblk), dim3(kThreads), smem, st, M, A, S,
                      u_in, u_n, out, ghost, tab);
@@ -449,73 +436,6 @@ hipError_t launch_rhs_stage(int dim, int degree, int precision, const Mesh& M, c
                             const double* tab64, const float* tab32, hipStream_t st) {
   if (precision == 1) return launch_rhs_prec<float>(dim, degree, M, A, S, u_in, u_n, out, ghost, tab32, st);
   return launch_rhs_prec<double>(dim, degree, M, A, S, u_in, u_n, out, ghost, tab64, st);
-}
-
-// ---------------------------------------------------------------------------
-// ghost traces and ring publish: one thread per (face-side, variable, node)
-// ---------------------------------------------------------------------------
-
-// AT weight of level j among nlev at fractional delay tau: Lagrange
-// extrapolation to offset 0 from the level times -(tau + i)
-__device__ __forceinline__ double at_weight(int j, int nlev, double tau) {
-  double w = 1.0;
-  for (int i = 0; i < nlev; ++i)
-    if (i != j) w *= (tau + i) / (double)(i - j);
-  return w;
-}
-
-template <int D, int P>
-__global__ __launch_bounds__(256) void ghost_kernel(Mesh M, Async A, const double* __restrict__ u_in,
-                                                    const double* __restrict__ u_n, double* __restrict__ ring,
-                                                    double* __restrict__ ghost, int publish) {
-  constexpr int V = D + 2, Fn = D == 2 ? P : P * P, Pd = Fn * P;
-  const long long total = M.nfs * V * Fn;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int j = (int)(i % Fn);
-  const long long r = i / Fn;
-  const int v = (int)(r % V);
-  const long long fs = r / V;
-  int c[3], f;
-  face_side_decode(M, fs, c, &f);
-  const long long nb = neighbour(M, c, f);
-  const long long src = (nb * V + v) * Pd + face_node<D, P>(f ^ 1, j);
-  if (publish) ring[(A.n % A.R) * total + i] = u_n[src];
-  const int k = delay_of(M, A, subdomain_of(M, c), f);
-  double g;
-  if (k == 0) {
-    g = u_in[src];
-  } else if (A.ghost == 1) {
-    g = ring[((A.n - k) % A.R) * total + i];
-  } else {
-    const double tau = k + A.c_m;
-    g = 0.0;
-    for (int l = 0; l < A.levels; ++l) g += at_weight(l, A.levels, tau) * ring[((A.n - k - l) % A.R) * total + i];
-  }
-  ghost[i] = g;
-}
-
-hipError_t launch_ghost(int dim, int degree, const Mesh& M, const Async& A, const double* u_in, const double* u_n,
-                        double* ring, double* ghost, const float* mlp, int publish, double* stats,
-                        hipStream_t st) {
-  (void)mlp;
-  (void)stats;
-  const int V = dim + 2;
-  long long Fn = 1;
-  for (int k = 0; k < dim - 1; ++k) Fn *= degree + 1;
-  const long long total = M.nfs * V * Fn;
-  if (total == 0) return hipSuccess;
-  const unsigned nblk = (unsigned)((total + 255) / 256);
-#define ADG_GH_CASE(d, p)                                                                                  \
-  if (dim == d && degree == p) {                                                                           \
-    hipLaunchKernelGGL((ghost_kernel<d, p + 1>), dim3(nblk), dim3(256), 0, st, M, A, u_in, u_n, ring, ghost, \
-                       publish);                                                                           \
-    return hipGetLastError();                                                                              \
-  }
-  ADG_GH_CASE(2, 1) ADG_GH_CASE(2, 2) ADG_GH_CASE(2, 3) ADG_GH_CASE(2, 4)
-  ADG_GH_CASE(3, 1) ADG_GH_CASE(3, 2) ADG_GH_CASE(3, 3) ADG_GH_CASE(3, 4)
-#undef ADG_GH_CASE
-  return hipErrorInvalidValue;
 }
 
 }  // namespace adg

@@ -75,7 +75,9 @@ def summarize(fetch_csv, write_csv, workload, out):
         vals = sum((d[k] for k in ks), [])
         return sum(vals) / len(vals), len(vals)
 
-    copy_name = [k for k in fe if "rhs_stage" not in k and "ghost" not in k and ("mul" in k or "elementwise" in k)]
+    # the elementwise multiply (reads and writes COPY_DOUBLES doubles); not
+    # the fill kernel that created its input
+    copy_name = [k for k in fe if "elementwise" in k and "Fill" not in k]
     if not copy_name:
         raise SystemExit("calibration copy kernel not found")
     cf = sum(fe[copy_name[0]]) / len(fe[copy_name[0]])
