@@ -15,6 +15,7 @@ constexpr int kTrainBlocks = 64;  // blocks per gradient launch
 constexpr int kTrainChunk = 64;   // samples per block per launch
 constexpr int kMaxBatch = kTrainBlocks * kTrainChunk;
 constexpr int kPackBytes = 8192;  // BF16 operand tiles + FP32 biases
+constexpr float kTargetClip = 64.0f;  // training targets beyond this get weight 0
 
 __host__ __device__ constexpr int mlp_nin(int V) { return 2 * V + 2; }
 __host__ __device__ constexpr int mlp_nparams(int V) { return kMlpH * mlp_nin(V) + kMlpH + V * kMlpH + V; }

@@ -269,12 +269,23 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
       }
     }
     if (collect && g == 0) {
+      // target: live stage value minus AT, in units of S. Targets beyond
+      // kTargetClip (well above the largest extrapolation coefficient the
+      // delays allow) come from the neighbour's own asynchronous jumps, not
+      // from the history: they get weight 0.
       float* rec = pairs + (pair_base + fs * Fn + j) * (long long)(NIN + V + 1);
+      bool keep = k >= 1;
+      float tg[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        tg[v] = k >= 1 ? (float)((live[v] - at[v]) / S3) : 0.0f;
+        keep = keep && fabsf(tg[v]) <= kTargetClip;
+      }
 #pragma unroll
       for (int q = 0; q < NIN; ++q) rec[q] = x[q];
 #pragma unroll
-      for (int v = 0; v < V; ++v) rec[NIN + v] = k >= 1 ? (float)((live[v] - at[v]) / S3) : 0.0f;
-      rec[NIN + V] = k >= 1 ? 1.0f : 0.0f;
+      for (int v = 0; v < V; ++v) rec[NIN + v] = keep ? tg[v] : 0.0f;
+      rec[NIN + V] = keep ? 1.0f : 0.0f;
     }
   }
 }
