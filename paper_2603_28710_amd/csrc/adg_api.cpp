@@ -302,21 +302,24 @@ static adg_status run_stage(adg_ctx_s* c, int m, double dt, bool learned_collect
   double* out[3] = {c->u_a, c->u_b, c->u_n};
   Async A = make_async(c, m);
   double* ghost = scratch_d(c, c->ghost_off);
+  // stale and AT traces are built inside the stage kernel from the ring; the
+  // learned predictor (and pair collection) runs as its own kernel first
+  int src = kSrcLive;
   if (A.ghost != 0 && c->mesh.nfs > 0) {
-    PROF_TRY(prof_begin(c, ADG_KERNEL_GHOST));
     if (A.ghost == 3 || learned_collect) {
+      PROF_TRY(prof_begin(c, ADG_KERNEL_GHOST));
       HIP_TRY(launch_ghost_learned(c->D, c->p, c->mesh, A, in[m], c->u_n, c->ring, ghost, m == 0, c->mlp,
                                    pair_base, learned_collect, c->stream));
+      PROF_TRY(prof_end(c));
+      src = kSrcGhost;
     } else {
-      HIP_TRY(launch_ghost(c->D, c->p, c->mesh, A, in[m], c->u_n, c->ring, ghost, nullptr, m == 0, nullptr,
-                           c->stream));
+      src = kSrcRing;
     }
-    PROF_TRY(prof_end(c));
   }
   Stage S{kSspA[m], kSspB[m], dt};
   PROF_TRY(prof_begin(c, ADG_KERNEL_RHS));
-  HIP_TRY(launch_rhs_stage(c->D, c->p, c->cfg.precision, c->mesh, A, S, in[m], c->u_n, out[m], ghost,
-                           c->d_tab64, c->d_tab32, c->stream));
+  HIP_TRY(launch_rhs_stage(c->D, c->p, c->cfg.precision, c->mesh, A, S, in[m], c->u_n, out[m], src, c->ring,
+                           ghost, c->d_tab64, c->d_tab32, c->stream));
   PROF_TRY(prof_end(c));
   return ADG_OK;
 }

@@ -177,9 +177,16 @@ __host__ __device__ inline int delay_of(const Mesh& M, const Async& A, int sub, 
 
 // ---- launchers (defined in the .hip files) ---------------------------------
 
+// Neighbour data at PE-boundary faces inside the stage kernel:
+// kSrcLive   every face reads the neighbour's live stage values (synchronous);
+// kSrcRing   the kernel builds the delayed / AT trace from the ring itself and,
+//            at stage 0, publishes its own boundary traces (stale and AT modes);
+// kSrcGhost  PE faces read a ghost buffer built by a separate kernel (learned).
+enum GhostSrc { kSrcLive = 0, kSrcRing = 1, kSrcGhost = 2 };
+
 hipError_t launch_rhs_stage(int dim, int degree, int precision, const Mesh& M, const Async& A, const Stage& S,
-                            const double* u_in, const double* u_n, double* out, const double* ghost,
-                            const double* tab64, const float* tab32, hipStream_t st);
+                            const double* u_in, const double* u_n, double* out, int src, double* ring,
+                            const double* ghost, const double* tab64, const float* tab32, hipStream_t st);
 hipError_t launch_ghost(int dim, int degree, const Mesh& M, const Async& A, const double* u_in, const double* u_n,
                         double* ring, double* ghost, const float* mlp, int publish, double* stats,
                         hipStream_t st);

@@ -49,10 +49,15 @@ struct Dims {
   static_assert(TR + TQ + TM <= 2 * SZQ, "face buffers exceed the LDS plan");
 };
 
+// per (element, face) descriptor kept in LDS: neighbour element offset, the
+// face-side offset of this face in the ring (or -1), the offset of the
+// face-side this face feeds in the neighbour subdomain's ring (or -1), delay
+constexpr int kFaceInfoBytes = 32;
+
 template <typename T, int D, int P, int Q>
 __host__ __device__ constexpr int rhs_elems_per_block() {
   using Dm = Dims<D, P, Q>;
-  constexpr int per = (2 * Dm::SZP + 2 * Dm::SZQ) * (int)sizeof(T) + Dm::nf * 12;
+  constexpr int per = (2 * Dm::SZP + 2 * Dm::SZQ) * (int)sizeof(T) + Dm::nf * kFaceInfoBytes;
   constexpr int tabb = tab_off(P, Q).total * (int)sizeof(T);
   int ne = kThreads / Dm::Pd;
   if (ne < 1) ne = 1;
@@ -63,7 +68,18 @@ __host__ __device__ constexpr int rhs_elems_per_block() {
 template <typename T, int D, int P, int Q>
 __host__ __device__ constexpr size_t rhs_smem_bytes(int NE) {
   using Dm = Dims<D, P, Q>;
-  return (size_t)NE * Dm::nf * 12 + (size_t)(NE * (2 * Dm::SZP + 2 * Dm::SZQ) + tab_off(P, Q).total) * sizeof(T);
+  return (size_t)NE * Dm::nf * kFaceInfoBytes +
+         (size_t)(NE * (2 * Dm::SZP + 2 * Dm::SZQ) + tab_off(P, Q).total) * sizeof(T);
+}
+
+// AT weight of level l among nlev at fractional delay tau: Lagrange
+// extrapolation to offset 0 from the level times -(tau + i), i.e. the
+// solution of the moment constraints of eq. at-flux-constraints
+__device__ __forceinline__ double at_weight_rhs(int l, int nlev, double tau) {
+  double w = 1.0;
+  for (int i = 0; i < nlev; ++i)
+    if (i != l) w *= (tau + i) / (double)(i - l);
+  return w;
 }
 
 // Apply the 1D operator A (NO x NI, row-major) along axis AX of nvec tensors
@@ -172,15 +188,18 @@ __device__ __forceinline__ int xcd_block() {
 template <typename T, int D, int P, int Q, int NE>
 __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, Stage S,
                                                              const double* __restrict__ u_in, const double* u_n,
-                                                             double* out, const double* __restrict__ ghost,
+                                                             double* out, int src, double* __restrict__ ring,
+                                                             const double* __restrict__ ghost,
                                                              const T* __restrict__ tab) {
   using Dm = Dims<D, P, Q>;
   constexpr int V = Dm::V, Pd = Dm::Pd, Qd = Dm::Qd, Fn = Dm::Fn, Fq = Dm::Fq, nf = Dm::nf, NS = Dm::NS;
   constexpr TabOff to = tab_off(P, Q);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  long long* sOff = reinterpret_cast<long long*>(smem_raw);
-  int* sKind = reinterpret_cast<int*>(sOff + NE * nf);
-  T* sU = reinterpret_cast<T*>(smem_raw + NE * nf * 12);
+  long long* sNb = reinterpret_cast<long long*>(smem_raw);  // neighbour element offset
+  long long* sFs = sNb + NE * nf;                           // own face-side offset, or -1
+  long long* sPub = sFs + NE * nf;                          // face-side fed by this face, or -1
+  int* sK = reinterpret_cast<int*>(sPub + NE * nf);         // delay of this face
+  T* sU = reinterpret_cast<T*>(smem_raw + NE * nf * kFaceInfoBytes);
   T* sR = sU + NE * Dm::SZP;
   T* sB1 = sR + NE * Dm::SZP;
   T* sB2 = sB1 + NE * Dm::SZQ;
@@ -189,9 +208,11 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
   const long long e0 = (long long)xcd_block() * NE;
   const int ne = (int)(M.E - e0 < NE ? M.E - e0 : NE);
   const int tid = threadIdx.x;
-  const bool use_ghost = A.ghost != 0 && M.nfs > 0;
+  const bool async_on = src != kSrcLive && M.nfs > 0;
+  const long long ring_level = M.nfs * V * Fn;  // values per ring level
+  const bool publish = src == kSrcRing && A.stage == 0;
 
-  // where each face's neighbour values come from (once per element face)
+  // per element face: neighbour, PE face-side, delay, and the face-side it feeds
   for (int t = tid; t < ne * nf; t += kThreads) {
     const int le = t / nf, f = t - le * nf;
     const unsigned e = (unsigned)(e0 + le);
@@ -200,19 +221,45 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
     const unsigned r = e / (unsigned)M.nc[0];
     c[1] = (int)(r % (unsigned)M.nc[1]);
     c[2] = (int)(r / (unsigned)M.nc[1]);
-    const long long fs = use_ghost ? face_side(M, c, f) : -1;
-    if (fs >= 0) {
-      sOff[t] = fs * V * Fn;
-      sKind[t] = 1;
-    } else {
-      sOff[t] = neighbour(M, c, f) * V * Pd;
-      sKind[t] = 0;
+    const long long nb = neighbour(M, c, f);
+    sNb[t] = nb * V * Pd;
+    const long long fs = async_on ? face_side(M, c, f) : -1;
+    sFs[t] = fs >= 0 ? fs * V * Fn : -1;
+    sK[t] = fs >= 0 && src == kSrcRing ? delay_of(M, A, subdomain_of(M, c), f) : 0;
+    long long pub = -1;
+    if (publish && fs >= 0) {
+      int cn[3];
+      const unsigned en = (unsigned)nb;
+      cn[0] = (int)(en % (unsigned)M.nc[0]);
+      const unsigned rn = en / (unsigned)M.nc[0];
+      cn[1] = (int)(rn % (unsigned)M.nc[1]);
+      cn[2] = (int)(rn / (unsigned)M.nc[1]);
+      pub = face_side(M, cn, f ^ 1) * V * Fn;
     }
+    sPub[t] = pub;
   }
   for (int i = tid; i < to.total; i += kThreads) sT[i] = tab[i];
   const double* gin = u_in + e0 * Dm::SZP;
   for (int i = tid; i < ne * Dm::SZP; i += kThreads) sU[i] = (T)gin[i];
   __syncthreads();
+
+  // stage 0 of a step: publish this block's PE-boundary traces of u^n into
+  // ring slot n mod R, where the neighbouring subdomain will read them. No
+  // reader of this launch touches that slot: delays >= 1 read older levels,
+  // delay 0 reads the live values.
+  if (publish) {
+    double* slot = ring + (A.n % A.R) * ring_level;
+    for (int i = tid; i < ne * nf * Fn; i += kThreads) {
+      const int j = i % Fn;
+      const int t = i / Fn;
+      const long long pub = sPub[t];
+      if (pub < 0) continue;
+      const int le = t / nf, f = t - le * nf;
+      const int node = face_node<D, P>(f, j);
+#pragma unroll
+      for (int v = 0; v < V; ++v) slot[pub + v * Fn + j] = gin[(le * V + v) * Pd + node];
+    }
+  }
 
   // ---- volume: interpolation to the Gauss points (result in sB1)
   if constexpr (D == 2) {
@@ -312,25 +359,55 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
   for (int pass = 0; pass < nf / NS; ++pass) {
     const int a = (pass * NS) >> 1;
     const int s0 = (pass * NS) & 1;
-    // gather own (side 0) and neighbour (side 1) face-node values
-    for (int i = tid; i < 2 * ne * NS * V * Fn; i += kThreads) {
-      const int side = i / (ne * NS * V * Fn);
-      const int r = i - side * (ne * NS * V * Fn);
-      const int j = r % Fn;
-      const int r2 = r / Fn;
-      const int v = r2 % V;
-      const int r3 = r2 / V;
-      const int s = r3 % NS + s0, le = r3 / NS;
+    // gather own (side 0) and neighbour (side 1) face-node values; one item
+    // per (side, element, face, node), all V variables
+    for (int i = tid; i < 2 * ne * NS * Fn; i += kThreads) {
+      const int j = i % Fn;
+      const int r = i / Fn;
+      const int ls = r % (ne * NS);  // le * NS + (s - s0)
+      const int side = r / (ne * NS);
+      const int le = ls / NS, s = ls - le * NS + s0;
       const int f = 2 * a + s;
-      T val;
+      T* dst = sTr + side * HALF_R + ls * V * Fn + j;
       if (side == 0) {
-        val = sU[(le * V + v) * Pd + face_node<D, P>(f, j)];
-      } else {
-        const int t = le * nf + f;
-        const long long o = sOff[t];
-        val = sKind[t] ? (T)ghost[o + v * Fn + j] : (T)u_in[o + v * Pd + face_node<D, P>(f ^ 1, j)];
+        const T* srcp = sU + le * V * Pd + face_node<D, P>(f, j);
+#pragma unroll
+        for (int v = 0; v < V; ++v) dst[v * Fn] = srcp[v * Pd];
+        continue;
       }
-      sTr[side * HALF_R + r] = val;
+      const int t = le * nf + f;
+      const long long fs = sFs[t];
+      const int k = sK[t];
+      if (fs < 0 || (src == kSrcRing && k == 0)) {
+        // interior face, synchronous mode, or zero delay: live stage values
+        const double* g = u_in + sNb[t] + face_node<D, P>(f ^ 1, j);
+#pragma unroll
+        for (int v = 0; v < V; ++v) dst[v * Fn] = (T)g[v * Pd];
+      } else if (src == kSrcGhost) {
+        const double* g = ghost + fs + j;
+#pragma unroll
+        for (int v = 0; v < V; ++v) dst[v * Fn] = (T)g[v * Fn];
+      } else if (A.ghost == 1) {
+        // standard flux on the trace k steps old (eq. delayed-flux)
+        const double* g = ring + ((A.n - k) % A.R) * ring_level + fs + j;
+#pragma unroll
+        for (int v = 0; v < V; ++v) dst[v * Fn] = (T)g[v * Fn];
+      } else {
+        // AT extrapolation of `levels` stored levels to the stage time
+        // (eq. at-flux, tau = k + c_m); weights and sums in FP64
+        const double tau = k + A.c_m;
+        double acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = 0.0;
+        for (int l = 0; l < A.levels; ++l) {
+          const double wl = at_weight_rhs(l, A.levels, tau);
+          const double* g = ring + ((A.n - k - l) % A.R) * ring_level + fs + j;
+#pragma unroll
+          for (int v = 0; v < V; ++v) acc[v] += wl * g[v * Fn];
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) dst[v * Fn] = (T)acc[v];
+      }
     }
     __syncthreads();
     // interpolation to the face points (both sides at once)
@@ -409,22 +486,23 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
 
 template <typename T, int D, int p>
 static hipError_t launch_rhs_t(const Mesh& M, const Async& A, const Stage& S, const double* u_in, const double* u_n,
-                               double* out, const double* ghost, const T* tab, hipStream_t st) {
+                               double* out, int src, double* ring, const double* ghost, const T* tab,
+                               hipStream_t st) {
   constexpr int P = p + 1, Q = p + 2;
   constexpr int NE = rhs_elems_per_block<T, D, P, Q>();
   const size_t smem = rhs_smem_bytes<T, D, P, Q>(NE);
   const long long nblk = (M.E + NE - 1) / NE;
   hipLaunchKernelGGL((rhs_stage_kernel<T, D, P, Q, NE>), dim3((unsigned)nblk), dim3(kThreads), smem, st, M, A, S,
-                     u_in, u_n, out, ghost, tab);
+                     u_in, u_n, out, src, ring, ghost, tab);
   return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_rhs_prec(int dim, int degree, const Mesh& M, const Async& A, const Stage& S,
-                                  const double* u_in, const double* u_n, double* out, const double* ghost,
-                                  const T* tab, hipStream_t st) {
+                                  const double* u_in, const double* u_n, double* out, int src, double* ring,
+                                  const double* ghost, const T* tab, hipStream_t st) {
 #define ADG_RHS_CASE(d, p) \
-  if (dim == d && degree == p) return launch_rhs_t<T, d, p>(M, A, S, u_in, u_n, out, ghost, tab, st);
+  if (dim == d && degree == p) return launch_rhs_t<T, d, p>(M, A, S, u_in, u_n, out, src, ring, ghost, tab, st);
   ADG_RHS_CASE(2, 1) ADG_RHS_CASE(2, 2) ADG_RHS_CASE(2, 3) ADG_RHS_CASE(2, 4)
   ADG_RHS_CASE(3, 1) ADG_RHS_CASE(3, 2) ADG_RHS_CASE(3, 3) ADG_RHS_CASE(3, 4)
 #undef ADG_RHS_CASE
@@ -432,10 +510,11 @@ static hipError_t launch_rhs_prec(int dim, int degree, const Mesh& M, const Asyn
 }
 
 hipError_t launch_rhs_stage(int dim, int degree, int precision, const Mesh& M, const Async& A, const Stage& S,
-                            const double* u_in, const double* u_n, double* out, const double* ghost,
-                            const double* tab64, const float* tab32, hipStream_t st) {
-  if (precision == 1) return launch_rhs_prec<float>(dim, degree, M, A, S, u_in, u_n, out, ghost, tab32, st);
-  return launch_rhs_prec<double>(dim, degree, M, A, S, u_in, u_n, out, ghost, tab64, st);
+                            const double* u_in, const double* u_n, double* out, int src, double* ring,
+                            const double* ghost, const double* tab64, const float* tab32, hipStream_t st) {
+  if (precision == 1)
+    return launch_rhs_prec<float>(dim, degree, M, A, S, u_in, u_n, out, src, ring, ghost, tab32, st);
+  return launch_rhs_prec<double>(dim, degree, M, A, S, u_in, u_n, out, src, ring, ghost, tab64, st);
 }
 
 }  // namespace adg
