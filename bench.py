@@ -2,13 +2,12 @@
 """Throughput of the asynchronous DG solver with AT neighbour traces on one
 MI355X: DOF-updates per second per SSP-RK3 stage.
 
-A step is one full SSP-RK3 step (3 stages, each: ring publish/ghost traces at
-the PE-boundary faces, then the fused right-hand-side stage kernel) over the
-whole mesh. Inputs are synthetic and resident in HBM before the timed region.
+A step is one full SSP-RK3 step over the whole mesh: 3 launches of the fused
+stage kernel, which also publishes the ring traces (stage 0) and builds the
+delayed / AT neighbour traces at the PE-boundary faces. Inputs are synthetic and resident in HBM before the timed region.
 Prints one JSON line.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -16,6 +15,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+from paper_2603_28710_amd import profile_traffic  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
@@ -81,14 +82,6 @@ def algorithmic_flops_per_element(dim, P, Q):
     return 2 * (interp + deriv + test + traces + lift + minv) + Qd * flux_qp + nf * Fq * llf + combine
 
 
-def source_hash():
-    h = hashlib.sha256()
-    for f in ("adg_rhs.hip",):
-        with open(os.path.join(ROOT, "paper_2603_28710_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(workload):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
@@ -97,7 +90,7 @@ def load_traffic(workload):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_sha256_16") != source_hash():
+    if d.get("source_sha256_16") != profile_traffic.source_hash():
         return None
     return d.get("hbm_bytes_per_launch")
 

@@ -12,8 +12,9 @@
 #include <vector>
 
 #include "../../include/adg.h"
-#include "adg_internal.h"
 #include "adg_ctx.h"
+#include "adg_internal.h"
+#include "adg_tables.h"
 
 using namespace adg;
 
@@ -25,156 +26,43 @@ namespace {
 
 // ---------------------------------------------------------------- 1D tables
 
-// Legendre P_n and its derivative by the Bonnet recurrence
-void legendre(int n, double x, double& Pn, double& dPn) {
-  double p0 = 1.0, p1 = x;
-  if (n == 0) {
-    Pn = 1.0;
-    dPn = 0.0;
-    return;
-  }
-  for (int k = 1; k < n; ++k) {
-    const double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
-    p0 = p1;
-    p1 = p2;
-  }
-  Pn = p1;
-  dPn = n * (p0 - x * p1) / (1.0 - x * x);
-}
-
-// Gauss-Legendre rule: Newton from Tricomi's initial guesses
-void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w) {
-  x.assign(n, 0.0);
-  w.assign(n, 0.0);
-  for (int i = 0; i < n; ++i) {
-    const double th = M_PI * (4.0 * (n - i) - 1.0) / (4.0 * n + 2.0);
-    double z = (1.0 - (n - 1.0) / (8.0 * n * n * n)) * std::cos(th);
-    for (int it = 0; it < 60; ++it) {
-      double P, dP;
-      legendre(n, z, P, dP);
-      const double dz = P / dP;
-      z -= dz;
-      if (std::fabs(dz) < 1e-17) break;
+// copy the compile-time operators for P nodes into the run-time table layout
+template <int P>
+void fill_tables(double* T) {
+  constexpr int Q = P + 1;
+  constexpr TabOff to = tab_off(P, Q);
+  constexpr const ops::Ops<P>& o = ops::kOps<P>;
+  for (int q = 0; q < Q; ++q) {
+    for (int j = 0; j < P; ++j) {
+      T[to.B + q * P + j] = o.B[q][j];
+      T[to.BT + j * Q + q] = o.B[q][j];
     }
-    double P, dP;
-    legendre(n, z, P, dP);
-    x[i] = z;
-    w[i] = 2.0 / ((1.0 - z * z) * dP * dP);
+    for (int r = 0; r < Q; ++r) T[to.DT + r * Q + q] = o.D[q][r];
+    T[to.WQ + q] = o.wg[q];
+    T[to.XQ + q] = o.xg[q];
+  }
+  for (int i = 0; i < P; ++i) {
+    for (int j = 0; j < P; ++j) T[to.MI + i * P + j] = o.MI[i][j];
+    T[to.XL + i] = o.xl[i];
+    T[to.WL + i] = o.wl[i];
+    for (int q = 0; q < Q; ++q) {
+      T[to.BTM + i * Q + q] = o.BTM[i][q];
+      T[to.BW + i * Q + q] = o.BW[i][q];
+      T[to.GW + i * Q + q] = o.GW[i][q];
+    }
+    T[to.MC + i] = o.MC[0][i];
+    T[to.MC + P + i] = o.MC[1][i];
   }
 }
 
-// Gauss-Lobatto-Legendre: interior nodes are the zeros of P'_N, one between
-// each pair of consecutive zeros of P_N (Rolle). Safeguarded Newton on
-// q = (1-x^2) P'_N, whose derivative is -N(N+1) P_N, inside that bracket.
-// Weights 2 / (N (N+1) P_N^2).
-void gll_rule(int n, std::vector<double>& x, std::vector<double>& w) {
-  const int N = n - 1;
-  x.assign(n, 0.0);
-  w.assign(n, 0.0);
-  x[0] = -1.0;
-  x[N] = 1.0;
-  std::vector<double> g, gw;
-  if (N >= 2) gauss_rule(N, g, gw);
-  for (int i = 1; i < N; ++i) {
-    double lo = g[i - 1], hi = g[i];
-    auto qf = [&](double z) {
-      double P, dP;
-      legendre(N, z, P, dP);
-      return (1.0 - z * z) * dP;
-    };
-    const double qlo = qf(lo);
-    double z = 0.5 * (lo + hi);
-    for (int it = 0; it < 200; ++it) {
-      double P, dP;
-      legendre(N, z, P, dP);
-      const double q = (1.0 - z * z) * dP;
-      if (q == 0.0) break;
-      if ((q > 0) == (qlo > 0))
-        lo = z;
-      else
-        hi = z;
-      const double dq = -N * (N + 1.0) * P;
-      double zn = z - q / dq;
-      if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
-      const double dz = zn - z;
-      z = zn;
-      if (std::fabs(dz) < 1e-17 || hi - lo < 1e-16) break;
-    }
-    x[i] = z;
+bool fill_tables(int P, double* T) {
+  switch (P) {
+    case 2: fill_tables<2>(T); return true;
+    case 3: fill_tables<3>(T); return true;
+    case 4: fill_tables<4>(T); return true;
+    case 5: fill_tables<5>(T); return true;
+    default: return false;
   }
-  for (int i = 0; i < n; ++i) {
-    double P, dP;
-    legendre(N, x[i], P, dP);
-    w[i] = 2.0 / (N * (N + 1.0) * P * P);
-  }
-}
-
-// barycentric Lagrange basis on `nodes` evaluated at x
-std::vector<double> bary_eval(const std::vector<double>& nodes, double x) {
-  const int n = (int)nodes.size();
-  std::vector<double> lam(n, 1.0), out(n, 0.0);
-  for (int j = 0; j < n; ++j)
-    for (int m = 0; m < n; ++m)
-      if (m != j) lam[j] /= (nodes[j] - nodes[m]);
-  for (int j = 0; j < n; ++j)
-    if (x == nodes[j]) {
-      out[j] = 1.0;
-      return out;
-    }
-  double den = 0.0;
-  for (int j = 0; j < n; ++j) den += lam[j] / (x - nodes[j]);
-  for (int j = 0; j < n; ++j) out[j] = lam[j] / (x - nodes[j]) / den;
-  return out;
-}
-
-// differentiation matrix D[i][j] = l_j'(x_i) on `nodes` (barycentric form)
-std::vector<double> bary_diff(const std::vector<double>& nodes) {
-  const int n = (int)nodes.size();
-  std::vector<double> lam(n, 1.0), Dm(n * n, 0.0);
-  for (int j = 0; j < n; ++j)
-    for (int m = 0; m < n; ++m)
-      if (m != j) lam[j] /= (nodes[j] - nodes[m]);
-  for (int i = 0; i < n; ++i) {
-    double diag = 0.0;
-    for (int j = 0; j < n; ++j) {
-      if (i == j) continue;
-      Dm[i * n + j] = (lam[j] / lam[i]) / (nodes[i] - nodes[j]);
-      diag -= Dm[i * n + j];
-    }
-    Dm[i * n + i] = diag;
-  }
-  return Dm;
-}
-
-// inverse of a symmetric positive definite matrix via Cholesky
-bool spd_inverse(int n, const std::vector<double>& A, std::vector<double>& Ai) {
-  std::vector<double> L(n * n, 0.0);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j <= i; ++j) {
-      double s = A[i * n + j];
-      for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
-      if (i == j) {
-        if (s <= 0.0) return false;
-        L[i * n + i] = std::sqrt(s);
-      } else {
-        L[i * n + j] = s / L[j * n + j];
-      }
-    }
-  Ai.assign(n * n, 0.0);
-  for (int c = 0; c < n; ++c) {
-    std::vector<double> y(n, 0.0);
-    for (int i = 0; i < n; ++i) {  // L y = e_c
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = 0; k < i; ++k) s -= L[i * n + k] * y[k];
-      y[i] = s / L[i * n + i];
-    }
-    for (int i = n - 1; i >= 0; --i) {  // L^T x = y
-      double s = y[i];
-      for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * Ai[k * n + c];
-      Ai[i * n + c] = s / L[i * n + i];
-    }
-  }
-  return true;
 }
 
 }  // namespace
@@ -221,6 +109,11 @@ Async make_async(const adg_ctx_s* c, int stage) {
   A.stage = stage;
   A.c_m = kSspC[stage];
   A.tol = c->as.learned_tol;
+  A.slot_n = c->R > 0 ? (int)(c->n % c->R) : 0;
+  unsigned mod = 1;
+  if (A.delay_kind == 1) mod = A.L + 1;
+  if (A.delay_kind == 2) mod = A.ghost == 1 ? A.L : A.L + A.Qh;
+  A.kmod = make_fastmod64(mod > 0 ? mod : 1);
   return A;
 }
 
@@ -414,6 +307,8 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
   }
   M.gamma = c.gamma;
   M.flux = c.flux;
+  for (int k = 0; k < 2; ++k) M.dnc[k] = make_fastdiv(M.nc[k]);
+  for (int k = 0; k < 3; ++k) M.dm[k] = make_fastdiv(M.m[k]);
   int off = 0;
   for (int f = 0; f < 6; ++f) {
     M.fs_off[f] = -1;
@@ -432,50 +327,12 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
   depth_of(x->as, x->R, x->Qh);
 
   // 1D tables
-  std::vector<double> xg, wg, xl, wl;
-  gauss_rule(x->Q, xg, wg);
-  gll_rule(x->P, xl, wl);
   const int P = x->P, Q = x->Q;
   const TabOff to = tab_off(P, Q);
   x->tab64.assign(to.total, 0.0);
-  double* T = x->tab64.data();
-  for (int q = 0; q < Q; ++q) {
-    std::vector<double> l = bary_eval(xl, xg[q]);
-    for (int j = 0; j < P; ++j) {
-      T[to.B + q * P + j] = l[j];
-      T[to.BT + j * Q + q] = l[j];
-    }
-  }
-  std::vector<double> Dg = bary_diff(xg);  // Dg[q][r] = l^G_r'(x_q)
-  for (int r = 0; r < Q; ++r)
-    for (int q = 0; q < Q; ++q) T[to.DT + r * Q + q] = Dg[q * Q + r];
-  std::vector<double> M1(P * P, 0.0), M1i;
-  for (int i = 0; i < P; ++i)
-    for (int j = 0; j < P; ++j)
-      for (int q = 0; q < Q; ++q) M1[i * P + j] += wg[q] * T[to.B + q * P + i] * T[to.B + q * P + j];
-  if (!spd_inverse(P, M1, M1i)) {
+  if (!fill_tables(P, x->tab64.data())) {
     delete x;
-    return fail(ADG_ERR_INVALID, "mass matrix not positive definite");
-  }
-  for (int i = 0; i < P * P; ++i) T[to.MI + i] = M1i[i];
-  for (int q = 0; q < Q; ++q) {
-    T[to.WQ + q] = wg[q];
-    T[to.XQ + q] = xg[q];
-  }
-  for (int j = 0; j < P; ++j) {
-    T[to.XL + j] = xl[j];
-    T[to.WL + j] = wl[j];
-  }
-  // inverse mass folded into the transposed interpolation: BTM = MI * BT,
-  // and the inverse mass applied to the face traces: columns 0 and P-1 of MI
-  for (int i = 0; i < P; ++i) {
-    for (int q = 0; q < Q; ++q) {
-      double a = 0.0;
-      for (int j = 0; j < P; ++j) a += M1i[i * P + j] * T[to.BT + j * Q + q];
-      T[to.BTM + i * Q + q] = a;
-    }
-    T[to.MC + i] = M1i[i * P + 0];
-    T[to.MC + P + i] = M1i[i * P + (P - 1)];
+    return fail(ADG_ERR_INVALID, "degree out of range");
   }
   // buffer plan
   x->ring_bytes = (size_t)x->R * (size_t)M.nfs * x->V * x->Fn * sizeof(double);

@@ -20,9 +20,10 @@ constexpr int kThreads = 256;
 // [P][P]; WQ: Gauss weights; XQ: Gauss points; XL/WL: GLL points/weights;
 // BTM = MI * BT [P][Q] (test functions followed by the inverse mass);
 // MC: the first and last columns of MI, [2][P] (inverse mass applied to the
-// trace of a face at -1 / +1).
+// trace of a face at -1 / +1); BW = BTM diag(WQ) [P][Q] and
+// GW = BTM DT diag(WQ) [P][Q] (the Gauss weights folded in).
 struct TabOff {
-  int B, BT, DT, MI, WQ, XQ, XL, WL, BTM, MC, total;
+  int B, BT, DT, MI, WQ, XQ, XL, WL, BTM, MC, BW, GW, total;
 };
 __host__ __device__ constexpr TabOff tab_off(int P, int Q) {
   return TabOff{0,
@@ -35,7 +36,43 @@ __host__ __device__ constexpr TabOff tab_off(int P, int Q) {
                 2 * Q * P + Q * Q + P * P + 2 * Q + P,
                 2 * Q * P + Q * Q + P * P + 2 * Q + 2 * P,
                 3 * Q * P + Q * Q + P * P + 2 * Q + 2 * P,
-                3 * Q * P + Q * Q + P * P + 2 * Q + 4 * P};
+                3 * Q * P + Q * Q + P * P + 2 * Q + 4 * P,
+                4 * Q * P + Q * Q + P * P + 2 * Q + 4 * P,
+                5 * Q * P + Q * Q + P * P + 2 * Q + 4 * P};
+}
+
+// Division by a divisor d >= 1 fixed at set-up, for dividends 0 <= x < 2^31:
+// with s = ceil(log2 d) and m = ceil(2^(31+s) / d) < 2^32, x / d equals
+// (x m) >> (31 + s) exactly, since the rounding error of m is below d and
+// x < 2^31 (the multiply-shift division of Granlund and Montgomery, 1994).
+struct FastDiv {
+  unsigned d, m, s;
+};
+inline FastDiv make_fastdiv(unsigned d) {
+  unsigned s = 0;
+  while ((1ull << s) < d) ++s;
+  const unsigned long long num = 1ull << (31 + s);
+  return FastDiv{d, (unsigned)((num + d - 1) / d), s};
+}
+__host__ __device__ inline unsigned fdiv(unsigned x, const FastDiv& f) {
+  return (unsigned)(((unsigned long long)x * f.m) >> (31 + f.s));
+}
+__host__ __device__ inline unsigned fmodu(unsigned x, const FastDiv& f) { return x - fdiv(x, f) * f.d; }
+
+// x mod d for any 64-bit x and 1 <= d <= 2^15, from x = a 2^62 + b 2^31 + c
+// (b, c < 2^31) and the residues of 2^31 and 2^62: every partial sum stays
+// below d^2 + 5d < 2^31.
+struct FastMod64 {
+  FastDiv f;
+  unsigned r31, r62;
+};
+inline FastMod64 make_fastmod64(unsigned d) {
+  const unsigned r31 = (unsigned)((1ull << 31) % d);
+  return FastMod64{make_fastdiv(d), r31, (unsigned)(((unsigned long long)r31 * r31) % d)};
+}
+__host__ __device__ inline unsigned fmod64(unsigned long long x, const FastMod64& g) {
+  const unsigned a = (unsigned)(x >> 62), b = (unsigned)((x >> 31) & 0x7fffffffu), c = (unsigned)(x & 0x7fffffffu);
+  return fmodu(a * g.r62 + fmodu(b, g.f) * g.r31 + fmodu(c, g.f), g.f);
 }
 
 // Structured periodic box, block partition into virtual subdomains, and the
@@ -59,6 +96,8 @@ struct Mesh {
   double detJf[3];   // face Jacobian for faces normal to axis a
   double gamma;
   int flux;
+  FastDiv dnc[2];  // division by nc[0], nc[1]
+  FastDiv dm[3];   // division by m[k]
 };
 
 // Asynchrony parameters for one stage.
@@ -72,7 +111,15 @@ struct Async {
   int stage;
   double c_m;        // stage time fraction
   double tol;        // learned accept bound
+  int slot_n;        // ring slot of level n (n mod R), 0 without a ring
+  FastMod64 kmod;    // the delay schedule's modulus: L+1 uniform, L caa-std, L+Qh caa-at
 };
+
+// ring slot of level n - back, for 0 <= back < R
+__host__ __device__ inline int ring_slot(const Async& A, int back) {
+  const int s = A.slot_n - back;
+  return s < 0 ? s + A.R : s;
+}
 
 // parameters of an analytic problem, passed by value
 struct Prm {
@@ -89,15 +136,18 @@ __host__ __device__ inline long long elem_index(const Mesh& M, int i, int j, int
   return (long long)i + (long long)M.nc[0] * ((long long)j + (long long)M.nc[1] * k);
 }
 
+// element coordinates of element index e (0 <= e < E <= 2^31)
 __host__ __device__ inline void elem_coords(const Mesh& M, long long e, int* c) {
-  c[0] = (int)(e % M.nc[0]);
-  long long r = e / M.nc[0];
-  c[1] = (int)(r % M.nc[1]);
-  c[2] = (int)(r / M.nc[1]);
+  const unsigned u = (unsigned)e;
+  const unsigned r = fdiv(u, M.dnc[0]);
+  c[0] = (int)(u - r * (unsigned)M.nc[0]);
+  const unsigned z = fdiv(r, M.dnc[1]);
+  c[1] = (int)(r - z * (unsigned)M.nc[1]);
+  c[2] = (int)z;
 }
 
 __host__ __device__ inline int subdomain_of(const Mesh& M, const int* c) {
-  return c[0] / M.m[0] + M.parts[0] * (c[1] / M.m[1] + M.parts[1] * (c[2] / M.m[2]));
+  return (int)(fdiv(c[0], M.dm[0]) + M.parts[0] * (fdiv(c[1], M.dm[1]) + M.parts[1] * fdiv(c[2], M.dm[2])));
 }
 
 // neighbour of element coords c across face f (periodic)
@@ -114,12 +164,12 @@ __host__ __device__ inline long long neighbour(const Mesh& M, const int* c, int 
 __host__ __device__ inline long long face_side(const Mesh& M, const int* c, int f) {
   int a = f >> 1;
   if (M.parts[a] < 2) return -1;
-  int l = c[a] % M.m[a];
+  const int l = (int)fmodu(c[a], M.dm[a]);
   if ((f & 1) ? (l != M.m[a] - 1) : (l != 0)) return -1;
-  int o0 = a == 0 ? 1 : 0;
-  int o1 = a == 2 ? 1 : 2;
-  long long li = c[o0] % M.m[o0];
-  if (M.dim == 3) li += (long long)M.m[o0] * (c[o1] % M.m[o1]);
+  const int o0 = a == 0 ? 1 : 0;
+  const int o1 = a == 2 ? 1 : 2;
+  long long li = fmodu(c[o0], M.dm[o0]);
+  if (M.dim == 3) li += (long long)M.m[o0] * fmodu(c[o1], M.dm[o1]);
   return (long long)subdomain_of(M, c) * M.fs_sub + M.fs_off[f] + li;
 }
 
@@ -164,11 +214,11 @@ __host__ __device__ inline int delay_of(const Mesh& M, const Async& A, int sub, 
     unsigned long long idx =
         ((unsigned long long)A.n * (unsigned long long)M.nsub + (unsigned long long)sub) * (2ull * M.dim) +
         (unsigned long long)f;
-    k = (long long)(splitmix64(A.seed, idx) % (unsigned long long)(A.L + 1));
+    k = fmod64(splitmix64(A.seed, idx), A.kmod);  // mod (L + 1)
   } else if (A.ghost == 1) {
-    k = A.L > 0 ? A.n % A.L : 0;  // Alg. caa-std
+    k = fmod64((unsigned long long)A.n, A.kmod);  // Alg. caa-std: n mod L
   } else {
-    long long per = A.L + A.Qh, r = A.n % per;  // Alg. caa-at
+    const long long r = fmod64((unsigned long long)A.n, A.kmod);  // Alg. caa-at: n mod (L + Q)
     k = r < A.Qh ? 0 : r - A.Qh + 1;
   }
   long long cap = A.n_rel - A.Qh + 1;
@@ -187,9 +237,11 @@ enum GhostSrc { kSrcLive = 0, kSrcRing = 1, kSrcGhost = 2 };
 hipError_t launch_rhs_stage(int dim, int degree, int precision, const Mesh& M, const Async& A, const Stage& S,
                             const double* u_in, const double* u_n, double* out, int src, double* ring,
                             const double* ghost, const double* tab64, const float* tab32, hipStream_t st);
-hipError_t launch_ghost(int dim, int degree, const Mesh& M, const Async& A, const double* u_in, const double* u_n,
-                        double* ring, double* ghost, const float* mlp, int publish, double* stats,
-                        hipStream_t st);
+// the d = 2 stage kernel (register-resident variables, one wavefront per 16
+// elements); launch_rhs_stage forwards to it for quadrilateral meshes
+hipError_t launch_rhs_stage_2d(int degree, int precision, const Mesh& M, const Async& A, const Stage& S,
+                               const double* u_in, const double* u_n, double* out, int src, double* ring,
+                               const double* ghost, hipStream_t st);
 hipError_t launch_init(int dim, int degree, const Mesh& M, int problem, const Prm& prm, double* u,
                        const double* tab64, hipStream_t st);
 hipError_t launch_norms(int dim, int degree, const Mesh& M, int what, int problem, const Prm& prm, double t,

@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
     const long long nb = neighbour(M, cc, f);
     const long long src = nb * V * Pd + face_node_l<D, P>(f ^ 1, j);
     if (publish)
-      for (int v = g; v < V; v += 4) ring[(A.n % A.R) * total + (fs * V + v) * Fn + j] = u_n[src + v * Pd];
+      for (int v = g; v < V; v += 4) ring[A.slot_n * total + (fs * V + v) * Fn + j] = u_n[src + v * Pd];
     k = delay_of(M, A, subdomain_of(M, cc), f);
 #pragma unroll
     for (int v = 0; v < V; ++v) live[v] = u_in[src + v * Pd];
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
 #pragma unroll
       for (int lv = 0; lv < kMlpK; ++lv)
 #pragma unroll
-        for (int v = 0; v < V; ++v) T[lv][v] = ring[((A.n - k - lv) % A.R) * total + (fs * V + v) * Fn + j];
+        for (int v = 0; v < V; ++v) T[lv][v] = ring[ring_slot(A, k + lv) * total + (fs * V + v) * Fn + j];
       const double tau = k + A.c_m;
       for (int lv = 0; lv < A.levels; ++lv) {
         const double wl = at_w(lv, A.levels, tau);

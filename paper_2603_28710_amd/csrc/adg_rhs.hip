@@ -215,12 +215,8 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
   // per element face: neighbour, PE face-side, delay, and the face-side it feeds
   for (int t = tid; t < ne * nf; t += kThreads) {
     const int le = t / nf, f = t - le * nf;
-    const unsigned e = (unsigned)(e0 + le);
     int c[3];
-    c[0] = (int)(e % (unsigned)M.nc[0]);
-    const unsigned r = e / (unsigned)M.nc[0];
-    c[1] = (int)(r % (unsigned)M.nc[1]);
-    c[2] = (int)(r / (unsigned)M.nc[1]);
+    elem_coords(M, e0 + le, c);
     const long long nb = neighbour(M, c, f);
     sNb[t] = nb * V * Pd;
     const long long fs = async_on ? face_side(M, c, f) : -1;
@@ -229,18 +225,29 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
     long long pub = -1;
     if (publish && fs >= 0) {
       int cn[3];
-      const unsigned en = (unsigned)nb;
-      cn[0] = (int)(en % (unsigned)M.nc[0]);
-      const unsigned rn = en / (unsigned)M.nc[0];
-      cn[1] = (int)(rn % (unsigned)M.nc[1]);
-      cn[2] = (int)(rn / (unsigned)M.nc[1]);
+      elem_coords(M, nb, cn);
       pub = face_side(M, cn, f ^ 1) * V * Fn;
     }
     sPub[t] = pub;
   }
   for (int i = tid; i < to.total; i += kThreads) sT[i] = tab[i];
+  // the stage input into LDS; u_n (and, for T = float, the FP64 input) for
+  // the combine into registers now, so their latency hides behind the compute
   const double* gin = u_in + e0 * Dm::SZP;
-  for (int i = tid; i < ne * Dm::SZP; i += kThreads) sU[i] = (T)gin[i];
+  const double* gn = u_n + e0 * Dm::SZP;
+  constexpr int CPT = (NE * Dm::SZP + kThreads - 1) / kThreads;
+  double ur[CPT], un[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int i = tid + k * kThreads;
+    ur[k] = un[k] = 0.0;
+    if (i < ne * Dm::SZP) {
+      const double x = gin[i];
+      sU[i] = (T)x;
+      if (sizeof(T) == 4) ur[k] = x;
+      if (S.a != 0.0) un[k] = gn[i];
+    }
+  }
   __syncthreads();
 
   // stage 0 of a step: publish this block's PE-boundary traces of u^n into
@@ -248,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
   // reader of this launch touches that slot: delays >= 1 read older levels,
   // delay 0 reads the live values.
   if (publish) {
-    double* slot = ring + (A.n % A.R) * ring_level;
+    double* slot = ring + A.slot_n * ring_level;
     for (int i = tid; i < ne * nf * Fn; i += kThreads) {
       const int j = i % Fn;
       const int t = i / Fn;
@@ -257,21 +264,24 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
       const int le = t / nf, f = t - le * nf;
       const int node = face_node<D, P>(f, j);
 #pragma unroll
-      for (int v = 0; v < V; ++v) slot[pub + v * Fn + j] = gin[(le * V + v) * Pd + node];
+      for (int v = 0; v < V; ++v) {
+        const int q = (le * V + v) * Pd + node;
+        slot[pub + v * Fn + j] = sizeof(T) == 8 ? (double)sU[q] : gin[q];
+      }
     }
   }
 
   // ---- volume: interpolation to the Gauss points (result in sB1)
   if constexpr (D == 2) {
-    sweep<T, P, Q, P, P, 1, 0, false>(sU, sB2, tab + to.B, ne * V);
+    sweep<T, P, Q, P, P, 1, 0, false>(sU, sB2, tab + to.B, NE * V);
     __syncthreads();
-    sweep<T, P, Q, Q, P, 1, 1, false>(sB2, sB1, tab + to.B, ne * V);
+    sweep<T, P, Q, Q, P, 1, 1, false>(sB2, sB1, tab + to.B, NE * V);
   } else {
-    sweep<T, P, Q, P, P, P, 0, false>(sU, sB1, tab + to.B, ne * V);
+    sweep<T, P, Q, P, P, P, 0, false>(sU, sB1, tab + to.B, NE * V);
     __syncthreads();
-    sweep<T, P, Q, Q, P, P, 1, false>(sB1, sB2, tab + to.B, ne * V);
+    sweep<T, P, Q, Q, P, P, 1, false>(sB1, sB2, tab + to.B, NE * V);
     __syncthreads();
-    sweep<T, P, Q, Q, Q, P, 2, false>(sB2, sB1, tab + to.B, ne * V);
+    sweep<T, P, Q, Q, Q, P, 2, false>(sB2, sB1, tab + to.B, NE * V);
   }
   __syncthreads();
 
@@ -282,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
 #pragma unroll
   for (int k = 0; k < QPT; ++k) {
     const int idx = tid + k * kThreads;
-    if (idx < ne * Qd) {
+    if (idx < NE * Qd) {
       const int le = idx / Qd, q = idx - le * Qd;
       T w[V];
 #pragma unroll
@@ -312,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
 #pragma unroll
     for (int k = 0; k < QPT; ++k) {
       const int idx = tid + k * kThreads;
-      if (idx < ne * Qd) {
+      if (idx < NE * Qd) {
         const int le = idx / Qd, q = idx - le * Qd;
 #pragma unroll
         for (int v = 0; v < V; ++v) sB1[(le * V + v) * Qd + q] = F[k][a][v];
@@ -321,30 +331,30 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
     __syncthreads();
     if (D == 2) {
       if (a == 0)
-        sweep<T, Q, Q, Q, Q, 1, 0, false>(sB1, sB2, tab + to.DT, ne * V);
+        sweep<T, Q, Q, Q, Q, 1, 0, false>(sB1, sB2, tab + to.DT, NE * V);
       else
-        sweep<T, Q, Q, Q, Q, 1, 1, true>(sB1, sB2, tab + to.DT, ne * V);
+        sweep<T, Q, Q, Q, Q, 1, 1, true>(sB1, sB2, tab + to.DT, NE * V);
     } else {
       if (a == 0)
-        sweep<T, Q, Q, Q, Q, Q, 0, false>(sB1, sB2, tab + to.DT, ne * V);
+        sweep<T, Q, Q, Q, Q, Q, 0, false>(sB1, sB2, tab + to.DT, NE * V);
       else if (a == 1)
-        sweep<T, Q, Q, Q, Q, Q, 1, true>(sB1, sB2, tab + to.DT, ne * V);
+        sweep<T, Q, Q, Q, Q, Q, 1, true>(sB1, sB2, tab + to.DT, NE * V);
       else
-        sweep<T, Q, Q, Q, Q, Q, 2, true>(sB1, sB2, tab + to.DT, ne * V);
+        sweep<T, Q, Q, Q, Q, Q, 2, true>(sB1, sB2, tab + to.DT, NE * V);
     }
     __syncthreads();
   }
   // test functions and inverse mass in one: BTM sweeps, k_volume in sR
   if constexpr (D == 2) {
-    sweep<T, Q, P, Q, Q, 1, 0, false>(sB2, sB1, tab + to.BTM, ne * V);
+    sweep<T, Q, P, Q, Q, 1, 0, false>(sB2, sB1, tab + to.BTM, NE * V);
     __syncthreads();
-    sweep<T, Q, P, P, Q, 1, 1, false>(sB1, sR, tab + to.BTM, ne * V);
+    sweep<T, Q, P, P, Q, 1, 1, false>(sB1, sR, tab + to.BTM, NE * V);
   } else {
-    sweep<T, Q, P, Q, Q, Q, 0, false>(sB2, sB1, tab + to.BTM, ne * V);
+    sweep<T, Q, P, Q, Q, Q, 0, false>(sB2, sB1, tab + to.BTM, NE * V);
     __syncthreads();
-    sweep<T, Q, P, P, Q, Q, 1, false>(sB1, sB2, tab + to.BTM, ne * V);
+    sweep<T, Q, P, P, Q, Q, 1, false>(sB1, sB2, tab + to.BTM, NE * V);
     __syncthreads();
-    sweep<T, Q, P, P, P, Q, 2, false>(sB2, sR, tab + to.BTM, ne * V);
+    sweep<T, Q, P, P, P, Q, 2, false>(sB2, sR, tab + to.BTM, NE * V);
   }
   __syncthreads();
 
@@ -354,19 +364,20 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
   T* sTr = sB1;
   T* sTq = sTr + NE * Dm::TR;
   T* sTm = sTq + NE * Dm::TQ;
-  const int HALF_R = ne * NS * V * Fn, HALF_Q = ne * NS * V * Fq;  // start of the neighbour half
+  constexpr int HALF_R = NE * NS * V * Fn, HALF_Q = NE * NS * V * Fq;  // start of the neighbour half
 #pragma unroll 1
   for (int pass = 0; pass < nf / NS; ++pass) {
     const int a = (pass * NS) >> 1;
     const int s0 = (pass * NS) & 1;
     // gather own (side 0) and neighbour (side 1) face-node values; one item
     // per (side, element, face, node), all V variables
-    for (int i = tid; i < 2 * ne * NS * Fn; i += kThreads) {
+    for (int i = tid; i < 2 * NE * NS * Fn; i += kThreads) {
       const int j = i % Fn;
       const int r = i / Fn;
-      const int ls = r % (ne * NS);  // le * NS + (s - s0)
-      const int side = r / (ne * NS);
+      const int ls = r % (NE * NS);  // le * NS + (s - s0)
+      const int side = r / (NE * NS);
       const int le = ls / NS, s = ls - le * NS + s0;
+      if (le >= ne) continue;  // past the last element
       const int f = 2 * a + s;
       T* dst = sTr + side * HALF_R + ls * V * Fn + j;
       if (side == 0) {
@@ -389,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
         for (int v = 0; v < V; ++v) dst[v * Fn] = (T)g[v * Fn];
       } else if (A.ghost == 1) {
         // standard flux on the trace k steps old (eq. delayed-flux)
-        const double* g = ring + ((A.n - k) % A.R) * ring_level + fs + j;
+        const double* g = ring + ring_slot(A, k) * ring_level + fs + j;
 #pragma unroll
         for (int v = 0; v < V; ++v) dst[v * Fn] = (T)g[v * Fn];
       } else {
@@ -401,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
         for (int v = 0; v < V; ++v) acc[v] = 0.0;
         for (int l = 0; l < A.levels; ++l) {
           const double wl = at_weight_rhs(l, A.levels, tau);
-          const double* g = ring + ((A.n - k - l) % A.R) * ring_level + fs + j;
+          const double* g = ring + ring_slot(A, k + l) * ring_level + fs + j;
 #pragma unroll
           for (int v = 0; v < V; ++v) acc[v] += wl * g[v * Fn];
         }
@@ -412,15 +423,15 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
     __syncthreads();
     // interpolation to the face points (both sides at once)
     if constexpr (D == 2) {
-      sweep<T, P, Q, P, 1, 1, 0, false>(sTr, sTq, tab + to.B, 2 * ne * NS * V);
+      sweep<T, P, Q, P, 1, 1, 0, false>(sTr, sTq, tab + to.B, 2 * NE * NS * V);
     } else {
-      sweep<T, P, Q, P, P, 1, 0, false>(sTr, sTm, tab + to.B, 2 * ne * NS * V);
+      sweep<T, P, Q, P, P, 1, 0, false>(sTr, sTm, tab + to.B, 2 * NE * NS * V);
       __syncthreads();
-      sweep<T, P, Q, Q, P, 1, 1, false>(sTm, sTq, tab + to.B, 2 * ne * NS * V);
+      sweep<T, P, Q, Q, P, 1, 1, false>(sTm, sTq, tab + to.B, 2 * NE * NS * V);
     }
     __syncthreads();
     // numerical flux at every face point, in place of the own values
-    for (int i = tid; i < ne * NS * Fq; i += kThreads) {
+    for (int i = tid; i < NE * NS * Fq; i += kThreads) {
       const int fq = i % Fq;
       const int r = i / Fq;
       const int s = r % NS + s0, le = r / NS;
@@ -447,15 +458,15 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
     __syncthreads();
     // lift with BTM to the face nodes (own half only), result in sTr
     if constexpr (D == 2) {
-      sweep<T, Q, P, Q, 1, 1, 0, false>(sTq, sTr, tab + to.BTM, ne * NS * V);
+      sweep<T, Q, P, Q, 1, 1, 0, false>(sTq, sTr, tab + to.BTM, NE * NS * V);
     } else {
-      sweep<T, Q, P, Q, Q, 1, 0, false>(sTq, sTm, tab + to.BTM, ne * NS * V);
+      sweep<T, Q, P, Q, Q, 1, 0, false>(sTq, sTm, tab + to.BTM, NE * NS * V);
       __syncthreads();
-      sweep<T, Q, P, P, Q, 1, 1, false>(sTm, sTr, tab + to.BTM, ne * NS * V);
+      sweep<T, Q, P, P, Q, 1, 1, false>(sTm, sTr, tab + to.BTM, NE * NS * V);
     }
     __syncthreads();
     // inverse mass along a: k += MC_side[i_a] * lifted(j)
-    for (int i = tid; i < ne * Dm::SZP; i += kThreads) {
+    for (int i = tid; i < NE * Dm::SZP; i += kThreads) {
       const int node = i % Pd;
       const int r = i / Pd;
       const int v = r % V, le = r / V;
@@ -475,12 +486,14 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
 
   // ---- SSP-RK3 combine in FP64
   double* gout = out + e0 * Dm::SZP;
-  const double* gn = u_n + e0 * Dm::SZP;
-  for (int i = tid; i < ne * Dm::SZP; i += kThreads) {
-    const double k = (double)sR[i];
-    const double ui = sizeof(T) == 8 ? (double)sU[i] : gin[i];
-    const double y = ui + S.dt * k;
-    gout[i] = S.a == 0.0 ? S.b * y : S.a * gn[i] + S.b * y;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int i = tid + k * kThreads;
+    if (i < ne * Dm::SZP) {
+      const double ui = sizeof(T) == 8 ? (double)sU[i] : ur[k];
+      const double y = ui + S.dt * (double)sR[i];
+      gout[i] = S.a == 0.0 ? S.b * y : S.a * un[k] + S.b * y;
+    }
   }
 }
 
@@ -503,7 +516,6 @@ static hipError_t launch_rhs_prec(int dim, int degree, const Mesh& M, const Asyn
                                   const double* ghost, const T* tab, hipStream_t st) {
 #define ADG_RHS_CASE(d, p) \
   if (dim == d && degree == p) return launch_rhs_t<T, d, p>(M, A, S, u_in, u_n, out, src, ring, ghost, tab, st);
-  ADG_RHS_CASE(2, 1) ADG_RHS_CASE(2, 2) ADG_RHS_CASE(2, 3) ADG_RHS_CASE(2, 4)
   ADG_RHS_CASE(3, 1) ADG_RHS_CASE(3, 2) ADG_RHS_CASE(3, 3) ADG_RHS_CASE(3, 4)
 #undef ADG_RHS_CASE
   return hipErrorInvalidValue;
@@ -512,6 +524,8 @@ static hipError_t launch_rhs_prec(int dim, int degree, const Mesh& M, const Asyn
 hipError_t launch_rhs_stage(int dim, int degree, int precision, const Mesh& M, const Async& A, const Stage& S,
                             const double* u_in, const double* u_n, double* out, int src, double* ring,
                             const double* ghost, const double* tab64, const float* tab32, hipStream_t st) {
+  if (dim == 2)
+    return launch_rhs_stage_2d(degree, precision, M, A, S, u_in, u_n, out, src, ring, ghost, st);
   if (precision == 1)
     return launch_rhs_prec<float>(dim, degree, M, A, S, u_in, u_n, out, src, ring, ghost, tab32, st);
   return launch_rhs_prec<double>(dim, degree, M, A, S, u_in, u_n, out, src, ring, ghost, tab64, st);

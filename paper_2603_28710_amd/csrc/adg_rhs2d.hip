@@ -1,0 +1,394 @@
+// adg_rhs2d.hip — the fused SSP-RK3 stage on quadrilateral meshes (d = 2).
+//
+// One wavefront owns 16 consecutive elements (x fastest). Lane (e, v) keeps
+// the P^2 nodal values of variable v of element e in registers and applies
+// every tensor-product operator of that variable there; LDS carries only the
+// exchanges that the nonlinear fluxes need (all V variables at one point).
+//
+//   volume: the lane interpolates its variable to the Q^2 Gauss points
+//           (x, then y) and stores it in LDS. Row by row of Gauss points, it
+//           then reads the full state, forms its own components F_x[v] and
+//           F_y[v] of the Euler flux (eq. euler-dealii) and accumulates
+//             k += (2/h_x) (GW (x) BW) F_x + (2/h_y) (BW (x) GW) F_y,
+//           with BW = M1^{-1} B^T W and GW = M1^{-1} B^T D^T W: the test
+//           functions, the collocation derivative on the Gauss points, the
+//           Gauss weights and the inverse 1D mass as one operator each
+//           (eq. weakform-dealii / weakform-compact-dealii; |J| cancels).
+//   faces:  per axis, every lane interpolates its own and the neighbour's
+//           face traces (live values, or the delayed / AT / learned trace at a
+//           PE-boundary face) to the Gauss points of both faces; one lane per
+//           (element, face, point) evaluates the local Lax-Friedrichs flux of
+//           eq. lfflux / lfflux-lambda in canonical (left, right) order, in
+//           place; every lane lifts its variable with BW and adds the column
+//           of M1^{-1} at that face.
+//   stage:  out = a u_n + b (u_in + dt k) in FP64 from the FP64 registers.
+//
+// Both sides of an interior face evaluate the flux with the same instruction
+// stream on identical operands, so their contributions are bitwise opposite.
+// At stage 0 of a step (stale and AT modes) the kernel also publishes its
+// PE-boundary traces of u^n into ring slot n mod R; readers in the same launch
+// use only older slots (delay >= 1) or live values (delay 0).
+// T = double (FP64 path) or float (FP32 contractions, FP64 state and combine).
+#include "adg_internal.h"
+#include "adg_tables.h"
+
+namespace adg {
+
+namespace {
+
+constexpr int kNE2 = 16;  // elements per wavefront (V = 4 lanes each)
+
+__device__ __forceinline__ double fmx2(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmx2(float a, float b, float c) { return fmaf(a, b, c); }
+
+// 1/x to an ulp or two: the hardware estimate refined by Newton steps (two in
+// FP64, one in FP32); every use of a given operand gives the same result
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// logical block index, XCD-aware (consecutive blocks go round-robin to the 8
+// XCDs; each XCD walks one contiguous range of elements)
+__device__ __forceinline__ int xcd_block2() {
+  const int nb = gridDim.x, i = blockIdx.x;
+  const int per = nb / 8, rem = nb % 8, x = i % 8, k = i / 8;
+  return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
+// AT weight of level l of nlev at fractional delay tau (Lagrange
+// extrapolation, the solution of eq. at-flux-constraints)
+__device__ __forceinline__ double at_w2(int l, int nlev, double tau) {
+  double w = 1.0;
+  for (int i = 0; i < nlev; ++i)
+    if (i != l) w *= (tau + i) / (double)(i - l);
+  return w;
+}
+
+// node index of face-local node j on face f (2D, x fastest)
+template <int P>
+__device__ __forceinline__ constexpr int fnode(int f, int j) {
+  return (f >> 1) == 0 ? j * P + ((f & 1) ? P - 1 : 0) : ((f & 1) ? P - 1 : 0) * P + j;
+}
+
+// n.F^ for n = +e_a, left state wl, right state wr (LLF or Rusanov speed)
+template <typename T>
+__device__ __forceinline__ void flux_llf(const T* wl, const T* wr, int a, T gamma, int kind, T* G) {
+  const T gm1 = gamma - (T)1;
+  const T il = recip(wl[0]), ir = recip(wr[0]);
+  const T ml2 = fmx2(wl[2], wl[2], wl[1] * wl[1]), mr2 = fmx2(wr[2], wr[2], wr[1] * wr[1]);
+  const T pl = gm1 * (wl[3] - (T)0.5 * ml2 * il), pr = gm1 * (wr[3] - (T)0.5 * mr2 * ir);
+  const T ual = wl[1 + a] * il, uar = wr[1 + a] * ir;
+  T Fl[4], Fr[4];
+  Fl[0] = wl[1 + a];
+  Fr[0] = wr[1 + a];
+  Fl[1] = wl[1] * ual + (a == 0 ? pl : (T)0);
+  Fr[1] = wr[1] * uar + (a == 0 ? pr : (T)0);
+  Fl[2] = wl[2] * ual + (a == 1 ? pl : (T)0);
+  Fr[2] = wr[2] * uar + (a == 1 ? pr : (T)0);
+  Fl[3] = (wl[3] + pl) * ual;
+  Fr[3] = (wr[3] + pr) * uar;
+  const T cl2 = gamma * pl * il, cr2 = gamma * pr * ir;
+  T lam;
+  if (kind == 1) {
+    const T sl = fabs(ual) + sqrt(cl2), sr = fabs(uar) + sqrt(cr2);
+    lam = sl > sr ? sl : sr;
+  } else {
+    const T sl = ml2 * il * il + cl2, sr = mr2 * ir * ir + cr2;
+    lam = (T)0.5 * sqrt(sl > sr ? sl : sr);
+  }
+  const T hl = (T)0.5 * lam;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) G[v] = (T)0.5 * (Fl[v] + Fr[v]) + hl * (wl[v] - wr[v]);
+}
+
+template <int P>
+__device__ __forceinline__ void load_col(const double* __restrict__ p, double* u) {
+  constexpr int Pd = P * P;
+  if constexpr (Pd % 2 == 0) {
+    const double2* p2 = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int i = 0; i < Pd / 2; ++i) {
+      const double2 x = p2[i];
+      u[2 * i] = x.x;
+      u[2 * i + 1] = x.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Pd; ++i) u[i] = p[i];
+  }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage S, const double* __restrict__ u_in,
+                                                         const double* u_n, double* out, int src,
+                                                         double* __restrict__ ring,
+                                                         const double* __restrict__ ghost) {
+  constexpr int Q = P + 1, V = 4, NE = kNE2, Pd = P * P, Qd = Q * Q;
+  constexpr ops::Ops<P> O = ops::make_ops<P>();
+  // per element: the state at the Gauss points [Qd][V], later the face
+  // traces [face s][side][Q][V] of one axis
+  constexpr int PER = Qd * V > 16 * Q ? Qd * V : 16 * Q;
+  __shared__ __align__(16) T sX[NE * PER];
+
+  const int lane = threadIdx.x, le = lane >> 2, v = lane & 3;
+  const long long e = (long long)xcd_block2() * NE + le;
+  const bool valid = e < M.E;
+  const long long col = (valid ? e : 0) * (V * Pd) + v * Pd;  // this lane's P^2 values
+
+  double u[Pd];
+  if (valid) {
+    load_col<P>(u_in + col, u);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Pd; ++i) u[i] = 0.0;
+  }
+
+  // ---- volume: interpolation to the Gauss points, x then y
+  {
+    T X[P][Q];
+#pragma unroll
+    for (int iy = 0; iy < P; ++iy)
+#pragma unroll
+      for (int qx = 0; qx < Q; ++qx) {
+        T acc = (T)O.B[qx][0] * (T)u[iy * P];
+#pragma unroll
+        for (int ix = 1; ix < P; ++ix) acc = fmx2((T)O.B[qx][ix], (T)u[iy * P + ix], acc);
+        X[iy][qx] = acc;
+      }
+    T* dst = sX + le * PER + v;
+#pragma unroll
+    for (int qy = 0; qy < Q; ++qy)
+#pragma unroll
+      for (int qx = 0; qx < Q; ++qx) {
+        T acc = (T)O.B[qy][0] * X[0][qx];
+#pragma unroll
+        for (int iy = 1; iy < P; ++iy) acc = fmx2((T)O.B[qy][iy], X[iy][qx], acc);
+        dst[(qy * Q + qx) * V] = acc;
+      }
+  }
+  __syncthreads();
+
+  // ---- volume: flux components of this lane's variable, tested row by row
+  T k[Pd];
+#pragma unroll
+  for (int i = 0; i < Pd; ++i) k[i] = (T)0;
+  {
+    const T gm1 = (T)M.gamma - (T)1;
+    const T sx = (T)(2.0 / M.h[0]), sy = (T)(2.0 / M.h[1]);
+    const T e1 = v == 1 ? (T)1 : (T)0, e2 = v == 2 ? (T)1 : (T)0, e3 = v == 3 ? (T)1 : (T)0;
+    const T* row = sX + le * PER;
+    // one Gauss row per iteration keeps the live state small; the
+    // row-dependent operator entries come from the device copy of the table
+    const ops::Ops<P>& OD = ops::kOps<P>;
+#pragma unroll 1
+    for (int qy = 0; qy < Q; ++qy) {
+      T tx[P], ty[P];
+#pragma unroll
+      for (int qx = 0; qx < Q; ++qx) {
+        const T* w = row + (qy * Q + qx) * V;
+        const T rho = w[0], mx = w[1], my = w[2], en = w[3];
+        const T wv = w[v];
+        const T ir = recip(rho);
+        const T ux = mx * ir, uy = my * ir;
+        const T p = gm1 * (en - (T)0.5 * fmx2(my, uy, mx * ux));
+        const T t = fmx2(p, e3, wv);
+        // F_x[v] = u_x (w_v + p [v=3]) + p [v=1], F_y alike
+        const T fx = fmx2(ux, t, p * e1);
+        const T fy = fmx2(uy, t, p * e2);
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          if (qx == 0) {
+            tx[i] = (T)O.GW[i][0] * fx;
+            ty[i] = (T)O.BW[i][0] * fy;
+          } else {
+            tx[i] = fmx2((T)O.GW[i][qx], fx, tx[i]);
+            ty[i] = fmx2((T)O.BW[i][qx], fy, ty[i]);
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        tx[i] *= sx;
+        ty[i] *= sy;
+      }
+#pragma unroll
+      for (int iy = 0; iy < P; ++iy) {
+        const T bw = (T)OD.BW[iy][qy], gw = (T)OD.GW[iy][qy];
+#pragma unroll
+        for (int ix = 0; ix < P; ++ix) k[iy * P + ix] = fmx2(gw, ty[ix], fmx2(bw, tx[ix], k[iy * P + ix]));
+      }
+    }
+  }
+
+  // ---- per-face neighbour data: element, PE face-side, delay
+  int c[3] = {0, 0, 0};
+  if (valid) elem_coords(M, e, c);
+  const bool async_on = src != kSrcLive && M.nfs > 0;
+  const long long ring_level = M.nfs * V * P;
+  const bool publish = src == kSrcRing && A.stage == 0;
+
+  // ---- faces, one axis per pass
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    __syncthreads();  // sX is rewritten
+    // own and neighbour traces of variable v at the Gauss points of both faces
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int f = 2 * a + s;
+      double g[P];  // neighbour trace at the face nodes
+#pragma unroll
+      for (int j = 0; j < P; ++j) g[j] = 0.0;
+      if (valid) {
+        const long long nb = neighbour(M, c, f);
+        const long long fs = async_on ? face_side(M, c, f) : -1;
+        int kd = 0;
+        if (fs >= 0 && src == kSrcRing) kd = delay_of(M, A, subdomain_of(M, c), f);
+        if (fs >= 0 && publish) {
+          int cn[3];
+          elem_coords(M, nb, cn);
+          double* dst = ring + A.slot_n * ring_level + face_side(M, cn, f ^ 1) * V * P + v * P;
+#pragma unroll
+          for (int j = 0; j < P; ++j) dst[j] = u[fnode<P>(f, j)];
+        }
+        if (fs < 0 || (src == kSrcRing && kd == 0)) {
+          const double* gp = u_in + nb * (V * Pd) + v * Pd;
+#pragma unroll
+          for (int j = 0; j < P; ++j) g[j] = gp[fnode<P>(f ^ 1, j)];
+        } else if (src == kSrcGhost) {
+          const double* gp = ghost + fs * V * P + v * P;
+#pragma unroll
+          for (int j = 0; j < P; ++j) g[j] = gp[j];
+        } else if (A.ghost == 1) {
+          // standard flux on the trace kd steps old (eq. delayed-flux)
+          const double* gp = ring + ring_slot(A, kd) * ring_level + fs * V * P + v * P;
+#pragma unroll
+          for (int j = 0; j < P; ++j) g[j] = gp[j];
+        } else {
+          // AT extrapolation to the stage time, tau = kd + c_m (eq. at-flux)
+          const double tau = kd + A.c_m;
+          for (int l = 0; l < A.levels; ++l) {
+            const double wl = at_w2(l, A.levels, tau);
+            const double* gp = ring + ring_slot(A, kd + l) * ring_level + fs * V * P + v * P;
+#pragma unroll
+            for (int j = 0; j < P; ++j) g[j] = fma(wl, gp[j], g[j]);
+          }
+        }
+      }
+      T* dst = sX + le * PER + s * (2 * Q * V) + v;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        T o = (T)O.B[q][0] * (T)u[fnode<P>(f, 0)];
+        T n = (T)O.B[q][0] * (T)g[0];
+#pragma unroll
+        for (int j = 1; j < P; ++j) {
+          o = fmx2((T)O.B[q][j], (T)u[fnode<P>(f, j)], o);
+          n = fmx2((T)O.B[q][j], (T)g[j], n);
+        }
+        dst[q * V] = o;
+        dst[(Q + q) * V] = n;
+      }
+    }
+    __syncthreads();
+    // numerical flux, one lane per (element, face, point), in place of the
+    // own trace, scaled by -(n.e_a) 2/h_a
+    {
+      const T gamma = (T)M.gamma;
+      const T sc = (T)(2.0 / M.h[a]);
+#pragma unroll
+      for (int it = 0; it < (NE * 2 * Q + 63) / 64; ++it) {
+        const int t = lane + 64 * it;
+        if (t < NE * 2 * Q) {
+          const int q = t % Q, s = (t / Q) & 1, el = t / (2 * Q);
+          T* base = sX + el * PER + s * (2 * Q * V);
+          // own trace at [q], neighbour's at [Q + q]; the +a face (s = 1)
+          // has the own side on the left
+          const T* pl = base + (s ? q : Q + q) * V;
+          const T* pr = base + (s ? Q + q : q) * V;
+          T wl[4], wr[4], G[4];
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv) {
+            wl[vv] = pl[vv];
+            wr[vv] = pr[vv];
+          }
+          flux_llf<T>(wl, wr, a, gamma, M.flux, G);
+          const T sg = s ? -sc : sc;
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv) base[q * V + vv] = sg * G[vv];
+        }
+      }
+    }
+    __syncthreads();
+    // lift: t_j = sum_q BW[j][q] G_q, then k(i_a, j) += MC_s[i_a] t_j
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const T* gsrc = sX + le * PER + s * (2 * Q * V) + v;
+      T G[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) G[q] = gsrc[q * V];
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        T tj = (T)O.BW[j][0] * G[0];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) tj = fmx2((T)O.BW[j][q], G[q], tj);
+#pragma unroll
+        for (int ia = 0; ia < P; ++ia) {
+          const int node = a == 0 ? j * P + ia : ia * P + j;
+          k[node] = fmx2((T)O.MC[s][ia], tj, k[node]);
+        }
+      }
+    }
+  }
+
+  // ---- SSP-RK3 combine in FP64
+  if (valid) {
+    double* o = out + col;
+    if (S.a == 0.0) {
+#pragma unroll
+      for (int i = 0; i < Pd; ++i) o[i] = S.b * (u[i] + S.dt * (double)k[i]);
+    } else {
+      double un[Pd];
+      load_col<P>(u_n + col, un);
+#pragma unroll
+      for (int i = 0; i < Pd; ++i) o[i] = S.a * un[i] + S.b * (u[i] + S.dt * (double)k[i]);
+    }
+  }
+}
+
+template <typename T, int P>
+hipError_t launch2d(const Mesh& M, const Async& A, const Stage& S, const double* u_in, const double* u_n,
+                    double* out, int src, double* ring, const double* ghost, hipStream_t st) {
+  const long long nblk = (M.E + kNE2 - 1) / kNE2;
+  hipLaunchKernelGGL((rhs_stage2d_kernel<T, P>), dim3((unsigned)nblk), dim3(64), 0, st, M, A, S, u_in, u_n, out, src,
+                     ring, ghost);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch2d_prec(int degree, const Mesh& M, const Async& A, const Stage& S, const double* u_in,
+                         const double* u_n, double* out, int src, double* ring, const double* ghost, hipStream_t st) {
+  switch (degree) {
+    case 1: return launch2d<T, 2>(M, A, S, u_in, u_n, out, src, ring, ghost, st);
+    case 2: return launch2d<T, 3>(M, A, S, u_in, u_n, out, src, ring, ghost, st);
+    case 3: return launch2d<T, 4>(M, A, S, u_in, u_n, out, src, ring, ghost, st);
+    case 4: return launch2d<T, 5>(M, A, S, u_in, u_n, out, src, ring, ghost, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_rhs_stage_2d(int degree, int precision, const Mesh& M, const Async& A, const Stage& S,
+                               const double* u_in, const double* u_n, double* out, int src, double* ring,
+                               const double* ghost, hipStream_t st) {
+  if (M.dim != 2) return hipErrorInvalidValue;
+  if (precision == 1) return launch2d_prec<float>(degree, M, A, S, u_in, u_n, out, src, ring, ghost, st);
+  return launch2d_prec<double>(degree, M, A, S, u_in, u_n, out, src, ring, ghost, st);
+}
+
+}  // namespace adg

@@ -20,10 +20,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_DOUBLES = 32 * 1024 * 1024  # 256 MiB read + 256 MiB written per copy
 
 
+KERNEL_SOURCES = ("adg_rhs.hip", "adg_rhs2d.hip", "adg_internal.h", "adg_tables.h")
+
+
 def source_hash():
+    """first 16 hex digits of the SHA-256 of the stage kernel's sources"""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2603_28710_amd", "csrc", "adg_rhs.hip"), "rb") as fh:
-        h.update(fh.read())
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_28710_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -73,7 +78,7 @@ def summarize(fetch_csv, write_csv, workload, out):
         if not ks:
             raise SystemExit(f"no kernel matching {needle}")
         vals = sum((d[k] for k in ks), [])
-        return sum(vals) / len(vals), len(vals)
+        return sum(vals) / len(vals), len(vals), ks[0].split("(")[0]
 
     # the elementwise multiply (reads and writes COPY_DOUBLES doubles); not
     # the fill kernel that created its input
@@ -84,10 +89,10 @@ def summarize(fetch_csv, write_csv, workload, out):
     cw = sum(wr[copy_name[0]]) / len(wr[copy_name[0]])
     f_scale = COPY_DOUBLES * 8 / (cf * 1024.0)
     w_scale = COPY_DOUBLES * 8 / (cw * 1024.0)
-    rf, nf = pick(fe, "rhs_stage")
-    rw, nw = pick(wr, "rhs_stage")
+    rf, nf, kname = pick(fe, "rhs_stage")
+    rw, nw, _ = pick(wr, "rhs_stage")
     res = {
-        "kernel": "rhs_stage_kernel", "workload": workload, "source_sha256_16": source_hash(),
+        "kernel": kname, "workload": workload, "source_sha256_16": source_hash(),
         "fetch_kib_per_dispatch": rf, "write_kib_per_dispatch": rw, "dispatches": [nf, nw],
         "copy_kernel": copy_name[0][:80], "copy_fetch_kib": cf, "copy_write_kib": cw,
         "fetch_scale": f_scale, "write_scale": w_scale,
