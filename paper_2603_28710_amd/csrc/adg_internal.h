@@ -225,6 +225,19 @@ __host__ __device__ inline int delay_of(const Mesh& M, const Async& A, int sub, 
   return (int)(k < cap ? k : cap);
 }
 
+// AT weight of stored level l (0 = newest) among nlev <= 4 levels for the
+// extrapolation to the fractional delay tau (eq. at-flux): the Lagrange weight
+// prod_{i != l} (tau + i) / (i - l), which solves the moment constraints of
+// eq. at-flux-constraints; the integer denominators enter as reciprocals
+inline constexpr double kAtInvDen[5][4] = {
+    {0, 0, 0, 0}, {1, 0, 0, 0}, {1, -1, 0, 0}, {0.5, -1, 0.5, 0}, {1.0 / 6, -0.5, 0.5, -1.0 / 6}};
+__host__ __device__ inline double at_weight(int l, int nlev, double tau) {
+  double w = kAtInvDen[nlev][l];
+  for (int i = 0; i < nlev; ++i)
+    if (i != l) w *= tau + i;
+  return w;
+}
+
 // ---- launchers (defined in the .hip files) ---------------------------------
 
 // Neighbour data at PE-boundary faces inside the stage kernel:

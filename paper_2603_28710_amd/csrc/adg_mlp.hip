@@ -135,13 +135,6 @@ __device__ __forceinline__ int face_node_l(int f, int j) {
   return j0 + P * (j1 + P * s);
 }
 
-__device__ __forceinline__ double at_w(int j, int nlev, double tau) {
-  double w = 1.0;
-  for (int i = 0; i < nlev; ++i)
-    if (i != j) w *= (tau + i) / (double)(i - j);
-  return w;
-}
-
 // Ghost traces with the learned correction (or, when collecting, AT ghosts
 // plus training pairs). Block: 4 wavefronts x 16 face nodes; whole face-sides
 // per block so the per-face judge stays inside the block.
@@ -188,7 +181,7 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
         for (int v = 0; v < V; ++v) T[lv][v] = ring[ring_slot(A, k + lv) * total + (fs * V + v) * Fn + j];
       const double tau = k + A.c_m;
       for (int lv = 0; lv < A.levels; ++lv) {
-        const double wl = at_w(lv, A.levels, tau);
+        const double wl = at_weight(lv, A.levels, tau);
 #pragma unroll
         for (int v = 0; v < V; ++v) at[v] += wl * T[lv][v];
       }

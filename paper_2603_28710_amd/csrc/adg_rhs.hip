@@ -72,15 +72,6 @@ __host__ __device__ constexpr size_t rhs_smem_bytes(int NE) {
          (size_t)(NE * (2 * Dm::SZP + 2 * Dm::SZQ) + tab_off(P, Q).total) * sizeof(T);
 }
 
-// AT weight of level l among nlev at fractional delay tau: Lagrange
-// extrapolation to offset 0 from the level times -(tau + i), i.e. the
-// solution of the moment constraints of eq. at-flux-constraints
-__device__ __forceinline__ double at_weight_rhs(int l, int nlev, double tau) {
-  double w = 1.0;
-  for (int i = 0; i < nlev; ++i)
-    if (i != l) w *= (tau + i) / (double)(i - l);
-  return w;
-}
 
 // Apply the 1D operator A (NO x NI, row-major) along axis AX of nvec tensors
 // stored back to back with extents (S0, S1, S2) (S_AX == NI); the result has
@@ -411,7 +402,7 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
 #pragma unroll
         for (int v = 0; v < V; ++v) acc[v] = 0.0;
         for (int l = 0; l < A.levels; ++l) {
-          const double wl = at_weight_rhs(l, A.levels, tau);
+          const double wl = at_weight(l, A.levels, tau);
           const double* g = ring + ring_slot(A, k + l) * ring_level + fs + j;
 #pragma unroll
           for (int v = 0; v < V; ++v) acc[v] += wl * g[v * Fn];

@@ -61,15 +61,6 @@ __device__ __forceinline__ int xcd_block2() {
   return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
 }
 
-// AT weight of level l of nlev at fractional delay tau (Lagrange
-// extrapolation, the solution of eq. at-flux-constraints)
-__device__ __forceinline__ double at_w2(int l, int nlev, double tau) {
-  double w = 1.0;
-  for (int i = 0; i < nlev; ++i)
-    if (i != l) w *= (tau + i) / (double)(i - l);
-  return w;
-}
-
 // node index of face-local node j on face f (2D, x fastest)
 template <int P>
 __device__ __forceinline__ constexpr int fnode(int f, int j) {
@@ -132,8 +123,11 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
   constexpr int Q = P + 1, V = 4, NE = kNE2, Pd = P * P, Qd = Q * Q;
   constexpr ops::Ops<P> O = ops::make_ops<P>();
   // per element: the state at the Gauss points [Qd][V], later the face
-  // traces [face s][side][Q][V] of one axis
-  constexpr int PER = Qd * V > 16 * Q ? Qd * V : 16 * Q;
+  // traces [face s][side][Q][V] of one axis. The element stride is padded so
+  // that the 16 elements' 16-byte reads at one offset hit distinct LDS banks
+  // (stride = 4 x odd dwords)
+  constexpr int PER0 = Qd * V > 16 * Q ? Qd * V : 16 * Q;
+  constexpr int PER = sizeof(T) == 8 ? PER0 + (6 - PER0 % 4) % 4 : PER0 + (12 - PER0 % 8) % 8;
   __shared__ __align__(16) T sX[NE * PER];
 
   const int lane = threadIdx.x, le = lane >> 2, v = lane & 3;
@@ -273,7 +267,7 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
           // AT extrapolation to the stage time, tau = kd + c_m (eq. at-flux)
           const double tau = kd + A.c_m;
           for (int l = 0; l < A.levels; ++l) {
-            const double wl = at_w2(l, A.levels, tau);
+            const double wl = at_weight(l, A.levels, tau);
             const double* gp = ring + ring_slot(A, kd + l) * ring_level + fs * V * P + v * P;
 #pragma unroll
             for (int j = 0; j < P; ++j) g[j] = fma(wl, gp[j], g[j]);
