@@ -49,12 +49,16 @@ WORKLOADS = {
 DEFAULT = "vortex256_p3_at3_uniformL3"
 
 
-def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, async_on):
-    """Minimum HBM bytes of one fused stage launch: the stage input read once,
-    u^n read on stages 2 and 3, the output written (8 B each per DoF,
-    averaged over the 3 stages: 64/3 B per DoF), plus the ghost traces read at
-    PE-boundary faces."""
-    return ndof * 64.0 / 3.0 + (8.0 * nfs_nodes_vars if async_on else 0.0)
+def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, ghost, levels):
+    """Minimum HBM bytes of one fused stage launch, averaged over the 3 stages
+    of a step: the stage input read once, u^n read on stages 2 and 3, the
+    output written (8 B each per DoF: 64/3 B per DoF); at PE-boundary faces
+    the ring levels read (one for stale traces, `levels` for AT) and, at
+    stage 0, one level written (nfs_nodes_vars values per level)."""
+    ring = 0.0
+    if ghost in (1, 2) and nfs_nodes_vars > 0:
+        ring = 8.0 * nfs_nodes_vars * ((1 if ghost == 1 else levels) + 1.0 / 3.0)
+    return ndof * 64.0 / 3.0 + ring
 
 
 def algorithmic_flops_per_element(dim, P, Q):
@@ -165,8 +169,7 @@ def main():
     value = s.ndof * stages / sec
     nfs = B.adg_delay(s.h, s.time()[0], 0, 0)[1]
     Fn = (c["degree"] + 1) ** (c["dim"] - 1)
-    async_on = a["ghost"] != 0 and nfs > 0
-    bytes_launch = algorithmic_bytes_per_launch(s.ndof, nfs * s.V * Fn, async_on)
+    bytes_launch = algorithmic_bytes_per_launch(s.ndof, nfs * s.V * Fn, a["ghost"], a["levels"])
     avg_s = rhs_ms / max(rhs_n, 1) / 1e3
     achieved = bytes_launch / avg_s / 1e9
     P, Q = c["degree"] + 1, c["degree"] + 2

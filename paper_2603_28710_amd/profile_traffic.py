@@ -1,4 +1,4 @@
-"""HBM traffic of the fused stage kernel from rocprofv3 counters.
+"""HBM traffic and kernel timings of the fused stage kernel from rocprofv3.
 
 run:        executes a benchmark workload for a few steps, then a plain
             elementwise copy of known size (the calibration kernel). Meant to
@@ -8,6 +8,8 @@ summarize:  reads the two counter CSVs, scales the stage kernel's per-dispatch
             FETCH_SIZE / WRITE_SIZE by what the same counters read for the copy
             (known bytes / counter reading), and writes the JSON summary that
             bench.py picks up (it is ignored once the kernel source changes).
+kstats:     turns the kernel_stats.csv of `rocprofv3 --kernel-trace --stats`
+            into a short text table, headed by the command that produced it.
 """
 import argparse
 import csv
@@ -53,6 +55,11 @@ def run(workload, steps):
     print(f"ran {workload} for {steps} steps and 3 copies of {COPY_DOUBLES * 8} bytes", flush=True)
 
 
+def _short(name):
+    """kernel name without the anonymous-namespace tag and argument list"""
+    return name.replace("(anonymous namespace)::", "").split("(")[0]
+
+
 def _per_dispatch(path, counter):
     """kernel name -> list of per-dispatch counter values (summed over
     dimensions/instances of one dispatch)"""
@@ -78,7 +85,7 @@ def summarize(fetch_csv, write_csv, workload, out):
         if not ks:
             raise SystemExit(f"no kernel matching {needle}")
         vals = sum((d[k] for k in ks), [])
-        return sum(vals) / len(vals), len(vals), ks[0].split("(")[0]
+        return sum(vals) / len(vals), len(vals), _short(ks[0])
 
     # the elementwise multiply (reads and writes COPY_DOUBLES doubles); not
     # the fill kernel that created its input
@@ -91,8 +98,13 @@ def summarize(fetch_csv, write_csv, workload, out):
     w_scale = COPY_DOUBLES * 8 / (cw * 1024.0)
     rf, nf, kname = pick(fe, "rhs_stage")
     rw, nw, _ = pick(wr, "rhs_stage")
+    cmd = ("rocprofv3 --pmc {c} --output-format csv -d <dir> -o p -- python3 "
+           "paper_2603_28710_amd/profile_traffic.py run --steps 2 --workload " + workload)
     res = {
         "kernel": kname, "workload": workload, "source_sha256_16": source_hash(),
+        "fetch_command": cmd.format(c="FETCH_SIZE"), "write_command": cmd.format(c="WRITE_SIZE"),
+        "summary_command": "python3 paper_2603_28710_amd/profile_traffic.py summarize --fetch <fetch csv> "
+                           "--write <write csv> --workload " + workload + " --out <this file>",
         "fetch_kib_per_dispatch": rf, "write_kib_per_dispatch": rw, "dispatches": [nf, nw],
         "copy_kernel": copy_name[0][:80], "copy_fetch_kib": cf, "copy_write_kib": cw,
         "fetch_scale": f_scale, "write_scale": w_scale,
@@ -101,6 +113,24 @@ def summarize(fetch_csv, write_csv, workload, out):
     with open(out, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))
+
+
+def kstats(stats_csv, command, out):
+    rows = []
+    with open(stats_csv) as f:
+        for r in csv.DictReader(f):
+            rows.append((_short(r["Name"])[:72], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
+                         float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+                         float(r["Percentage"])))
+    rows.sort(key=lambda x: -x[2])
+    lines = [f"# rocprofv3 kernel statistics (kernel sources sha256/16 {source_hash()})",
+             f"# command: {command}", "",
+             f"{'kernel':72s} {'calls':>6s} {'total_us':>11s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'pct':>6s}"]
+    for n, c, t, a, lo, hi, pct in rows:
+        lines.append(f"{n:72s} {c:6d} {t:11.1f} {a:9.2f} {lo:9.2f} {hi:9.2f} {pct:6.2f}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def main():
@@ -114,11 +144,17 @@ def main():
     s.add_argument("--write", required=True)
     s.add_argument("--workload", default="vortex256_p3_at3_uniformL3")
     s.add_argument("--out", required=True)
+    k = sub.add_parser("kstats")
+    k.add_argument("--stats", required=True)
+    k.add_argument("--command", required=True)
+    k.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd == "run":
         run(a.workload, a.steps)
-    else:
+    elif a.cmd == "summarize":
         summarize(a.fetch, a.write, a.workload, a.out)
+    else:
+        kstats(a.stats, a.command, a.out)
 
 
 if __name__ == "__main__":
