@@ -25,8 +25,35 @@
 // bitwise opposite and the synchronous scheme conserves to round-off.
 // T = double (FP64 path) or float (FP32 contractions; combine in FP64).
 #include "adg_internal.h"
+#include "adg_tables.h"
 
 namespace adg {
+
+// threads per workgroup: one wavefront, so the workgroup barriers between the
+// LDS sweeps cost no cross-wave waiting
+constexpr int kNT3 = 64;
+
+// the 1D operators as compile-time constants in the kernel's precision
+template <typename T, int P>
+struct KOps {
+  static constexpr int Q = P + 1;
+  T B[Q * P];    // B[q][j] = l_j(x_q)
+  T DT[Q * Q];   // DT[r][q] = g_r'(x_q)
+  T BTM[P * Q];  // M1^{-1} B^T
+};
+template <typename T, int P>
+constexpr KOps<T, P> make_kops() {
+  constexpr int Q = P + 1;
+  const ops::Ops<P> o = ops::make_ops<P>();
+  KOps<T, P> k{};
+  for (int q = 0; q < Q; ++q) {
+    for (int j = 0; j < P; ++j) k.B[q * P + j] = static_cast<T>(o.B[q][j]);
+    for (int r = 0; r < Q; ++r) k.DT[r * Q + q] = static_cast<T>(o.D[q][r]);
+  }
+  for (int i = 0; i < P; ++i)
+    for (int q = 0; q < Q; ++q) k.BTM[i * Q + q] = static_cast<T>(o.BTM[i][q]);
+  return k;
+}
 
 __device__ __forceinline__ double fmx(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float fmx(float a, float b, float c) { return fmaf(a, b, c); }
@@ -59,7 +86,7 @@ __host__ __device__ constexpr int rhs_elems_per_block() {
   using Dm = Dims<D, P, Q>;
   constexpr int per = (2 * Dm::SZP + 2 * Dm::SZQ) * (int)sizeof(T) + Dm::nf * kFaceInfoBytes;
   constexpr int tabb = tab_off(P, Q).total * (int)sizeof(T);
-  int ne = kThreads / Dm::Pd;
+  int ne = kNT3 / Dm::Pd;
   if (ne < 1) ne = 1;
   while (ne > 1 && ne * per + tabb > 64 * 1024) --ne;
   return ne;
@@ -85,7 +112,7 @@ __device__ __forceinline__ void sweep(const T* __restrict__ in, T* __restrict__ 
   constexpr int istr = AX == 0 ? 1 : (AX == 1 ? S0 : S0 * S1);
   constexpr int ostr = AX == 0 ? 1 : (AX == 1 ? O0 : O0 * O1);
   static_assert((AX == 0 ? S0 : (AX == 1 ? S1 : S2)) == NI, "extent mismatch");
-  for (int t = threadIdx.x; t < nvec * nl; t += kThreads) {
+  for (int t = threadIdx.x; t < nvec * nl; t += kNT3) {
     const int v = t / nl, l = t - v * nl;
     int ib, ob;
     if (AX == 0) {
@@ -177,7 +204,7 @@ __device__ __forceinline__ int xcd_block() {
 }
 
 template <typename T, int D, int P, int Q, int NE>
-__global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, Stage S,
+__global__ __launch_bounds__(kNT3) void rhs_stage_kernel(Mesh M, Async A, Stage S,
                                                              const double* __restrict__ u_in, const double* u_n,
                                                              double* out, int src, double* __restrict__ ring,
                                                              const double* __restrict__ ghost,
@@ -185,6 +212,7 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
   using Dm = Dims<D, P, Q>;
   constexpr int V = Dm::V, Pd = Dm::Pd, Qd = Dm::Qd, Fn = Dm::Fn, Fq = Dm::Fq, nf = Dm::nf, NS = Dm::NS;
   constexpr TabOff to = tab_off(P, Q);
+  static constexpr KOps<T, P> KO = make_kops<T, P>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   long long* sNb = reinterpret_cast<long long*>(smem_raw);  // neighbour element offset
   long long* sFs = sNb + NE * nf;                           // own face-side offset, or -1
@@ -204,7 +232,7 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
   const bool publish = src == kSrcRing && A.stage == 0;
 
   // per element face: neighbour, PE face-side, delay, and the face-side it feeds
-  for (int t = tid; t < ne * nf; t += kThreads) {
+  for (int t = tid; t < ne * nf; t += kNT3) {
     const int le = t / nf, f = t - le * nf;
     int c[3];
     elem_coords(M, e0 + le, c);
@@ -221,16 +249,16 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
     }
     sPub[t] = pub;
   }
-  for (int i = tid; i < to.total; i += kThreads) sT[i] = tab[i];
+  for (int i = tid; i < to.total; i += kNT3) sT[i] = tab[i];
   // the stage input into LDS; u_n (and, for T = float, the FP64 input) for
   // the combine into registers now, so their latency hides behind the compute
   const double* gin = u_in + e0 * Dm::SZP;
   const double* gn = u_n + e0 * Dm::SZP;
-  constexpr int CPT = (NE * Dm::SZP + kThreads - 1) / kThreads;
+  constexpr int CPT = (NE * Dm::SZP + kNT3 - 1) / kNT3;
   double ur[CPT], un[CPT];
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
-    const int i = tid + k * kThreads;
+    const int i = tid + k * kNT3;
     ur[k] = un[k] = 0.0;
     if (i < ne * Dm::SZP) {
       const double x = gin[i];
@@ -247,7 +275,7 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
   // delay 0 reads the live values.
   if (publish) {
     double* slot = ring + A.slot_n * ring_level;
-    for (int i = tid; i < ne * nf * Fn; i += kThreads) {
+    for (int i = tid; i < ne * nf * Fn; i += kNT3) {
       const int j = i % Fn;
       const int t = i / Fn;
       const long long pub = sPub[t];
@@ -264,25 +292,25 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
 
   // ---- volume: interpolation to the Gauss points (result in sB1)
   if constexpr (D == 2) {
-    sweep<T, P, Q, P, P, 1, 0, false>(sU, sB2, tab + to.B, NE * V);
+    sweep<T, P, Q, P, P, 1, 0, false>(sU, sB2, KO.B, NE * V);
     __syncthreads();
-    sweep<T, P, Q, Q, P, 1, 1, false>(sB2, sB1, tab + to.B, NE * V);
+    sweep<T, P, Q, Q, P, 1, 1, false>(sB2, sB1, KO.B, NE * V);
   } else {
-    sweep<T, P, Q, P, P, P, 0, false>(sU, sB1, tab + to.B, NE * V);
+    sweep<T, P, Q, P, P, P, 0, false>(sU, sB1, KO.B, NE * V);
     __syncthreads();
-    sweep<T, P, Q, Q, P, P, 1, false>(sB1, sB2, tab + to.B, NE * V);
+    sweep<T, P, Q, Q, P, P, 1, false>(sB1, sB2, KO.B, NE * V);
     __syncthreads();
-    sweep<T, P, Q, Q, Q, P, 2, false>(sB2, sB1, tab + to.B, NE * V);
+    sweep<T, P, Q, Q, Q, P, 2, false>(sB2, sB1, KO.B, NE * V);
   }
   __syncthreads();
 
   // Euler flux columns at the Gauss points, scaled by w_q 2/h_a (registers)
-  constexpr int QPT = (NE * Qd + kThreads - 1) / kThreads;
+  constexpr int QPT = (NE * Qd + kNT3 - 1) / kNT3;
   T F[QPT][D][V];
   const T gamma = (T)M.gamma, gm1 = gamma - (T)1;
 #pragma unroll
   for (int k = 0; k < QPT; ++k) {
-    const int idx = tid + k * kThreads;
+    const int idx = tid + k * kNT3;
     if (idx < NE * Qd) {
       const int le = idx / Qd, q = idx - le * Qd;
       T w[V];
@@ -312,7 +340,7 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
   for (int a = 0; a < D; ++a) {
 #pragma unroll
     for (int k = 0; k < QPT; ++k) {
-      const int idx = tid + k * kThreads;
+      const int idx = tid + k * kNT3;
       if (idx < NE * Qd) {
         const int le = idx / Qd, q = idx - le * Qd;
 #pragma unroll
@@ -322,30 +350,30 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
     __syncthreads();
     if (D == 2) {
       if (a == 0)
-        sweep<T, Q, Q, Q, Q, 1, 0, false>(sB1, sB2, tab + to.DT, NE * V);
+        sweep<T, Q, Q, Q, Q, 1, 0, false>(sB1, sB2, KO.DT, NE * V);
       else
-        sweep<T, Q, Q, Q, Q, 1, 1, true>(sB1, sB2, tab + to.DT, NE * V);
+        sweep<T, Q, Q, Q, Q, 1, 1, true>(sB1, sB2, KO.DT, NE * V);
     } else {
       if (a == 0)
-        sweep<T, Q, Q, Q, Q, Q, 0, false>(sB1, sB2, tab + to.DT, NE * V);
+        sweep<T, Q, Q, Q, Q, Q, 0, false>(sB1, sB2, KO.DT, NE * V);
       else if (a == 1)
-        sweep<T, Q, Q, Q, Q, Q, 1, true>(sB1, sB2, tab + to.DT, NE * V);
+        sweep<T, Q, Q, Q, Q, Q, 1, true>(sB1, sB2, KO.DT, NE * V);
       else
-        sweep<T, Q, Q, Q, Q, Q, 2, true>(sB1, sB2, tab + to.DT, NE * V);
+        sweep<T, Q, Q, Q, Q, Q, 2, true>(sB1, sB2, KO.DT, NE * V);
     }
     __syncthreads();
   }
   // test functions and inverse mass in one: BTM sweeps, k_volume in sR
   if constexpr (D == 2) {
-    sweep<T, Q, P, Q, Q, 1, 0, false>(sB2, sB1, tab + to.BTM, NE * V);
+    sweep<T, Q, P, Q, Q, 1, 0, false>(sB2, sB1, KO.BTM, NE * V);
     __syncthreads();
-    sweep<T, Q, P, P, Q, 1, 1, false>(sB1, sR, tab + to.BTM, NE * V);
+    sweep<T, Q, P, P, Q, 1, 1, false>(sB1, sR, KO.BTM, NE * V);
   } else {
-    sweep<T, Q, P, Q, Q, Q, 0, false>(sB2, sB1, tab + to.BTM, NE * V);
+    sweep<T, Q, P, Q, Q, Q, 0, false>(sB2, sB1, KO.BTM, NE * V);
     __syncthreads();
-    sweep<T, Q, P, P, Q, Q, 1, false>(sB1, sB2, tab + to.BTM, NE * V);
+    sweep<T, Q, P, P, Q, Q, 1, false>(sB1, sB2, KO.BTM, NE * V);
     __syncthreads();
-    sweep<T, Q, P, P, P, Q, 2, false>(sB2, sR, tab + to.BTM, NE * V);
+    sweep<T, Q, P, P, P, Q, 2, false>(sB2, sR, KO.BTM, NE * V);
   }
   __syncthreads();
 
@@ -362,7 +390,7 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
     const int s0 = (pass * NS) & 1;
     // gather own (side 0) and neighbour (side 1) face-node values; one item
     // per (side, element, face, node), all V variables
-    for (int i = tid; i < 2 * NE * NS * Fn; i += kThreads) {
+    for (int i = tid; i < 2 * NE * NS * Fn; i += kNT3) {
       const int j = i % Fn;
       const int r = i / Fn;
       const int ls = r % (NE * NS);  // le * NS + (s - s0)
@@ -414,15 +442,15 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
     __syncthreads();
     // interpolation to the face points (both sides at once)
     if constexpr (D == 2) {
-      sweep<T, P, Q, P, 1, 1, 0, false>(sTr, sTq, tab + to.B, 2 * NE * NS * V);
+      sweep<T, P, Q, P, 1, 1, 0, false>(sTr, sTq, KO.B, 2 * NE * NS * V);
     } else {
-      sweep<T, P, Q, P, P, 1, 0, false>(sTr, sTm, tab + to.B, 2 * NE * NS * V);
+      sweep<T, P, Q, P, P, 1, 0, false>(sTr, sTm, KO.B, 2 * NE * NS * V);
       __syncthreads();
-      sweep<T, P, Q, Q, P, 1, 1, false>(sTm, sTq, tab + to.B, 2 * NE * NS * V);
+      sweep<T, P, Q, Q, P, 1, 1, false>(sTm, sTq, KO.B, 2 * NE * NS * V);
     }
     __syncthreads();
     // numerical flux at every face point, in place of the own values
-    for (int i = tid; i < NE * NS * Fq; i += kThreads) {
+    for (int i = tid; i < NE * NS * Fq; i += kNT3) {
       const int fq = i % Fq;
       const int r = i / Fq;
       const int s = r % NS + s0, le = r / NS;
@@ -449,15 +477,15 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
     __syncthreads();
     // lift with BTM to the face nodes (own half only), result in sTr
     if constexpr (D == 2) {
-      sweep<T, Q, P, Q, 1, 1, 0, false>(sTq, sTr, tab + to.BTM, NE * NS * V);
+      sweep<T, Q, P, Q, 1, 1, 0, false>(sTq, sTr, KO.BTM, NE * NS * V);
     } else {
-      sweep<T, Q, P, Q, Q, 1, 0, false>(sTq, sTm, tab + to.BTM, NE * NS * V);
+      sweep<T, Q, P, Q, Q, 1, 0, false>(sTq, sTm, KO.BTM, NE * NS * V);
       __syncthreads();
-      sweep<T, Q, P, P, Q, 1, 1, false>(sTm, sTr, tab + to.BTM, NE * NS * V);
+      sweep<T, Q, P, P, Q, 1, 1, false>(sTm, sTr, KO.BTM, NE * NS * V);
     }
     __syncthreads();
     // inverse mass along a: k += MC_side[i_a] * lifted(j)
-    for (int i = tid; i < NE * Dm::SZP; i += kThreads) {
+    for (int i = tid; i < NE * Dm::SZP; i += kNT3) {
       const int node = i % Pd;
       const int r = i / Pd;
       const int v = r % V, le = r / V;
@@ -479,7 +507,7 @@ __global__ __launch_bounds__(kThreads) void rhs_stage_kernel(Mesh M, Async A, St
   double* gout = out + e0 * Dm::SZP;
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
-    const int i = tid + k * kThreads;
+    const int i = tid + k * kNT3;
     if (i < ne * Dm::SZP) {
       const double ui = sizeof(T) == 8 ? (double)sU[i] : ur[k];
       const double y = ui + S.dt * (double)sR[i];
@@ -496,7 +524,7 @@ static hipError_t launch_rhs_t(const Mesh& M, const Async& A, const Stage& S, co
   constexpr int NE = rhs_elems_per_block<T, D, P, Q>();
   const size_t smem = rhs_smem_bytes<T, D, P, Q>(NE);
   const long long nblk = (M.E + NE - 1) / NE;
-  hipLaunchKernelGGL((rhs_stage_kernel<T, D, P, Q, NE>), dim3((unsigned)nblk), dim3(kThreads), smem, st, M, A, S,
+  hipLaunchKernelGGL((rhs_stage_kernel<T, D, P, Q, NE>), dim3((unsigned)nblk), dim3(kNT3), smem, st, M, A, S,
                      u_in, u_n, out, src, ring, ghost, tab);
   return hipGetLastError();
 }
