@@ -173,6 +173,57 @@ __host__ __device__ inline long long face_side(const Mesh& M, const int* c, int 
   return (long long)subdomain_of(M, c) * M.fs_sub + M.fs_off[f] + li;
 }
 
+// An element's position: its coordinates, its coordinates inside its
+// subdomain and the subdomain's coordinates; computed once per element, it
+// makes the per-face queries below a few integer operations each.
+struct ElemPos {
+  int c[3], l[3], sc[3];
+};
+__host__ __device__ inline ElemPos elem_pos(const Mesh& M, long long e) {
+  ElemPos p;
+  elem_coords(M, e, p.c);
+  for (int k = 0; k < 3; ++k) {
+    p.sc[k] = (int)fdiv((unsigned)p.c[k], M.dm[k]);
+    p.l[k] = p.c[k] - p.sc[k] * M.m[k];
+  }
+  return p;
+}
+__host__ __device__ inline int sub_at(const Mesh& M, const int* sc) {
+  return sc[0] + M.parts[0] * (sc[1] + M.parts[1] * sc[2]);
+}
+// element across face f of element e (periodic)
+__host__ __device__ inline long long neighbour_of(const Mesh& M, long long e, const ElemPos& p, int f) {
+  const int a = f >> 1;
+  const long long stride = a == 0 ? 1 : (a == 1 ? (long long)M.nc[0] : (long long)M.nc[0] * M.nc[1]);
+  const long long wrap = (long long)(M.nc[a] - 1) * stride;
+  if (f & 1) return p.c[a] == M.nc[a] - 1 ? e - wrap : e + stride;
+  return p.c[a] == 0 ? e + wrap : e - stride;
+}
+// position of an element's face-sides of direction f inside the subdomain's
+// block of direction f (other axes ascending, lowest fastest)
+__host__ __device__ inline int face_local_index(const Mesh& M, const int* l, int a) {
+  const int o0 = a == 0 ? 1 : 0, o1 = a == 2 ? 1 : 2;
+  return M.dim == 3 ? l[o0] + M.m[o0] * l[o1] : l[o0];
+}
+// face_side for the element at p: its face-side of face f, or -1
+__host__ __device__ inline long long face_side_at(const Mesh& M, const ElemPos& p, int f) {
+  const int a = f >> 1;
+  if (M.parts[a] < 2) return -1;
+  if ((f & 1) ? (p.l[a] != M.m[a] - 1) : (p.l[a] != 0)) return -1;
+  return (long long)sub_at(M, p.sc) * M.fs_sub + M.fs_off[f] + face_local_index(M, p.l, a);
+}
+// the face-side fed by PE face f of the element at p: face f^1 of its
+// neighbour, which lies in the adjacent subdomain at the same tangential
+// position
+__host__ __device__ inline long long fed_face_side(const Mesh& M, const ElemPos& p, int f) {
+  const int a = f >> 1;
+  int sc[3] = {p.sc[0], p.sc[1], p.sc[2]};
+  sc[a] += (f & 1) ? 1 : -1;
+  if (sc[a] < 0) sc[a] += M.parts[a];
+  if (sc[a] >= M.parts[a]) sc[a] -= M.parts[a];
+  return (long long)sub_at(M, sc) * M.fs_sub + M.fs_off[f ^ 1] + face_local_index(M, p.l, a);
+}
+
 // inverse of face_side: receiving element coords and face
 __host__ __device__ inline void face_side_decode(const Mesh& M, long long fs, int* c, int* f_out) {
   int s = (int)(fs / M.fs_sub);

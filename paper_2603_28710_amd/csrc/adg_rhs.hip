@@ -234,20 +234,12 @@ __global__ __launch_bounds__(kNT3) void rhs_stage_kernel(Mesh M, Async A, Stage 
   // per element face: neighbour, PE face-side, delay, and the face-side it feeds
   for (int t = tid; t < ne * nf; t += kNT3) {
     const int le = t / nf, f = t - le * nf;
-    int c[3];
-    elem_coords(M, e0 + le, c);
-    const long long nb = neighbour(M, c, f);
-    sNb[t] = nb * V * Pd;
-    const long long fs = async_on ? face_side(M, c, f) : -1;
+    const ElemPos pos = elem_pos(M, e0 + le);
+    sNb[t] = neighbour_of(M, e0 + le, pos, f) * V * Pd;
+    const long long fs = async_on ? face_side_at(M, pos, f) : -1;
     sFs[t] = fs >= 0 ? fs * V * Fn : -1;
-    sK[t] = fs >= 0 && src == kSrcRing ? delay_of(M, A, subdomain_of(M, c), f) : 0;
-    long long pub = -1;
-    if (publish && fs >= 0) {
-      int cn[3];
-      elem_coords(M, nb, cn);
-      pub = face_side(M, cn, f ^ 1) * V * Fn;
-    }
-    sPub[t] = pub;
+    sK[t] = fs >= 0 && src == kSrcRing ? delay_of(M, A, sub_at(M, pos.sc), f) : 0;
+    sPub[t] = publish && fs >= 0 ? fed_face_side(M, pos, f) * V * Fn : -1;
   }
   for (int i = tid; i < to.total; i += kNT3) sT[i] = tab[i];
   // the stage input into LDS; u_n (and, for T = float, the FP64 input) for

@@ -221,8 +221,7 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
   }
 
   // ---- per-face neighbour data: element, PE face-side, delay
-  int c[3] = {0, 0, 0};
-  if (valid) elem_coords(M, e, c);
+  const ElemPos pos = elem_pos(M, valid ? e : 0);
   const bool async_on = src != kSrcLive && M.nfs > 0;
   const long long ring_level = M.nfs * V * P;
   const bool publish = src == kSrcRing && A.stage == 0;
@@ -239,19 +238,17 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
 #pragma unroll
       for (int j = 0; j < P; ++j) g[j] = 0.0;
       if (valid) {
-        const long long nb = neighbour(M, c, f);
-        const long long fs = async_on ? face_side(M, c, f) : -1;
+        const long long fs = async_on ? face_side_at(M, pos, f) : -1;
         int kd = 0;
-        if (fs >= 0 && src == kSrcRing) kd = delay_of(M, A, subdomain_of(M, c), f);
+        if (fs >= 0 && src == kSrcRing) kd = delay_of(M, A, sub_at(M, pos.sc), f);
         if (fs >= 0 && publish) {
-          int cn[3];
-          elem_coords(M, nb, cn);
-          double* dst = ring + A.slot_n * ring_level + face_side(M, cn, f ^ 1) * V * P + v * P;
+          double* dst = ring + A.slot_n * ring_level + fed_face_side(M, pos, f) * V * P + v * P;
 #pragma unroll
           for (int j = 0; j < P; ++j) dst[j] = u[fnode<P>(f, j)];
         }
         if (fs < 0 || (src == kSrcRing && kd == 0)) {
-          const double* gp = u_in + nb * (V * Pd) + v * Pd;
+          const unsigned nb = (unsigned)neighbour_of(M, e, pos, f);
+          const double* gp = u_in + (size_t)nb * (V * Pd) + v * Pd;
 #pragma unroll
           for (int j = 0; j < P; ++j) g[j] = gp[fnode<P>(f ^ 1, j)];
         } else if (src == kSrcGhost) {
