@@ -168,6 +168,19 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
   }
   __syncthreads();
 
+  // the live neighbour traces of the two x faces, loaded now so that their
+  // latency hides behind the volume work (the y faces' would cost the
+  // registers of a third wavefront per SIMD)
+  const ElemPos pos = elem_pos(M, valid ? e : 0);
+  double nbv[2][P];
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const unsigned nb = (unsigned)neighbour_of(M, valid ? e : 0, pos, f);
+    const double* gp = u_in + (size_t)nb * (V * Pd) + v * Pd;
+#pragma unroll
+    for (int j = 0; j < P; ++j) nbv[f][j] = gp[fnode<P>(f ^ 1, j)];
+  }
+
   // ---- volume: flux components of this lane's variable, tested row by row
   T k[Pd];
 #pragma unroll
@@ -221,7 +234,6 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
   }
 
   // ---- per-face neighbour data: element, PE face-side, delay
-  const ElemPos pos = elem_pos(M, valid ? e : 0);
   const bool async_on = src != kSrcLive && M.nfs > 0;
   const long long ring_level = M.nfs * V * P;
   const bool publish = src == kSrcRing && A.stage == 0;
@@ -247,10 +259,15 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
           for (int j = 0; j < P; ++j) dst[j] = u[fnode<P>(f, j)];
         }
         if (fs < 0 || (src == kSrcRing && kd == 0)) {
-          const unsigned nb = (unsigned)neighbour_of(M, e, pos, f);
-          const double* gp = u_in + (size_t)nb * (V * Pd) + v * Pd;
+          if (a == 0) {
 #pragma unroll
-          for (int j = 0; j < P; ++j) g[j] = gp[fnode<P>(f ^ 1, j)];
+            for (int j = 0; j < P; ++j) g[j] = nbv[s][j];
+          } else {
+            const unsigned nb = (unsigned)neighbour_of(M, e, pos, f);
+            const double* gp = u_in + (size_t)nb * (V * Pd) + v * Pd;
+#pragma unroll
+            for (int j = 0; j < P; ++j) g[j] = gp[fnode<P>(f ^ 1, j)];
+          }
         } else if (src == kSrcGhost) {
           const double* gp = ghost + fs * V * P + v * P;
 #pragma unroll
