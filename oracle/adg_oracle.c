@@ -259,7 +259,8 @@ typedef struct {
   double *lagF;               /* face nodes -> face Gauss points: [Fq][Fn] */
   double* Minv;               /* inverse reference mass matrix [Pd][Pd] */
   double *u, *ua, *ub, *kb, *Fnum;
-  double* hist;
+  double* hist;  /* trace modes: past states [R][state] */
+  double* fhist; /* flux modes: stored PE-face fluxes [R][E][D][Fq][V], keyed by the left element */
   int R, Qh;
   int64_t n;
   double t;
@@ -469,9 +470,18 @@ void* orc_create(const orc_cfg* cfg) {
     case 0: s->Qh = 1; s->R = 0; break;
     case 1: s->Qh = 1; s->R = cfg->L + 1; break;
     case 2: s->Qh = lev; s->R = cfg->L + lev; break;
-    default: s->Qh = lev > K_MLP ? lev : K_MLP; s->R = cfg->L + s->Qh; break;
+    case 3: s->Qh = lev > K_MLP ? lev : K_MLP; s->R = cfg->L + s->Qh; break;
+    case 4: s->Qh = 1; s->R = cfg->L + 1; break;
+    case 5: s->Qh = lev; s->R = cfg->L + lev; break;
+    default: orc_destroy(s); return NULL;
   }
-  if (s->R > 0) s->hist = (double*)xmalloc(sizeof(double) * nd * s->R);
+  if (cfg->ghost >= 4 && cfg->delay_kind != 2) {
+    orc_destroy(s);
+    return NULL;
+  }
+  if (s->R > 0 && cfg->ghost <= 3) s->hist = (double*)xmalloc(sizeof(double) * nd * s->R);
+  if (cfg->ghost >= 4)
+    s->fhist = (double*)xmalloc(sizeof(double) * (size_t)s->R * s->E * D * Fq * s->V);
   s->nin = 2 * s->V + 2;
   s->nh = NH_MLP;
   s->nout = s->V;
@@ -485,7 +495,7 @@ void orc_destroy(void* vs) {
   free(s->phiF); free(s->wF); free(s->phiFN); free(s->lagF);
   free(s->Minv);
   free(s->u); free(s->ua); free(s->ub); free(s->kb); free(s->Fnum);
-  free(s->hist); free(s->mlp);
+  free(s->hist); free(s->fhist); free(s->mlp);
   free(s);
 }
 
@@ -578,7 +588,7 @@ static int raw_delay(const orc_solver* s, int64_t n, int64_t sub, int dir) {
       return (int)(orc_splitmix64_draw(s->c.seed, idx) % (uint64_t)(L + 1));
     }
     default: {
-      if (s->c.ghost == 1) {
+      if (s->c.ghost == 1 || s->c.ghost == 4) {
         /* Alg. caa-std: communicate when n % L == 0, delay counts silent steps */
         return L > 0 ? (int)(n % L) : 0;
       }
@@ -799,6 +809,41 @@ static void face_fluxes(orc_solver* s, const double* uin, int stage, int use_gho
       double* FR = s->Fnum + ((size_t)e * nf + fR) * Fq * V;
       double* FL = s->Fnum + ((size_t)e2 * nf + fL) * Fq * V;
       int pe = use_ghosts && s->c.ghost != 0 && is_pe_face(s, e, e2);
+      if (pe && s->c.ghost >= 4) {
+        /* Alg. caa-std / caa-at: at the first stage of a communicating step
+         * the flux computed from current data is stored; silent steps reuse
+         * the stored flux (FLUX_STALE) or extrapolate the stored history to
+         * the stage time (FLUX_AT, eq. at-flux on fluxes). Both sides of the
+         * face see the same value. */
+        int k = orc_delay(s, s->n, orc_subdomain(s, e), fR);
+        size_t lvl = (size_t)E * D * Fq * V;
+        size_t off = ((size_t)e * D + a) * Fq * V;
+        double c[MAXN];
+        if (k > 0 && s->c.ghost == 5) orc_at_weights(s->c.levels, k + SSP_C[stage], c);
+        for (int fq = 0; fq < Fq; ++fq) {
+          if (k == 0) {
+            trace_at(s, uin, e, fR, fq, wm);
+            trace_at(s, uin, e2, fL, fq, wp);
+            num_flux(s, wm, wp, a, 1.0, G);
+            if (stage == 0)
+              for (int v = 0; v < V; ++v) s->fhist[(size_t)(s->n % s->R) * lvl + off + fq * V + v] = G[v];
+          } else if (s->c.ghost == 4) {
+            for (int v = 0; v < V; ++v) G[v] = s->fhist[(size_t)((s->n - k) % s->R) * lvl + off + fq * V + v];
+          } else {
+            for (int v = 0; v < V; ++v) {
+              double acc = 0.0;
+              for (int j = 0; j < s->c.levels; ++j)
+                acc += c[j] * s->fhist[(size_t)((s->n - k - j) % s->R) * lvl + off + fq * V + v];
+              G[v] = acc;
+            }
+          }
+          for (int v = 0; v < V; ++v) {
+            FR[fq * V + v] = G[v];
+            FL[fq * V + v] = -G[v];
+          }
+        }
+        continue;
+      }
       if (pe) {
         ghost_face(s, uin, e, fR, stage, gA);  /* e's picture of e2 */
         ghost_face(s, uin, e2, fL, stage, gB); /* e2's picture of e */
@@ -933,7 +978,7 @@ int orc_step(void* vs, int64_t nsteps, double dt) {
   orc_solver* s = (orc_solver*)vs;
   size_t nd = (size_t)orc_ndof(s);
   for (int64_t it = 0; it < nsteps; ++it) {
-    if (s->R > 0) memcpy(s->hist + (size_t)(s->n % s->R) * nd, s->u, sizeof(double) * nd);
+    if (s->hist) memcpy(s->hist + (size_t)(s->n % s->R) * nd, s->u, sizeof(double) * nd);
     double* in[3] = {s->u, s->ua, s->ub};
     double* outp[3] = {s->ua, s->ub, s->u};
     for (int m = 0; m < 3; ++m) {

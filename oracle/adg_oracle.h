@@ -30,7 +30,10 @@ typedef struct orc_cfg {
   double lo[3], hi[3];  /* periodic box */
   double gamma;         /* ratio of specific heats */
   int32_t flux;         /* 0: local Lax-Friedrichs as printed (lambda with 1/2), 1: Rusanov */
-  int32_t ghost;        /* 0 SYNC, 1 STALE (standard flux on old traces), 2 AT, 3 LEARNED */
+  int32_t ghost;        /* 0 SYNC, 1 STALE (standard flux on old traces), 2 AT, 3 LEARNED,
+                           4 FLUX_STALE (Alg. caa-std: the stored flux is reused),
+                           5 FLUX_AT (Alg. caa-at: AT over stored fluxes); 4 and 5 need the
+                           CAA delay schedule */
   int32_t delay_kind;   /* 0 FIXED (k=L), 1 UNIFORM {0..L}, 2 CAA schedule */
   int32_t L;            /* maximum delay */
   int32_t levels;       /* AT levels (order of the extrapolation) */

@@ -10,7 +10,7 @@ import numpy as np
 
 from . import build as _build
 
-SYNC, STALE, AT, LEARNED = 0, 1, 2, 3
+SYNC, STALE, AT, LEARNED, FLUX_STALE, FLUX_AT = 0, 1, 2, 3, 4, 5
 FIXED, UNIFORM, CAA = 0, 1, 2
 VORTEX, DENSITY_WAVE, CONSTANT = 0, 1, 2
 LLF, RUSANOV = 0, 1
