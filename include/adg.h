@@ -72,10 +72,17 @@ typedef int32_t adg_status;
 #define ADG_GHOST_STALE 1   /* standard flux on the trace delayed by k steps (eq. delayed-flux) */
 #define ADG_GHOST_AT 2      /* AT extrapolation of `levels` past traces (eq. at-flux) */
 #define ADG_GHOST_LEARNED 3 /* AT plus a learned correction, judged per face (AT fallback) */
+/* flux-history modes, ADG_DELAY_CAA only: the numerical flux at each PE face
+ * is computed from current data and stored at the first stage of
+ * communicating steps; silent steps reuse it (Alg. caa-std) or extrapolate the
+ * stored history to the stage time with the AT weights (Alg. caa-at). Both
+ * sides of a face use one value, so the scheme conserves under asynchrony. */
+#define ADG_GHOST_FLUX_STALE 4
+#define ADG_GHOST_FLUX_AT 5
 /* delay per (step, receiving subdomain, face direction) */
 #define ADG_DELAY_FIXED 0   /* k = L */
 #define ADG_DELAY_UNIFORM 1 /* k uniform in {0..L}, SplitMix64 draw from the seed */
-#define ADG_DELAY_CAA 2     /* Alg. caa-std (STALE) / Alg. caa-at (AT, LEARNED) schedule */
+#define ADG_DELAY_CAA 2     /* Alg. caa-std (STALE, FLUX_STALE) / Alg. caa-at (AT, LEARNED, FLUX_AT) schedule */
 /* analytic problems */
 #define ADG_VORTEX 0       /* isentropic vortex (Sec. 5.1), periodic; params x0,y0,beta,mean_u,mean_v */
 #define ADG_DENSITY_WAVE 1 /* rho = 1 + A sin(2 pi sum_k (x_k - u_k t)); params A,u1,u2,u3,p */
@@ -113,8 +120,12 @@ typedef struct adg_ctx_s* adg_ctx;
 adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_stream, adg_ctx* out);
 
 /* Sizes the caller must allocate: n_dof doubles per state register
- * (state_bytes = 8 n_dof), ring_bytes for the trace history (0 for SYNC),
- * scratch_bytes for the ghost traces and reductions. */
+ * (state_bytes = 8 n_dof), ring_bytes for the history (0 for SYNC): R levels
+ * of double[n_face_sides][V][P^(d-1)] face-node traces, or, in the
+ * flux-history modes, of double[n_face_sides][V][n_q^(d-1)] face-point
+ * fluxes, with R = L+1 (STALE, FLUX_STALE), L+levels (AT, FLUX_AT) or
+ * L+max(levels,4) (LEARNED); scratch_bytes for the ghost traces and
+ * reductions. */
 adg_status adg_sizes(adg_ctx ctx, size_t* n_dof, size_t* state_bytes, size_t* ring_bytes, size_t* scratch_bytes);
 
 /* Bind caller-owned device buffers: the three SSP-RK3 registers (u_n holds

@@ -18,6 +18,7 @@ ADG_FLUX_LLF, ADG_FLUX_RUSANOV = 0, 1
 ADG_SSPRK3 = 0
 ADG_FP64, ADG_FP32_CONTRACT = 0, 1
 ADG_GHOST_SYNC, ADG_GHOST_STALE, ADG_GHOST_AT, ADG_GHOST_LEARNED = 0, 1, 2, 3
+ADG_GHOST_FLUX_STALE, ADG_GHOST_FLUX_AT = 4, 5
 ADG_DELAY_FIXED, ADG_DELAY_UNIFORM, ADG_DELAY_CAA = 0, 1, 2
 ADG_VORTEX, ADG_DENSITY_WAVE, ADG_CONSTANT = 0, 1, 2
 

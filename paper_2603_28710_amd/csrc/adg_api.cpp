@@ -75,11 +75,14 @@ const double kSspC[3] = {0.0, 1.0, 0.5};
 
 adg_status check_async(const adg_config& c, const adg_async& a) {
   (void)c;
-  if (a.ghost < 0 || a.ghost > 3) return fail(ADG_ERR_INVALID, "async.ghost must be 0..3");
+  if (a.ghost < 0 || a.ghost > 5) return fail(ADG_ERR_INVALID, "async.ghost must be 0..5");
+  if (a.ghost >= ADG_GHOST_FLUX_STALE && a.delay_kind != ADG_DELAY_CAA)
+    return fail(ADG_ERR_INVALID, "the flux-history modes need the CAA delay schedule");
   if (a.delay_kind < 0 || a.delay_kind > 2) return fail(ADG_ERR_INVALID, "async.delay_kind must be 0..2");
   if (a.L < 0 || a.L > 16) return fail(ADG_ERR_INVALID, "async.L must be in 0..16");
   if (a.levels < 1 || a.levels > 4) return fail(ADG_ERR_INVALID, "async.levels must be in 1..4");
-  if (a.ghost == 1 && a.delay_kind == 2 && a.L < 1) return fail(ADG_ERR_INVALID, "CAA with STALE needs L >= 1");
+  if ((a.ghost == 1 || a.ghost == 4) && a.delay_kind == 2 && a.L < 1)
+    return fail(ADG_ERR_INVALID, "CAA with a stale trace or flux needs L >= 1");
   if (!(a.learned_tol >= 0.0)) return fail(ADG_ERR_INVALID, "async.learned_tol must be >= 0");
   return ADG_OK;
 }
@@ -89,8 +92,18 @@ void depth_of(const adg_async& a, int& R, int& Qh) {
     case 0: R = 0; Qh = 1; break;
     case 1: R = a.L + 1; Qh = 1; break;
     case 2: R = a.L + a.levels; Qh = a.levels; break;
-    default: Qh = a.levels > kMlpK ? a.levels : kMlpK; R = a.L + Qh; break;
+    case 3: Qh = a.levels > kMlpK ? a.levels : kMlpK; R = a.L + Qh; break;
+    case 4: R = a.L + 1; Qh = 1; break;
+    default: R = a.L + a.levels; Qh = a.levels; break;
   }
+}
+
+// values per ring level: face-node traces (trace modes) or face-point fluxes
+// (flux-history modes) of every PE face-side
+size_t ring_level_values(const Mesh& M, int D, int P, int ghost) {
+  const int Q = P + 1;
+  const size_t per = ghost >= ADG_GHOST_FLUX_STALE ? (D == 3 ? Q * Q : Q) : (D == 3 ? P * P : P);
+  return (size_t)M.nfs * (D + 2) * per;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -112,7 +125,7 @@ Async make_async(const adg_ctx_s* c, int stage) {
   A.slot_n = c->R > 0 ? (int)(c->n % c->R) : 0;
   unsigned mod = 1;
   if (A.delay_kind == 1) mod = A.L + 1;
-  if (A.delay_kind == 2) mod = A.ghost == 1 ? A.L : A.L + A.Qh;
+  if (A.delay_kind == 2) mod = (A.ghost == 1 || A.ghost == 4) ? A.L : A.L + A.Qh;
   A.kmod = make_fastmod64(mod > 0 ? mod : 1);
   return A;
 }
@@ -199,7 +212,9 @@ static adg_status run_stage(adg_ctx_s* c, int m, double dt, bool learned_collect
   // learned predictor (and pair collection) runs as its own kernel first
   int src = kSrcLive;
   if (A.ghost != 0 && c->mesh.nfs > 0) {
-    if (A.ghost == 3 || learned_collect) {
+    if (A.ghost >= ADG_GHOST_FLUX_STALE) {
+      src = kSrcFlux;
+    } else if (A.ghost == 3 || learned_collect) {
       PROF_TRY(prof_begin(c, ADG_KERNEL_GHOST));
       HIP_TRY(launch_ghost_learned(c->D, c->p, c->mesh, A, in[m], c->u_n, c->ring, ghost, m == 0, c->mlp,
                                    pair_base, learned_collect, c->stream));
@@ -335,7 +350,7 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
     return fail(ADG_ERR_INVALID, "degree out of range");
   }
   // buffer plan
-  x->ring_bytes = (size_t)x->R * (size_t)M.nfs * x->V * x->Fn * sizeof(double);
+  x->ring_bytes = (size_t)x->R * ring_level_values(M, x->D, x->P, x->as.ghost) * sizeof(double);
   size_t s = 0;
   x->ghost_off = s;
   s = align256(s + (size_t)M.nfs * x->V * x->Fn * sizeof(double));
@@ -446,7 +461,7 @@ adg_status adg_set_async(adg_ctx c, const adg_async* a) {
   if (s != ADG_OK) return s;
   int R, Qh;
   depth_of(*a, R, Qh);
-  const size_t need = (size_t)R * (size_t)c->mesh.nfs * c->V * c->Fn * sizeof(double);
+  const size_t need = (size_t)R * ring_level_values(c->mesh, c->D, c->P, a->ghost) * sizeof(double);
   if (c->bound && need > c->ring_cap)
     return fail(ADG_ERR_INVALID, "ring bound at adg_bind is too small for this depth (" + std::to_string(need) +
                                      " bytes needed)");

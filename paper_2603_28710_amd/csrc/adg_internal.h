@@ -266,7 +266,7 @@ __host__ __device__ inline int delay_of(const Mesh& M, const Async& A, int sub, 
         ((unsigned long long)A.n * (unsigned long long)M.nsub + (unsigned long long)sub) * (2ull * M.dim) +
         (unsigned long long)f;
     k = fmod64(splitmix64(A.seed, idx), A.kmod);  // mod (L + 1)
-  } else if (A.ghost == 1) {
+  } else if (A.ghost == 1 || A.ghost == 4) {
     k = fmod64((unsigned long long)A.n, A.kmod);  // Alg. caa-std: n mod L
   } else {
     const long long r = fmod64((unsigned long long)A.n, A.kmod);  // Alg. caa-at: n mod (L + Q)
@@ -295,8 +295,12 @@ __host__ __device__ inline double at_weight(int l, int nlev, double tau) {
 // kSrcLive   every face reads the neighbour's live stage values (synchronous);
 // kSrcRing   the kernel builds the delayed / AT trace from the ring itself and,
 //            at stage 0, publishes its own boundary traces (stale and AT modes);
-// kSrcGhost  PE faces read a ghost buffer built by a separate kernel (learned).
-enum GhostSrc { kSrcLive = 0, kSrcRing = 1, kSrcGhost = 2 };
+// kSrcGhost  PE faces read a ghost buffer built by a separate kernel (learned);
+// kSrcFlux   the ring holds numerical fluxes at the face Gauss points: stored
+//            at stage 0 of communicating steps (delay 0), reused (FLUX_STALE)
+//            or AT-extrapolated (FLUX_AT) in silent steps (Alg. caa-std /
+//            caa-at).
+enum GhostSrc { kSrcLive = 0, kSrcRing = 1, kSrcGhost = 2, kSrcFlux = 3 };
 
 hipError_t launch_rhs_stage(int dim, int degree, int precision, const Mesh& M, const Async& A, const Stage& S,
                             const double* u_in, const double* u_n, double* out, int src, double* ring,

@@ -228,7 +228,9 @@ __global__ __launch_bounds__(kNT3) void rhs_stage_kernel(Mesh M, Async A, Stage 
   const int ne = (int)(M.E - e0 < NE ? M.E - e0 : NE);
   const int tid = threadIdx.x;
   const bool async_on = src != kSrcLive && M.nfs > 0;
-  const long long ring_level = M.nfs * V * Fn;  // values per ring level
+  const bool flux_mode = src == kSrcFlux;
+  // values per ring level: face-node traces, or face-point fluxes
+  const long long ring_level = M.nfs * V * (flux_mode ? Fq : Fn);
   const bool publish = src == kSrcRing && A.stage == 0;
 
   // per element face: neighbour, PE face-side, delay, and the face-side it feeds
@@ -237,8 +239,8 @@ __global__ __launch_bounds__(kNT3) void rhs_stage_kernel(Mesh M, Async A, Stage 
     const ElemPos pos = elem_pos(M, e0 + le);
     sNb[t] = neighbour_of(M, e0 + le, pos, f) * V * Pd;
     const long long fs = async_on ? face_side_at(M, pos, f) : -1;
-    sFs[t] = fs >= 0 ? fs * V * Fn : -1;
-    sK[t] = fs >= 0 && src == kSrcRing ? delay_of(M, A, sub_at(M, pos.sc), f) : 0;
+    sFs[t] = fs >= 0 ? fs * V * (flux_mode ? Fq : Fn) : -1;
+    sK[t] = fs >= 0 && (src == kSrcRing || flux_mode) ? delay_of(M, A, sub_at(M, pos.sc), f) : 0;
     sPub[t] = publish && fs >= 0 ? fed_face_side(M, pos, f) * V * Fn : -1;
   }
   for (int i = tid; i < to.total; i += kNT3) sT[i] = tab[i];
@@ -400,11 +402,15 @@ __global__ __launch_bounds__(kNT3) void rhs_stage_kernel(Mesh M, Async A, Stage 
       const int t = le * nf + f;
       const long long fs = sFs[t];
       const int k = sK[t];
-      if (fs < 0 || (src == kSrcRing && k == 0)) {
+      if (fs < 0 || ((src == kSrcRing || flux_mode) && k == 0)) {
         // interior face, synchronous mode, or zero delay: live stage values
         const double* g = u_in + sNb[t] + face_node<D, P>(f ^ 1, j);
 #pragma unroll
         for (int v = 0; v < V; ++v) dst[v * Fn] = (T)g[v * Pd];
+      } else if (flux_mode) {
+        // silent step: the face uses the stored flux, no trace needed
+#pragma unroll
+        for (int v = 0; v < V; ++v) dst[v * Fn] = (T)0;
       } else if (src == kSrcGhost) {
         const double* g = ghost + fs + j;
 #pragma unroll
@@ -458,7 +464,39 @@ __global__ __launch_bounds__(kNT3) void rhs_stage_kernel(Mesh M, Async A, Stage 
         wl[v] = s ? wo[v] : wn[v];
         wr[v] = s ? wn[v] : wo[v];
       }
-      num_flux<T, D>(wl, wr, a, gamma, M.flux, G);
+      const int tf = le * nf + 2 * a + s;
+      const long long ffs = flux_mode && le < ne ? sFs[tf] : -1;
+      const int fkd = flux_mode && le < ne ? sK[tf] : 0;
+      if (ffs >= 0 && fkd > 0) {
+        // silent step of Alg. caa-std / caa-at: the stored flux, or its AT
+        // extrapolation to the stage time tau = k + c_m (FP64)
+        const double* fp = ring + ffs + fq;
+        double acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = 0.0;
+        if (A.ghost == 4) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) acc[v] = fp[ring_slot(A, fkd) * ring_level + v * Fq];
+        } else {
+          const double tau = fkd + A.c_m;
+          for (int l = 0; l < A.levels; ++l) {
+            const double w = at_weight(l, A.levels, tau);
+            const double* lp = fp + ring_slot(A, fkd + l) * ring_level;
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] = fma(w, lp[v * Fq], acc[v]);
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) G[v] = (T)acc[v];
+      } else {
+        num_flux<T, D>(wl, wr, a, gamma, M.flux, G);
+        // communicating step of a flux-history mode: keep the stage-0 flux
+        if (ffs >= 0 && A.stage == 0) {
+          double* fp = ring + A.slot_n * ring_level + ffs + fq;
+#pragma unroll
+          for (int v = 0; v < V; ++v) fp[v * Fq] = (double)G[v];
+        }
+      }
       T ws = sT[to.WQ + fq % Q];
       if (D == 3) ws *= sT[to.WQ + fq / Q];
       ws *= (T)(2.0 / M.h[a]);

@@ -129,6 +129,10 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
   constexpr int PER0 = Qd * V > 16 * Q ? Qd * V : 16 * Q;
   constexpr int PER = sizeof(T) == 8 ? PER0 + (6 - PER0 % 4) % 4 : PER0 + (12 - PER0 % 8) % 8;
   __shared__ __align__(16) T sX[NE * PER];
+  // flux-history modes: per (element, face of the current axis) the
+  // face-side offset in the flux ring (or -1) and the delay
+  __shared__ long long sFsF[NE * 2];
+  __shared__ int sKdF[NE * 2];
 
   const int lane = threadIdx.x, le = lane >> 2, v = lane & 3;
   const long long e = (long long)xcd_block2() * NE + le;
@@ -235,7 +239,8 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
 
   // ---- per-face neighbour data: element, PE face-side, delay
   const bool async_on = src != kSrcLive && M.nfs > 0;
-  const long long ring_level = M.nfs * V * P;
+  const bool flux_mode = src == kSrcFlux;
+  const long long ring_level = M.nfs * V * (flux_mode ? Q : P);  // values per ring level
   const bool publish = src == kSrcRing && A.stage == 0;
 
   // ---- faces, one axis per pass
@@ -249,16 +254,17 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
       double g[P];  // neighbour trace at the face nodes
 #pragma unroll
       for (int j = 0; j < P; ++j) g[j] = 0.0;
+      long long fs = -1;
+      int kd = 0;
       if (valid) {
-        const long long fs = async_on ? face_side_at(M, pos, f) : -1;
-        int kd = 0;
-        if (fs >= 0 && src == kSrcRing) kd = delay_of(M, A, sub_at(M, pos.sc), f);
+        fs = async_on ? face_side_at(M, pos, f) : -1;
+        if (fs >= 0 && (src == kSrcRing || flux_mode)) kd = delay_of(M, A, sub_at(M, pos.sc), f);
         if (fs >= 0 && publish) {
           double* dst = ring + A.slot_n * ring_level + fed_face_side(M, pos, f) * V * P + v * P;
 #pragma unroll
           for (int j = 0; j < P; ++j) dst[j] = u[fnode<P>(f, j)];
         }
-        if (fs < 0 || (src == kSrcRing && kd == 0)) {
+        if (fs < 0 || ((src == kSrcRing || flux_mode) && kd == 0)) {
           if (a == 0) {
 #pragma unroll
             for (int j = 0; j < P; ++j) g[j] = nbv[s][j];
@@ -268,6 +274,8 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
 #pragma unroll
             for (int j = 0; j < P; ++j) g[j] = gp[fnode<P>(f ^ 1, j)];
           }
+        } else if (flux_mode) {
+          // silent step: the face uses the stored flux, no trace needed
         } else if (src == kSrcGhost) {
           const double* gp = ghost + fs * V * P + v * P;
 #pragma unroll
@@ -287,6 +295,10 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
             for (int j = 0; j < P; ++j) g[j] = fma(wl, gp[j], g[j]);
           }
         }
+      }
+      if (flux_mode && v == 0) {
+        sFsF[le * 2 + s] = fs;
+        sKdF[le * 2 + s] = kd;
       }
       T* dst = sX + le * PER + s * (2 * Q * V) + v;
 #pragma unroll
@@ -324,7 +336,36 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
             wl[vv] = pl[vv];
             wr[vv] = pr[vv];
           }
-          flux_llf<T>(wl, wr, a, gamma, M.flux, G);
+          const long long ffs = flux_mode ? sFsF[el * 2 + s] : -1;
+          const int fkd = flux_mode ? sKdF[el * 2 + s] : 0;
+          if (ffs >= 0 && fkd > 0) {
+            // silent step of Alg. caa-std / caa-at: the stored flux, or its
+            // AT extrapolation to the stage time tau = k + c_m (FP64)
+            const double* fp = ring + ffs * V * Q + q;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            if (A.ghost == 4) {
+#pragma unroll
+              for (int vv = 0; vv < 4; ++vv) acc[vv] = fp[ring_slot(A, fkd) * ring_level + vv * Q];
+            } else {
+              const double tau = fkd + A.c_m;
+              for (int l = 0; l < A.levels; ++l) {
+                const double w = at_weight(l, A.levels, tau);
+                const double* lp = fp + ring_slot(A, fkd + l) * ring_level;
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) acc[vv] = fma(w, lp[vv * Q], acc[vv]);
+              }
+            }
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) G[vv] = (T)acc[vv];
+          } else {
+            flux_llf<T>(wl, wr, a, gamma, M.flux, G);
+            // communicating step of a flux-history mode: keep the stage-0 flux
+            if (ffs >= 0 && A.stage == 0) {
+              double* fp = ring + A.slot_n * ring_level + ffs * V * Q + q;
+#pragma unroll
+              for (int vv = 0; vv < 4; ++vv) fp[vv * Q] = (double)G[vv];
+            }
+          }
           const T sg = s ? -sc : sc;
 #pragma unroll
           for (int vv = 0; vv < 4; ++vv) base[q * V + vv] = sg * G[vv];

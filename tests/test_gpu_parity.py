@@ -123,6 +123,7 @@ ASYNC_MODES = [
     ("stale_fixed2", 1, 0, 2, 1), ("stale_uniform3", 1, 1, 3, 1), ("stale_caa4", 1, 2, 4, 1),
     ("at3_fixed1", 2, 0, 1, 3), ("at3_uniform3", 2, 1, 3, 3), ("at3_caa3", 2, 2, 3, 3),
     ("at2_uniform2", 2, 1, 2, 2), ("at4_uniform2", 2, 1, 2, 4),
+    ("flux_stale_caa3", 4, 2, 3, 1), ("flux_at3_caa3", 5, 2, 3, 3), ("flux_at2_caa4", 5, 2, 4, 2),
 ]
 
 
@@ -152,6 +153,43 @@ def test_async_at_uniform_3d(oracle_mod, S, seed):
     r = rel_l2(s.download(), o.state(), 3, s=s)
     say("  rel L2", r)
     assert r <= TOL
+
+
+@pytest.mark.parametrize("ghost,precision", [(4, 0), (5, 0), (5, 1)])
+def test_flux_history_3d(oracle_mod, S, ghost, precision):
+    # Alg. caa-std / caa-at with stored fluxes on hexahedra: FP64 against the
+    # oracle; the FP32-contraction variant within 1e-6 of it
+    O = oracle_mod
+    say(f"case: density wave 3D p=2 8^3 parts 2^3 flux-history ghost={ghost} precision={precision}, 14 steps")
+    cfg = dict(dim=3, cells=(8, 8, 8), parts=(2, 2, 2), hi=(1, 1, 1), ghost=ghost, delay_kind=2, L=3, levels=3)
+    o = O.Oracle(p=2, **cfg)
+    o.init_problem(O.DENSITY_WAVE)
+    s = S(degree=2, precision=precision, **cfg)
+    s.upload(o.state())
+    dt = o.stable_dt(0.1)
+    o.step(14, dt)
+    s.step(14, dt)
+    r = rel_l2(s.download(), o.state(), 3, s=s)
+    say("  rel L2", r)
+    assert r <= (TOL if precision == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_flux_history_conserves_on_gpu(oracle_mod, S, dim):
+    # both sides of a PE face use one stored flux: the integrals stay put to
+    # round-off through silent steps
+    O = oracle_mod
+    say(f"case: flux-history AT conservation {dim}D")
+    cells = (32, 32, 1) if dim == 2 else (8, 8, 8)
+    parts = (4, 4, 1) if dim == 2 else (2, 2, 2)
+    s = S(dim=dim, degree=3 if dim == 2 else 2, cells=cells, parts=parts, hi=(10, 10, 1) if dim == 2 else (1, 1, 1),
+          ghost=5, delay_kind=2, L=3, levels=3)
+    s.init_problem(O.VORTEX if dim == 2 else O.DENSITY_WAVE)
+    I0 = np.array(s.integrals())
+    s.step(40, 0.5 * s.stable_dt(0.1))
+    I1 = np.array(s.integrals())
+    say("  max drift", np.abs(I1 - I0).max() / np.abs(I0).max())
+    assert np.all(np.abs(I1 - I0) <= 1e-13 * np.abs(I0).max())
 
 
 def test_zero_delay_bitwise_equals_sync(oracle_mod, S):

@@ -47,8 +47,10 @@ def test_create_rejects_bad_config(B, kw, msg):
     assert ei.value.code == B.ADG_ERR_INVALID and msg in str(ei.value)
 
 
-@pytest.mark.parametrize("kw", [dict(ghost=5), dict(delay_kind=4), dict(L=17), dict(levels=0),
-                                dict(levels=5), dict(ghost=1, delay_kind=2, L=0)])
+@pytest.mark.parametrize("kw", [dict(ghost=6), dict(delay_kind=4), dict(L=17), dict(levels=0),
+                                dict(levels=5), dict(ghost=1, delay_kind=2, L=0),
+                                dict(ghost=4, delay_kind=0, L=2), dict(ghost=5, delay_kind=1, L=2),
+                                dict(ghost=4, delay_kind=2, L=0)])
 def test_create_rejects_bad_async(B, kw):
     with pytest.raises(B.AdgError):
         B.adg_create(B.make_config(), B.make_async(**kw))
@@ -84,9 +86,22 @@ def test_sizes_match_oracle_face_sides(B, oracle_mod, dim, p, cells, parts, ghos
     B.adg_destroy(h)
 
 
+@pytest.mark.parametrize("dim,p,ghost,L,levels,R", [(2, 3, 4, 3, 1, 4), (2, 2, 5, 3, 3, 6), (3, 2, 5, 4, 2, 6)])
+def test_flux_history_ring_holds_face_point_fluxes(B, oracle_mod, dim, p, ghost, L, levels, R):
+    # one ring level = every PE face-side's V fluxes at its (p+2)^(d-1) Gauss points
+    cells = (8, 8, 8 if dim == 3 else 1)
+    parts = (2, 4, 2 if dim == 3 else 1)
+    h = B.adg_create(B.make_config(dim=dim, degree=p, cells=cells, parts=parts, hi=(1, 1, 1)),
+                     B.make_async(ghost=ghost, delay_kind=2, L=L, levels=levels))
+    _, _, rb, _ = B.adg_sizes(h)
+    nfs = oracle_mod.Oracle(dim=dim, p=p, cells=cells, parts=parts, hi=(1, 1, 1)).n_face_sides()
+    assert rb == R * nfs * (dim + 2) * (p + 2) ** (dim - 1) * 8
+    B.adg_destroy(h)
+
+
 @pytest.mark.parametrize("ghost,kind,L,levels", [
     (1, 0, 3, 1), (1, 1, 3, 1), (1, 2, 4, 1), (2, 0, 2, 3), (2, 1, 3, 3), (2, 2, 4, 3), (2, 2, 10, 3),
-    (2, 1, 2, 2), (3, 1, 4, 3), (3, 2, 3, 3),
+    (2, 1, 2, 2), (3, 1, 4, 3), (3, 2, 3, 3), (4, 2, 3, 1), (5, 2, 3, 3), (5, 2, 5, 2),
 ])
 def test_delay_schedule_identical_to_oracle(B, oracle_mod, ghost, kind, L, levels):
     O = oracle_mod
