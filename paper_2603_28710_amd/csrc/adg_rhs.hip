@@ -24,6 +24,7 @@
 // stream on identical operands in the same order, so their contributions are
 // bitwise opposite and the synchronous scheme conserves to round-off.
 // T = double (FP64 path) or float (FP32 contractions; combine in FP64).
+#include "adg_device.h"
 #include "adg_internal.h"
 #include "adg_tables.h"
 
@@ -54,9 +55,6 @@ constexpr KOps<T, P> make_kops() {
     for (int q = 0; q < Q; ++q) k.BTM[i * Q + q] = static_cast<T>(o.BTM[i][q]);
   return k;
 }
-
-__device__ __forceinline__ double fmx(double a, double b, double c) { return fma(a, b, c); }
-__device__ __forceinline__ float fmx(float a, float b, float c) { return fmaf(a, b, c); }
 
 template <int D, int P, int Q>
 struct Dims {
@@ -153,54 +151,6 @@ __device__ __forceinline__ int face_node(int f, int j) {
   if (a == 0) return s + P * (j0 + P * j1);
   if (a == 1) return j0 + P * (s + P * j1);
   return j0 + P * (j1 + P * s);
-}
-
-// n.F^ for n = +e_a with left state wl and right state wr (eq. lfflux,
-// lambda of eq. lfflux-lambda, or the Rusanov speed for kind 1)
-template <typename T, int D>
-__device__ __forceinline__ void num_flux(const T* wl, const T* wr, int a, T gamma, int kind, T* G) {
-  constexpr int V = D + 2;
-  const T gm1 = gamma - (T)1;
-  const T il = (T)1 / wl[0], ir = (T)1 / wr[0];
-  T ml2 = wl[1] * wl[1], mr2 = wr[1] * wr[1];
-#pragma unroll
-  for (int k = 1; k < D; ++k) {
-    ml2 = fmx(wl[1 + k], wl[1 + k], ml2);
-    mr2 = fmx(wr[1 + k], wr[1 + k], mr2);
-  }
-  const T pl = gm1 * (wl[D + 1] - (T)0.5 * ml2 * il), pr = gm1 * (wr[D + 1] - (T)0.5 * mr2 * ir);
-  const T ual = wl[1 + a] * il, uar = wr[1 + a] * ir;
-  T Fl[V], Fr[V];
-  Fl[0] = wl[1 + a];
-  Fr[0] = wr[1 + a];
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    Fl[1 + k] = wl[1 + k] * ual + (k == a ? pl : (T)0);
-    Fr[1 + k] = wr[1 + k] * uar + (k == a ? pr : (T)0);
-  }
-  Fl[D + 1] = (wl[D + 1] + pl) * ual;
-  Fr[D + 1] = (wr[D + 1] + pr) * uar;
-  const T cl2 = gamma * pl * il, cr2 = gamma * pr * ir;
-  T lam;
-  if (kind == 1) {
-    const T sl = fabs(ual) + sqrt(cl2), sr = fabs(uar) + sqrt(cr2);
-    lam = sl > sr ? sl : sr;
-  } else {
-    const T sl = ml2 * il * il + cl2, sr = mr2 * ir * ir + cr2;
-    lam = (T)0.5 * sqrt(sl > sr ? sl : sr);
-  }
-  const T hl = (T)0.5 * lam;
-#pragma unroll
-  for (int v = 0; v < V; ++v) G[v] = (T)0.5 * (Fl[v] + Fr[v]) + hl * (wl[v] - wr[v]);
-}
-
-// logical block index: the hardware deals consecutive blocks round-robin to
-// the 8 XCDs; remap so each XCD walks a contiguous range of elements and its
-// L2 holds the neighbours it reads
-__device__ __forceinline__ int xcd_block() {
-  const int nb = gridDim.x, i = blockIdx.x;
-  const int per = nb / 8, rem = nb % 8, x = i % 8, k = i / 8;
-  return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
 }
 
 template <typename T, int D, int P, int Q, int NE>
@@ -565,7 +515,7 @@ static hipError_t launch_rhs_prec(int dim, int degree, const Mesh& M, const Asyn
                                   const double* ghost, const T* tab, hipStream_t st) {
 #define ADG_RHS_CASE(d, p) \
   if (dim == d && degree == p) return launch_rhs_t<T, d, p>(M, A, S, u_in, u_n, out, src, ring, ghost, tab, st);
-  ADG_RHS_CASE(3, 1) ADG_RHS_CASE(3, 2) ADG_RHS_CASE(3, 3) ADG_RHS_CASE(3, 4)
+  ADG_RHS_CASE(3, 3) ADG_RHS_CASE(3, 4)
 #undef ADG_RHS_CASE
   return hipErrorInvalidValue;
 }
@@ -575,6 +525,8 @@ hipError_t launch_rhs_stage(int dim, int degree, int precision, const Mesh& M, c
                             const double* ghost, const double* tab64, const float* tab32, hipStream_t st) {
   if (dim == 2)
     return launch_rhs_stage_2d(degree, precision, M, A, S, u_in, u_n, out, src, ring, ghost, st);
+  if (degree <= 2)
+    return launch_rhs_stage_3d(degree, precision, M, A, S, u_in, u_n, out, src, ring, ghost, st);
   if (precision == 1)
     return launch_rhs_prec<float>(dim, degree, M, A, S, u_in, u_n, out, src, ring, ghost, tab32, st);
   return launch_rhs_prec<double>(dim, degree, M, A, S, u_in, u_n, out, src, ring, ghost, tab64, st);

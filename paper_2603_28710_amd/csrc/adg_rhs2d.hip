@@ -29,6 +29,7 @@
 // PE-boundary traces of u^n into ring slot n mod R; readers in the same launch
 // use only older slots (delay >= 1) or live values (delay 0).
 // T = double (FP64 path) or float (FP32 contractions, FP64 state and combine).
+#include "adg_device.h"
 #include "adg_internal.h"
 #include "adg_tables.h"
 
@@ -38,64 +39,10 @@ namespace {
 
 constexpr int kNE2 = 16;  // elements per wavefront (V = 4 lanes each)
 
-__device__ __forceinline__ double fmx2(double a, double b, double c) { return fma(a, b, c); }
-__device__ __forceinline__ float fmx2(float a, float b, float c) { return fmaf(a, b, c); }
-
-// 1/x to an ulp or two: the hardware estimate refined by Newton steps (two in
-// FP64, one in FP32); every use of a given operand gives the same result
-__device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return fma(r, fma(-x, r, 1.0), r);
-}
-__device__ __forceinline__ float recip(float x) {
-  const float r = __builtin_amdgcn_rcpf(x);
-  return fmaf(r, fmaf(-x, r, 1.0f), r);
-}
-
-// logical block index, XCD-aware (consecutive blocks go round-robin to the 8
-// XCDs; each XCD walks one contiguous range of elements)
-__device__ __forceinline__ int xcd_block2() {
-  const int nb = gridDim.x, i = blockIdx.x;
-  const int per = nb / 8, rem = nb % 8, x = i % 8, k = i / 8;
-  return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
-}
-
 // node index of face-local node j on face f (2D, x fastest)
 template <int P>
 __device__ __forceinline__ constexpr int fnode(int f, int j) {
   return (f >> 1) == 0 ? j * P + ((f & 1) ? P - 1 : 0) : ((f & 1) ? P - 1 : 0) * P + j;
-}
-
-// n.F^ for n = +e_a, left state wl, right state wr (LLF or Rusanov speed)
-template <typename T>
-__device__ __forceinline__ void flux_llf(const T* wl, const T* wr, int a, T gamma, int kind, T* G) {
-  const T gm1 = gamma - (T)1;
-  const T il = recip(wl[0]), ir = recip(wr[0]);
-  const T ml2 = fmx2(wl[2], wl[2], wl[1] * wl[1]), mr2 = fmx2(wr[2], wr[2], wr[1] * wr[1]);
-  const T pl = gm1 * (wl[3] - (T)0.5 * ml2 * il), pr = gm1 * (wr[3] - (T)0.5 * mr2 * ir);
-  const T ual = wl[1 + a] * il, uar = wr[1 + a] * ir;
-  T Fl[4], Fr[4];
-  Fl[0] = wl[1 + a];
-  Fr[0] = wr[1 + a];
-  Fl[1] = wl[1] * ual + (a == 0 ? pl : (T)0);
-  Fr[1] = wr[1] * uar + (a == 0 ? pr : (T)0);
-  Fl[2] = wl[2] * ual + (a == 1 ? pl : (T)0);
-  Fr[2] = wr[2] * uar + (a == 1 ? pr : (T)0);
-  Fl[3] = (wl[3] + pl) * ual;
-  Fr[3] = (wr[3] + pr) * uar;
-  const T cl2 = gamma * pl * il, cr2 = gamma * pr * ir;
-  T lam;
-  if (kind == 1) {
-    const T sl = fabs(ual) + sqrt(cl2), sr = fabs(uar) + sqrt(cr2);
-    lam = sl > sr ? sl : sr;
-  } else {
-    const T sl = ml2 * il * il + cl2, sr = mr2 * ir * ir + cr2;
-    lam = (T)0.5 * sqrt(sl > sr ? sl : sr);
-  }
-  const T hl = (T)0.5 * lam;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) G[v] = (T)0.5 * (Fl[v] + Fr[v]) + hl * (wl[v] - wr[v]);
 }
 
 template <int P>
@@ -135,7 +82,7 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
   __shared__ int sKdF[NE * 2];
 
   const int lane = threadIdx.x, le = lane >> 2, v = lane & 3;
-  const long long e = (long long)xcd_block2() * NE + le;
+  const long long e = (long long)xcd_block() * NE + le;
   const bool valid = e < M.E;
   const long long col = (valid ? e : 0) * (V * Pd) + v * Pd;  // this lane's P^2 values
 
@@ -156,7 +103,7 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
       for (int qx = 0; qx < Q; ++qx) {
         T acc = (T)O.B[qx][0] * (T)u[iy * P];
 #pragma unroll
-        for (int ix = 1; ix < P; ++ix) acc = fmx2((T)O.B[qx][ix], (T)u[iy * P + ix], acc);
+        for (int ix = 1; ix < P; ++ix) acc = fmx((T)O.B[qx][ix], (T)u[iy * P + ix], acc);
         X[iy][qx] = acc;
       }
     T* dst = sX + le * PER + v;
@@ -166,7 +113,7 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
       for (int qx = 0; qx < Q; ++qx) {
         T acc = (T)O.B[qy][0] * X[0][qx];
 #pragma unroll
-        for (int iy = 1; iy < P; ++iy) acc = fmx2((T)O.B[qy][iy], X[iy][qx], acc);
+        for (int iy = 1; iy < P; ++iy) acc = fmx((T)O.B[qy][iy], X[iy][qx], acc);
         dst[(qy * Q + qx) * V] = acc;
       }
   }
@@ -207,19 +154,19 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
         const T wv = w[v];
         const T ir = recip(rho);
         const T ux = mx * ir, uy = my * ir;
-        const T p = gm1 * (en - (T)0.5 * fmx2(my, uy, mx * ux));
-        const T t = fmx2(p, e3, wv);
+        const T p = gm1 * (en - (T)0.5 * fmx(my, uy, mx * ux));
+        const T t = fmx(p, e3, wv);
         // F_x[v] = u_x (w_v + p [v=3]) + p [v=1], F_y alike
-        const T fx = fmx2(ux, t, p * e1);
-        const T fy = fmx2(uy, t, p * e2);
+        const T fx = fmx(ux, t, p * e1);
+        const T fy = fmx(uy, t, p * e2);
 #pragma unroll
         for (int i = 0; i < P; ++i) {
           if (qx == 0) {
             tx[i] = (T)O.GW[i][0] * fx;
             ty[i] = (T)O.BW[i][0] * fy;
           } else {
-            tx[i] = fmx2((T)O.GW[i][qx], fx, tx[i]);
-            ty[i] = fmx2((T)O.BW[i][qx], fy, ty[i]);
+            tx[i] = fmx((T)O.GW[i][qx], fx, tx[i]);
+            ty[i] = fmx((T)O.BW[i][qx], fy, ty[i]);
           }
         }
       }
@@ -232,7 +179,7 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
       for (int iy = 0; iy < P; ++iy) {
         const T bw = (T)OD.BW[iy][qy], gw = (T)OD.GW[iy][qy];
 #pragma unroll
-        for (int ix = 0; ix < P; ++ix) k[iy * P + ix] = fmx2(gw, ty[ix], fmx2(bw, tx[ix], k[iy * P + ix]));
+        for (int ix = 0; ix < P; ++ix) k[iy * P + ix] = fmx(gw, ty[ix], fmx(bw, tx[ix], k[iy * P + ix]));
       }
     }
   }
@@ -307,8 +254,8 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
         T n = (T)O.B[q][0] * (T)g[0];
 #pragma unroll
         for (int j = 1; j < P; ++j) {
-          o = fmx2((T)O.B[q][j], (T)u[fnode<P>(f, j)], o);
-          n = fmx2((T)O.B[q][j], (T)g[j], n);
+          o = fmx((T)O.B[q][j], (T)u[fnode<P>(f, j)], o);
+          n = fmx((T)O.B[q][j], (T)g[j], n);
         }
         dst[q * V] = o;
         dst[(Q + q) * V] = n;
@@ -358,7 +305,7 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) G[vv] = (T)acc[vv];
           } else {
-            flux_llf<T>(wl, wr, a, gamma, M.flux, G);
+            num_flux<T, 2>(wl, wr, a, gamma, M.flux, G);
             // communicating step of a flux-history mode: keep the stage-0 flux
             if (ffs >= 0 && A.stage == 0) {
               double* fp = ring + A.slot_n * ring_level + ffs * V * Q + q;
@@ -384,11 +331,11 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
       for (int j = 0; j < P; ++j) {
         T tj = (T)O.BW[j][0] * G[0];
 #pragma unroll
-        for (int q = 1; q < Q; ++q) tj = fmx2((T)O.BW[j][q], G[q], tj);
+        for (int q = 1; q < Q; ++q) tj = fmx((T)O.BW[j][q], G[q], tj);
 #pragma unroll
         for (int ia = 0; ia < P; ++ia) {
           const int node = a == 0 ? j * P + ia : ia * P + j;
-          k[node] = fmx2((T)O.MC[s][ia], tj, k[node]);
+          k[node] = fmx((T)O.MC[s][ia], tj, k[node]);
         }
       }
     }

@@ -1,0 +1,410 @@
+// adg_rhs3d.hip — the fused SSP-RK3 stage on hexahedral meshes of degree
+// 1 and 2, with the element data in registers.
+//
+// One wavefront owns 12 consecutive elements (x fastest); lane (e, v) keeps
+// the P^3 nodal values of variable v of element e in registers (lanes 60-63
+// idle) and applies the tensor-product operators of that variable there. LDS
+// carries only what the nonlinear fluxes need (all V variables at a point).
+//
+//   volume: one Gauss plane q_z at a time. The lane combines its nodal
+//           planes along z (B), interpolates the result in x and y, and
+//           stores the plane's values; row by row it then reads the full
+//           state, forms its own flux components F_x[v], F_y[v], F_z[v]
+//           (eq. euler-dealii) and accumulates
+//             k += (2/h_x) (GW (x) BW (x) BW) F_x + (2/h_y) (BW (x) GW (x) BW) F_y
+//                + (2/h_z) (BW (x) BW (x) GW) F_z
+//           (BW = M1^{-1} B^T W, GW = M1^{-1} B^T D^T W per direction;
+//           eq. weakform-dealii / weakform-compact-dealii).
+//   faces:  one face direction at a time. Each lane interpolates its own and
+//           the neighbour's face traces (live values; the delayed / AT /
+//           learned trace at a PE-boundary face; or, in the flux-history
+//           modes, the stored flux) to the face's Gauss points; one lane per
+//           (element, point) evaluates the LLF flux (eq. lfflux /
+//           lfflux-lambda) in canonical (left, right) order; each lane lifts
+//           its variable with BW along the two tangential axes and adds the
+//           column of M1^{-1} at that face.
+//   stage:  out = a u_n + b (u_in + dt k) in FP64 from the FP64 registers.
+//
+// The ring publish (stage 0, stale and AT modes), the delay schedule, the AT
+// extrapolation and the flux history follow the same rules as the other
+// stage kernels. T = double (FP64) or float (FP32 contractions).
+#include <type_traits>
+
+#include "adg_device.h"
+#include "adg_internal.h"
+#include "adg_tables.h"
+
+namespace adg {
+
+namespace {
+
+constexpr int kNE3 = 12;  // elements per wavefront (V = 5 lanes each)
+
+// node index (x fastest) of the node with coordinate ia along axis a and
+// coordinates (j0, j1) along the other two axes in ascending order
+template <int P>
+__device__ __forceinline__ constexpr int node3(int a, int ia, int j0, int j1) {
+  return a == 0 ? ia + P * (j0 + P * j1) : (a == 1 ? j0 + P * (ia + P * j1) : j0 + P * (j1 + P * ia));
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage S, const double* __restrict__ u_in,
+                                                         const double* u_n, double* out, int src,
+                                                         double* __restrict__ ring,
+                                                         const double* __restrict__ ghost) {
+  constexpr int Q = P + 1, V = 5, NE = kNE3, Pd = P * P * P, Fn = P * P, Fq = Q * Q;
+  constexpr ops::Ops<P> O = ops::make_ops<P>();
+  const ops::Ops<P>& OD = ops::kOps<P>;  // entries indexed at run time
+  // per element: the state at the points of one Gauss plane [Fq][V] during
+  // the volume, the own and neighbour traces of one face [2][Fq][V] during
+  // the faces; one spare element slot for the idle lanes; the stride is
+  // padded so 16-byte reads of consecutive elements spread over the banks
+  constexpr int PER0 = 2 * Fq * V;
+  constexpr int PER = sizeof(T) == 8 ? PER0 + (6 - PER0 % 4) % 4 : PER0 + (12 - PER0 % 8) % 8;
+  __shared__ __align__(16) T sX[(NE + 1) * PER];
+  __shared__ long long sFsF[NE + 1];  // flux-history modes: face-side of the current face, or -1
+  __shared__ int sKdF[NE + 1];        // and its delay
+
+  const int lane = threadIdx.x, le = lane / V, v = lane - le * V;  // le == NE: idle lane
+  const long long e = (long long)xcd_block() * NE + le;
+  const bool valid = le < NE && e < M.E;
+  const long long col = (valid ? e : 0) * (V * Pd) + v * Pd;  // this lane's P^3 values
+
+  double u[Pd];
+#pragma unroll
+  for (int i = 0; i < Pd; ++i) u[i] = valid ? u_in[col + i] : 0.0;
+
+  T k[Pd];
+#pragma unroll
+  for (int i = 0; i < Pd; ++i) k[i] = (T)0;
+  T* mine = sX + le * PER;
+
+  // ---- volume, one Gauss plane q_z at a time
+  {
+    const T gm1 = (T)M.gamma - (T)1;
+    const T sx = (T)(2.0 / M.h[0]), sy = (T)(2.0 / M.h[1]), sz = (T)(2.0 / M.h[2]);
+    const T e1 = v == 1 ? (T)1 : (T)0, e2 = v == 2 ? (T)1 : (T)0, e3 = v == 3 ? (T)1 : (T)0;
+    const T e4 = v == 4 ? (T)1 : (T)0;
+#pragma unroll 1
+    for (int qz = 0; qz < Q; ++qz) {
+      if (qz) __syncthreads();  // the previous plane has been read
+      T bq[P], bw[P], gw[P];
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        bq[i] = (T)OD.B[qz][i];
+        bw[i] = (T)OD.BW[i][qz];
+        gw[i] = (T)OD.GW[i][qz];
+      }
+      // this lane's variable on the plane: z combination, then x, then y
+      {
+        T Z[P][P];
+#pragma unroll
+        for (int iy = 0; iy < P; ++iy)
+#pragma unroll
+          for (int ix = 0; ix < P; ++ix) {
+            T acc = bq[0] * (T)u[iy * P + ix];
+#pragma unroll
+            for (int iz = 1; iz < P; ++iz) acc = fmx(bq[iz], (T)u[(iz * P + iy) * P + ix], acc);
+            Z[iy][ix] = acc;
+          }
+        T X[P][Q];
+#pragma unroll
+        for (int iy = 0; iy < P; ++iy)
+#pragma unroll
+          for (int qx = 0; qx < Q; ++qx) {
+            T acc = (T)O.B[qx][0] * Z[iy][0];
+#pragma unroll
+            for (int ix = 1; ix < P; ++ix) acc = fmx((T)O.B[qx][ix], Z[iy][ix], acc);
+            X[iy][qx] = acc;
+          }
+#pragma unroll
+        for (int qy = 0; qy < Q; ++qy)
+#pragma unroll
+          for (int qx = 0; qx < Q; ++qx) {
+            T acc = (T)O.B[qy][0] * X[0][qx];
+#pragma unroll
+            for (int iy = 1; iy < P; ++iy) acc = fmx((T)O.B[qy][iy], X[iy][qx], acc);
+            mine[(qy * Q + qx) * V + v] = acc;
+          }
+      }
+      __syncthreads();
+      // flux components of this lane's variable, tested row by row
+#pragma unroll
+      for (int qy = 0; qy < Q; ++qy) {
+        T tx[P], ty[P], tz[P];
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx) {
+          const T* w = mine + (qy * Q + qx) * V;
+          const T rho = w[0], mx = w[1], my = w[2], mz = w[3], en = w[4];
+          const T wv = w[v];
+          const T ir = recip(rho);
+          const T ux = mx * ir, uy = my * ir, uz = mz * ir;
+          const T p = gm1 * (en - (T)0.5 * fmx(mz, uz, fmx(my, uy, mx * ux)));
+          const T t = fmx(p, e4, wv);
+          // F_a[v] = u_a (w_v + p [v=4]) + p [v=1+a]
+          const T fx = fmx(ux, t, p * e1), fy = fmx(uy, t, p * e2), fz = fmx(uz, t, p * e3);
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            if (qx == 0) {
+              tx[i] = (T)O.GW[i][0] * fx;
+              ty[i] = (T)O.BW[i][0] * fy;
+              tz[i] = (T)O.BW[i][0] * fz;
+            } else {
+              tx[i] = fmx((T)O.GW[i][qx], fx, tx[i]);
+              ty[i] = fmx((T)O.BW[i][qx], fy, ty[i]);
+              tz[i] = fmx((T)O.BW[i][qx], fz, tz[i]);
+            }
+          }
+        }
+#pragma unroll
+        for (int iy = 0; iy < P; ++iy) {
+          T ab[P], c[P];
+#pragma unroll
+          for (int ix = 0; ix < P; ++ix) {
+            ab[ix] = fmx((T)O.GW[iy][qy] * sy, ty[ix], ((T)O.BW[iy][qy] * sx) * tx[ix]);
+            c[ix] = ((T)O.BW[iy][qy] * sz) * tz[ix];
+          }
+#pragma unroll
+          for (int iz = 0; iz < P; ++iz)
+#pragma unroll
+            for (int ix = 0; ix < P; ++ix) {
+              const int n = (iz * P + iy) * P + ix;
+              k[n] = fmx(gw[iz], c[ix], fmx(bw[iz], ab[ix], k[n]));
+            }
+        }
+      }
+    }
+  }
+
+  // ---- faces, one face at a time
+  const ElemPos pos = elem_pos(M, valid ? e : 0);
+  const bool async_on = src != kSrcLive && M.nfs > 0;
+  const bool flux_mode = src == kSrcFlux;
+  const long long ring_level = M.nfs * V * (flux_mode ? Fq : Fn);  // values per ring level
+  const bool publish = src == kSrcRing && A.stage == 0;
+  // one pass per face, with the face index a compile-time constant so that
+  // every register index below is fixed
+  auto face_pass = [&](auto fc) {
+    constexpr int f = decltype(fc)::value;
+    constexpr int a = f >> 1, s = f & 1, ia = s ? P - 1 : 0;
+    __syncthreads();  // sX is rewritten
+    // neighbour trace of variable v at the face nodes (j0 + P j1)
+    double g[Fn];
+#pragma unroll
+    for (int j = 0; j < Fn; ++j) g[j] = 0.0;
+    long long fs = -1;
+    int kd = 0;
+    if (valid) {
+      fs = async_on ? face_side_at(M, pos, f) : -1;
+      if (fs >= 0 && (src == kSrcRing || flux_mode)) kd = delay_of(M, A, sub_at(M, pos.sc), f);
+      if (fs >= 0 && publish) {
+        double* dst = ring + A.slot_n * ring_level + fed_face_side(M, pos, f) * V * Fn + v * Fn;
+#pragma unroll
+        for (int j1 = 0; j1 < P; ++j1)
+#pragma unroll
+          for (int j0 = 0; j0 < P; ++j0) dst[j0 + P * j1] = u[node3<P>(a, ia, j0, j1)];
+      }
+      if (fs < 0 || ((src == kSrcRing || flux_mode) && kd == 0)) {
+        const unsigned nb = (unsigned)neighbour_of(M, e, pos, f);
+        const double* gp = u_in + (size_t)nb * (V * Pd) + v * Pd;
+#pragma unroll
+        for (int j1 = 0; j1 < P; ++j1)
+#pragma unroll
+          for (int j0 = 0; j0 < P; ++j0) g[j0 + P * j1] = gp[node3<P>(a, P - 1 - ia, j0, j1)];
+      } else if (flux_mode) {
+        // silent step: the face uses the stored flux, no trace needed
+      } else if (src == kSrcGhost) {
+        const double* gp = ghost + fs * V * Fn + v * Fn;
+#pragma unroll
+        for (int j = 0; j < Fn; ++j) g[j] = gp[j];
+      } else if (A.ghost == 1) {
+        // standard flux on the trace kd steps old (eq. delayed-flux)
+        const double* gp = ring + ring_slot(A, kd) * ring_level + fs * V * Fn + v * Fn;
+#pragma unroll
+        for (int j = 0; j < Fn; ++j) g[j] = gp[j];
+      } else {
+        // AT extrapolation to the stage time, tau = kd + c_m (eq. at-flux)
+        const double tau = kd + A.c_m;
+        for (int l = 0; l < A.levels; ++l) {
+          const double wl = at_weight(l, A.levels, tau);
+          const double* gp = ring + ring_slot(A, kd + l) * ring_level + fs * V * Fn + v * Fn;
+#pragma unroll
+          for (int j = 0; j < Fn; ++j) g[j] = fma(wl, gp[j], g[j]);
+        }
+      }
+    }
+    if (flux_mode && v == 0) {
+      sFsF[le] = fs;
+      sKdF[le] = kd;
+    }
+    // own and neighbour traces at the Gauss points (q0 + Q q1) of the face
+    {
+      T Xo[P][Q], Xn[P][Q];
+#pragma unroll
+      for (int j1 = 0; j1 < P; ++j1)
+#pragma unroll
+        for (int q0 = 0; q0 < Q; ++q0) {
+          T o = (T)O.B[q0][0] * (T)u[node3<P>(a, ia, 0, j1)];
+          T n = (T)O.B[q0][0] * (T)g[P * j1];
+#pragma unroll
+          for (int j0 = 1; j0 < P; ++j0) {
+            o = fmx((T)O.B[q0][j0], (T)u[node3<P>(a, ia, j0, j1)], o);
+            n = fmx((T)O.B[q0][j0], (T)g[j0 + P * j1], n);
+          }
+          Xo[j1][q0] = o;
+          Xn[j1][q0] = n;
+        }
+#pragma unroll
+      for (int q1 = 0; q1 < Q; ++q1)
+#pragma unroll
+        for (int q0 = 0; q0 < Q; ++q0) {
+          T o = (T)O.B[q1][0] * Xo[0][q0];
+          T n = (T)O.B[q1][0] * Xn[0][q0];
+#pragma unroll
+          for (int j1 = 1; j1 < P; ++j1) {
+            o = fmx((T)O.B[q1][j1], Xo[j1][q0], o);
+            n = fmx((T)O.B[q1][j1], Xn[j1][q0], n);
+          }
+          mine[(q1 * Q + q0) * V + v] = o;
+          mine[(Fq + q1 * Q + q0) * V + v] = n;
+        }
+    }
+    __syncthreads();
+    // numerical flux, one lane per (element, face point), in place of the
+    // own trace, scaled by -(n.e_a) 2/h_a
+    {
+      const T gamma = (T)M.gamma;
+      const T sc = (T)(2.0 / M.h[a]);
+#pragma unroll
+      for (int it = 0; it < (NE * Fq + 63) / 64; ++it) {
+        const int t = lane + 64 * it;
+        if (t < NE * Fq) {
+          const int el = t / Fq, m = t - el * Fq;
+          T* base = sX + el * PER;
+          const T* pl = base + (s ? m : Fq + m) * V;  // the +a face has the own side on the left
+          const T* pr = base + (s ? Fq + m : m) * V;
+          T wl[V], wr[V], G[V];
+#pragma unroll
+          for (int vv = 0; vv < V; ++vv) {
+            wl[vv] = pl[vv];
+            wr[vv] = pr[vv];
+          }
+          const long long ffs = flux_mode ? sFsF[el] : -1;
+          const int fkd = flux_mode ? sKdF[el] : 0;
+          if (ffs >= 0 && fkd > 0) {
+            // silent step of Alg. caa-std / caa-at: the stored flux, or its
+            // AT extrapolation to the stage time tau = k + c_m (FP64)
+            const double* fp = ring + ffs * V * Fq + m;
+            double acc[V];
+#pragma unroll
+            for (int vv = 0; vv < V; ++vv) acc[vv] = 0.0;
+            if (A.ghost == 4) {
+#pragma unroll
+              for (int vv = 0; vv < V; ++vv) acc[vv] = fp[ring_slot(A, fkd) * ring_level + vv * Fq];
+            } else {
+              const double tau = fkd + A.c_m;
+              for (int l = 0; l < A.levels; ++l) {
+                const double w = at_weight(l, A.levels, tau);
+                const double* lp = fp + ring_slot(A, fkd + l) * ring_level;
+#pragma unroll
+                for (int vv = 0; vv < V; ++vv) acc[vv] = fma(w, lp[vv * Fq], acc[vv]);
+              }
+            }
+#pragma unroll
+            for (int vv = 0; vv < V; ++vv) G[vv] = (T)acc[vv];
+          } else {
+            num_flux<T, 3>(wl, wr, a, gamma, M.flux, G);
+            // communicating step of a flux-history mode: keep the stage-0 flux
+            if (ffs >= 0 && A.stage == 0) {
+              double* fp = ring + A.slot_n * ring_level + ffs * V * Fq + m;
+#pragma unroll
+              for (int vv = 0; vv < V; ++vv) fp[vv * Fq] = (double)G[vv];
+            }
+          }
+          const T sg = s ? -sc : sc;
+#pragma unroll
+          for (int vv = 0; vv < V; ++vv) base[m * V + vv] = sg * G[vv];
+        }
+      }
+    }
+    __syncthreads();
+    // lift with BW along both tangential axes, then k(i_a, j0, j1) +=
+    // MC_s[i_a] * lifted(j0, j1)
+    {
+      T L0[Q][P];
+#pragma unroll
+      for (int q1 = 0; q1 < Q; ++q1) {
+        T G[Q];
+#pragma unroll
+        for (int q0 = 0; q0 < Q; ++q0) G[q0] = mine[(q1 * Q + q0) * V + v];
+#pragma unroll
+        for (int j0 = 0; j0 < P; ++j0) {
+          T acc = (T)O.BW[j0][0] * G[0];
+#pragma unroll
+          for (int q0 = 1; q0 < Q; ++q0) acc = fmx((T)O.BW[j0][q0], G[q0], acc);
+          L0[q1][j0] = acc;
+        }
+      }
+#pragma unroll
+      for (int j1 = 0; j1 < P; ++j1)
+#pragma unroll
+        for (int j0 = 0; j0 < P; ++j0) {
+          T lf = (T)O.BW[j1][0] * L0[0][j0];
+#pragma unroll
+          for (int q1 = 1; q1 < Q; ++q1) lf = fmx((T)O.BW[j1][q1], L0[q1][j0], lf);
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            const int n = node3<P>(a, i, j0, j1);
+            k[n] = fmx((T)O.MC[s][i], lf, k[n]);
+          }
+        }
+    }
+  };
+  face_pass(std::integral_constant<int, 0>{});
+  face_pass(std::integral_constant<int, 1>{});
+  face_pass(std::integral_constant<int, 2>{});
+  face_pass(std::integral_constant<int, 3>{});
+  face_pass(std::integral_constant<int, 4>{});
+  face_pass(std::integral_constant<int, 5>{});
+
+  // ---- SSP-RK3 combine in FP64
+  if (valid) {
+    double* o = out + col;
+    if (S.a == 0.0) {
+#pragma unroll
+      for (int i = 0; i < Pd; ++i) o[i] = S.b * (u[i] + S.dt * (double)k[i]);
+    } else {
+      const double* un = u_n + col;
+#pragma unroll
+      for (int i = 0; i < Pd; ++i) o[i] = S.a * un[i] + S.b * (u[i] + S.dt * (double)k[i]);
+    }
+  }
+}
+
+template <typename T, int P>
+hipError_t launch3d(const Mesh& M, const Async& A, const Stage& S, const double* u_in, const double* u_n,
+                    double* out, int src, double* ring, const double* ghost, hipStream_t st) {
+  const long long nblk = (M.E + kNE3 - 1) / kNE3;
+  hipLaunchKernelGGL((rhs_stage3d_kernel<T, P>), dim3((unsigned)nblk), dim3(64), 0, st, M, A, S, u_in, u_n, out, src,
+                     ring, ghost);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_rhs_stage_3d(int degree, int precision, const Mesh& M, const Async& A, const Stage& S,
+                               const double* u_in, const double* u_n, double* out, int src, double* ring,
+                               const double* ghost, hipStream_t st) {
+  if (M.dim != 3) return hipErrorInvalidValue;
+  if (degree == 1) {
+    if (precision == 1) return launch3d<float, 2>(M, A, S, u_in, u_n, out, src, ring, ghost, st);
+    return launch3d<double, 2>(M, A, S, u_in, u_n, out, src, ring, ghost, st);
+  }
+  if (degree == 2) {
+    if (precision == 1) return launch3d<float, 3>(M, A, S, u_in, u_n, out, src, ring, ghost, st);
+    return launch3d<double, 3>(M, A, S, u_in, u_n, out, src, ring, ghost, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace adg

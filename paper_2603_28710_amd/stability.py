@@ -1,0 +1,94 @@
+"""Largest stable CFL number of the asynchronous schemes, by bisection.
+
+The paper observes that delays shrink the stable time step and that AT
+fluxes relax that limit again (Sec. 5.1, the stability remark after the
+vortex figures). This tool measures it on the GPU solver: a run at CFL sigma
+is stable if `adg_step`, with the state checked every `check` steps, reports
+no non-finite or non-physical state up to t_end. The returned sigma is the
+largest stable value found by bisection between lo and hi.
+
+    python -m paper_2603_28710_amd.stability [--t-end 4] [--cells 64] [--degree 2]
+
+prints one JSON line per (mode, L) with the bracket [stable, unstable].
+"""
+import argparse
+import json
+import math
+
+MODES = {
+    "stale_caa": dict(ghost=1, delay_kind=2),
+    "at_caa": dict(ghost=2, delay_kind=2),
+    "flux_stale_caa": dict(ghost=4, delay_kind=2),
+    "flux_at_caa": dict(ghost=5, delay_kind=2),
+    "at_uniform": dict(ghost=2, delay_kind=1),
+}
+
+
+def runs_stably(make, sigma, t_end):
+    """True if the solver built by make() reaches t_end at CFL sigma"""
+    from paper_2603_28710_amd import binding as B
+
+    s = make()
+    dt0 = s.stable_dt(sigma)
+    n = int(math.ceil(t_end / dt0))
+    st = s.step_status(n, t_end / n)
+    if st in (B.ADG_ERR_NONFINITE, B.ADG_ERR_NONPHYSICAL):
+        return False
+    if st != B.ADG_OK:
+        raise RuntimeError(B.adg_last_error())
+    return True
+
+
+def max_stable_cfl(make, t_end, lo=0.005, hi=1.0, iters=8):
+    """bisection on sigma; assumes stability at lo (checked) and returns the
+    bracket (largest stable, smallest unstable) found"""
+    if not runs_stably(make, lo, t_end):
+        return 0.0, lo
+    if runs_stably(make, hi, t_end):
+        return hi, float("inf")
+    for _ in range(iters):
+        mid = math.sqrt(lo * hi)
+        if runs_stably(make, mid, t_end):
+            lo = mid
+        else:
+            hi = mid
+    return lo, hi
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--t-end", type=float, default=4.0)
+    ap.add_argument("--cells", type=int, default=64)
+    ap.add_argument("--parts", type=int, default=16)
+    ap.add_argument("--degree", type=int, default=2)
+    ap.add_argument("--levels", type=int, default=3)
+    ap.add_argument("--L", type=int, nargs="+", default=[1, 2, 3, 4])
+    ap.add_argument("--modes", nargs="+", default=list(MODES))
+    ap.add_argument("--check", type=int, default=50)
+    a = ap.parse_args()
+
+    from paper_2603_28710_amd.solver import Solver
+
+    n = a.cells
+
+    def maker(mode, L):
+        def make():
+            s = Solver(dim=2, degree=a.degree, cells=(n, n, 1), parts=(a.parts, a.parts, 1), lo=(0, 0, 0),
+                       hi=(10, 10, 1), check_every=a.check, levels=a.levels, L=L, seed=0, **MODES[mode])
+            s.init_problem(0)
+            return s
+        return make
+
+    sync_lo, sync_hi = max_stable_cfl(maker("at_caa", 0), a.t_end)
+    print(json.dumps({"mode": "sync", "L": 0, "stable": sync_lo, "unstable": sync_hi}), flush=True)
+    for mode in a.modes:
+        for L in a.L:
+            if L == 0 and mode in ("stale_caa", "flux_stale_caa"):
+                continue
+            lo, hi = max_stable_cfl(maker(mode, L), a.t_end)
+            print(json.dumps({"mode": mode, "L": L, "stable": lo, "unstable": hi, "cells": n,
+                              "degree": a.degree, "t_end": a.t_end}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
