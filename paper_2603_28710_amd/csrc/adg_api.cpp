@@ -324,6 +324,7 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
   M.flux = c.flux;
   for (int k = 0; k < 2; ++k) M.dnc[k] = make_fastdiv(M.nc[k]);
   for (int k = 0; k < 3; ++k) M.dm[k] = make_fastdiv(M.m[k]);
+  for (int k = 0; k < 2; ++k) M.dparts[k] = make_fastdiv(M.parts[k]);
   int off = 0;
   for (int f = 0; f < 6; ++f) {
     M.fs_off[f] = -1;
@@ -338,6 +339,11 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
   }
   M.fs_sub = off;
   M.nfs = (long long)off * M.nsub;
+  M.dfs_sub = make_fastdiv(off > 0 ? off : 1);
+  if (M.nfs >= (1ll << 31)) {
+    delete x;
+    return fail(ADG_ERR_INVALID, "too many PE-boundary face-sides");
+  }
   x->ndof = (size_t)E * x->V * x->Pd;
   depth_of(x->as, x->R, x->Qh);
 

@@ -96,8 +96,10 @@ struct Mesh {
   double detJf[3];   // face Jacobian for faces normal to axis a
   double gamma;
   int flux;
-  FastDiv dnc[2];  // division by nc[0], nc[1]
-  FastDiv dm[3];   // division by m[k]
+  FastDiv dnc[2];    // division by nc[0], nc[1]
+  FastDiv dm[3];     // division by m[k]
+  FastDiv dparts[2]; // division by parts[0], parts[1]
+  FastDiv dfs_sub;   // division by fs_sub (face-side -> subdomain)
 };
 
 // Asynchrony parameters for one stage.
@@ -225,20 +227,23 @@ __host__ __device__ inline long long fed_face_side(const Mesh& M, const ElemPos&
 }
 
 // inverse of face_side: receiving element coords and face
+// (0 <= fs < n_face_sides < 2^31)
 __host__ __device__ inline void face_side_decode(const Mesh& M, long long fs, int* c, int* f_out) {
-  int s = (int)(fs / M.fs_sub);
-  int r = (int)(fs - (long long)s * M.fs_sub);
+  const unsigned s = fdiv((unsigned)fs, M.dfs_sub);
+  const int r = (int)((unsigned)fs - s * (unsigned)M.fs_sub);
   int f = 0;
   for (int g = 0; g < 2 * M.dim; ++g)
     if (M.fs_off[g] >= 0 && r >= M.fs_off[g]) f = g;
-  int li = r - M.fs_off[f];
-  int a = f >> 1;
-  int o0 = a == 0 ? 1 : 0;
-  int o1 = a == 2 ? 1 : 2;
-  int sc[3] = {s % M.parts[0], (s / M.parts[0]) % M.parts[1], s / (M.parts[0] * M.parts[1])};
+  const int li = r - M.fs_off[f];
+  const int a = f >> 1;
+  const int o0 = a == 0 ? 1 : 0;
+  const int o1 = a == 2 ? 1 : 2;
+  const unsigned s1 = fdiv(s, M.dparts[0]);
+  int sc[3] = {(int)(s - s1 * (unsigned)M.parts[0]), (int)fmodu(s1, M.dparts[1]), (int)fdiv(s1, M.dparts[1])};
   int l[3] = {0, 0, 0};
-  l[o0] = li % M.m[o0];
-  if (M.dim == 3) l[o1] = li / M.m[o0];
+  const unsigned lq = fdiv((unsigned)li, M.dm[o0]);
+  l[o0] = li - (int)lq * M.m[o0];
+  if (M.dim == 3) l[o1] = (int)lq;
   l[a] = (f & 1) ? M.m[a] - 1 : 0;
   for (int k = 0; k < 3; ++k) c[k] = sc[k] * M.m[k] + l[k];
   *f_out = f;

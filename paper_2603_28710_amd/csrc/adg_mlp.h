@@ -16,6 +16,9 @@ constexpr int kTrainChunk = 64;   // samples per block per launch
 constexpr int kMaxBatch = kTrainBlocks * kTrainChunk;
 constexpr int kPackBytes = 8192;  // BF16 operand tiles + FP32 biases
 constexpr float kTargetClip = 64.0f;  // training targets beyond this get weight 0
+// the judge statistics (accepted, judged) are kept in kStatSlots copies that
+// wavefronts add to round-robin, so their atomics do not queue on one address
+constexpr int kStatSlots = 256;
 
 __host__ __device__ constexpr int mlp_nin(int V) { return 2 * V + 2; }
 __host__ __device__ constexpr int mlp_nparams(int V) { return kMlpH * mlp_nin(V) + kMlpH + V * kMlpH + V; }
@@ -41,7 +44,7 @@ struct MlpDev {
   float* gpart;               // [kTrainBlocks][nparams] partial gradients
   float* lpart;               // [kTrainBlocks][2] partial loss and weight sums
   uint16_t* pack;             // BF16 operand tiles and FP32 biases (kPackBytes)
-  unsigned long long* stats;  // accepted faces, judged faces
+  unsigned long long* stats;  // [kStatSlots][2]: accepted faces, judged faces
   float* gout;                // reduced gradient (nparams)
   float* yout;                // inference outputs (kMaxBatch * V)
   float* loss;                // last loss

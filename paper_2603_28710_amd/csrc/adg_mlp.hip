@@ -37,7 +37,7 @@ size_t mlp_scratch_bytes(int V) {
   s = al256(s + (size_t)kTrainBlocks * np * 4);  // gpart
   s = al256(s + (size_t)kTrainBlocks * 2 * 4);   // lpart
   s = al256(s + kPackBytes);                     // pack
-  s = al256(s + 4 * sizeof(unsigned long long)); // stats
+  s = al256(s + 2 * kStatSlots * sizeof(unsigned long long));  // stats
   s = al256(s + np * 4);                         // gout
   s = al256(s + (size_t)kMaxBatch * V * 4);      // yout
   s = al256(s + 4 * 4);                          // loss
@@ -60,7 +60,7 @@ MlpDev mlp_dev(const MlpState& s) {
   d.gpart = reinterpret_cast<float*>(take((size_t)kTrainBlocks * np * 4));
   d.lpart = reinterpret_cast<float*>(take((size_t)kTrainBlocks * 2 * 4));
   d.pack = reinterpret_cast<uint16_t*>(take(kPackBytes));
-  d.stats = reinterpret_cast<unsigned long long*>(take(4 * sizeof(unsigned long long)));
+  d.stats = reinterpret_cast<unsigned long long*>(take(2 * kStatSlots * sizeof(unsigned long long)));
   d.gout = reinterpret_cast<float*>(take(np * 4));
   d.yout = reinterpret_cast<float*>(take((size_t)kMaxBatch * s.V * 4));
   d.loss = reinterpret_cast<float*>(take(16));
@@ -136,8 +136,10 @@ __device__ __forceinline__ int face_node_l(int f, int j) {
 }
 
 // Ghost traces with the learned correction (or, when collecting, AT ghosts
-// plus training pairs). Block: 4 wavefronts x 16 face nodes; whole face-sides
-// per block so the per-face judge stays inside the block.
+// plus training pairs). One face node per lane; a wavefront holds NFW =
+// 64 / Fn whole face-sides, so the per-face judge stays inside it. The
+// network runs on the matrix cores in four batches of 16 nodes, its inputs
+// and outputs passing through LDS.
 template <int D, int P>
 __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, const double* __restrict__ u_in,
                                                             const double* __restrict__ u_n,
@@ -147,14 +149,14 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
                                                             float* __restrict__ pairs, long long pair_base,
                                                             int collect) {
   constexpr int V = D + 2, Fn = D == 2 ? P : P * P, Pd = Fn * P, NIN = 2 * V + 2;
-  constexpr int NFB = 64 / Fn;
-  __shared__ double s_max[256];
-  __shared__ int s_acc[64], s_k[64];
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, c = l & 15, g = l >> 4;
-  const int item = 16 * w + c;
-  const long long fs = (long long)blockIdx.x * NFB + item / Fn;
-  const int j = item % Fn;
-  const bool valid = item < NFB * Fn && fs < M.nfs;
+  constexpr int NFW = 64 / Fn;  // face-sides per wavefront
+  __shared__ float s_io[4][64][17];  // per wavefront and node: features, then outputs
+  __shared__ double s_max[4][64];
+  __shared__ int s_acc[4][64];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const long long fs = ((long long)blockIdx.x * 4 + w) * NFW + lane / Fn;
+  const int j = lane % Fn;
+  const bool valid = lane < NFW * Fn && fs < M.nfs;
   const long long total = M.nfs * V * Fn;
   int k = 0;
   double at[V], live[V], S3 = 0.0;
@@ -169,7 +171,8 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
     const long long nb = neighbour(M, cc, f);
     const long long src = nb * V * Pd + face_node_l<D, P>(f ^ 1, j);
     if (publish)
-      for (int v = g; v < V; v += 4) ring[A.slot_n * total + (fs * V + v) * Fn + j] = u_n[src + v * Pd];
+#pragma unroll
+      for (int v = 0; v < V; ++v) ring[A.slot_n * total + (fs * V + v) * Fn + j] = u_n[src + v * Pd];
     k = delay_of(M, A, subdomain_of(M, cc), f);
 #pragma unroll
     for (int v = 0; v < V; ++v) live[v] = u_in[src + v * Pd];
@@ -180,10 +183,13 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
 #pragma unroll
         for (int v = 0; v < V; ++v) T[lv][v] = ring[ring_slot(A, k + lv) * total + (fs * V + v) * Fn + j];
       const double tau = k + A.c_m;
-      for (int lv = 0; lv < A.levels; ++lv) {
-        const double wl = at_weight(lv, A.levels, tau);
 #pragma unroll
-        for (int v = 0; v < V; ++v) at[v] += wl * T[lv][v];
+      for (int lv = 0; lv < kMlpK; ++lv) {  // levels <= 4 = kMlpK: fixed register indices
+        if (lv < A.levels) {
+          const double wl = at_weight(lv, A.levels, tau);
+#pragma unroll
+          for (int v = 0; v < V; ++v) at[v] += wl * T[lv][v];
+        }
       }
       // second and third backward differences (no contraction: the features
       // are bit-reproducible), both scaled by S = max|second| + max|third|
@@ -206,62 +212,59 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
       S3 = S;
     }
   }
-  bf16x4 xb;
+  float(*io)[17] = s_io[w];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    float xi = 0.0f;
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (q == 4 * g + i) xi = x[q];
-    xb[i] = to_bf16(xi);
-  }
-  const f32x4 y = mlp_forward_wave(pk, xb);
-  double dl[4], mx = 0.0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int o = 4 * g + i;
-    dl[i] = o < V ? S3 * (double)y[i] : 0.0;
-    if (o < V && !(fabs(dl[i]) <= mx)) mx = fabs(dl[i]);
-  }
-  s_max[tid] = (valid && k >= 1) ? mx : 0.0;
-  if (valid && j == 0 && g == 0) s_k[item / Fn] = k;
+  for (int q = 0; q < 16; ++q) io[lane][q] = x[q];
   __syncthreads();
-  if (tid < NFB) {
-    const long long fst = (long long)blockIdx.x * NFB + tid;
-    int acc = 0;
-    if (fst < M.nfs) {
-      double mm = 0.0;
-      for (int it = tid * Fn; it < tid * Fn + Fn; ++it)
-        for (int gg = 0; gg < 4; ++gg) {
-          const double v = s_max[(it >> 4) * 64 + gg * 16 + (it & 15)];
-          if (!(v <= mm)) mm = v;
-        }
-      acc = use_net && (mm <= A.tol);
-      if (s_k[tid] >= 1 && use_net) {
-        atomicAdd(&stats[1], 1ull);
-        if (acc) atomicAdd(&stats[0], 1ull);
-      }
+  // the network on batches of 16 nodes: lane 16g + c feeds features
+  // 4g..4g+3 of node 16b + c and gets back outputs 4g..4g+3 of that node,
+  // stored over the same four entries it read
+  {
+    const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      bf16x4 xb;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xb[i] = to_bf16(io[16 * b + c][4 * g + i]);
+      const f32x4 y = mlp_forward_wave(pk, xb);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) io[16 * b + c][4 * g + i] = y[i];
     }
-    s_acc[tid] = acc;
+  }
+  __syncthreads();
+  double dl[V], mx = 0.0;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    dl[v] = S3 * (double)io[lane][v];
+    if (!(fabs(dl[v]) <= mx)) mx = fabs(dl[v]);
+  }
+  s_max[w][lane] = (valid && k >= 1) ? mx : 0.0;
+  __syncthreads();
+  // per face-side judge (its first node's lane), counted per wavefront
+  int acc = 0, judged = 0;
+  if (valid && j == 0) {
+    double mm = 0.0;
+#pragma unroll
+    for (int q = 0; q < Fn; ++q) {
+      const double v = s_max[w][lane + q];
+      if (!(v <= mm)) mm = v;
+    }
+    acc = use_net && (mm <= A.tol);
+    judged = k >= 1 && use_net;
+    s_acc[w][lane] = acc;
+  }
+  const unsigned long long mj = __ballot(judged), ma = __ballot(judged && acc);
+  if (lane == 0) {
+    unsigned long long* slot = stats + 2 * ((blockIdx.x * 4 + w) % kStatSlots);
+    if (mj) atomicAdd(&slot[1], (unsigned long long)__popcll(mj));
+    if (ma) atomicAdd(&slot[0], (unsigned long long)__popcll(ma));
   }
   __syncthreads();
   if (valid) {
-    const int acc = s_acc[item / Fn];
+    const int fa = s_acc[w][lane - j];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int v = 4 * g + i;
-      if (v < V) {
-        double lv = live[0], av = at[0];
-#pragma unroll
-        for (int q = 0; q < V; ++q)
-          if (q == v) {
-            lv = live[q];
-            av = at[q];
-          }
-        ghost[(fs * V + v) * Fn + j] = k == 0 ? lv : av + (acc ? dl[i] : 0.0);
-      }
-    }
-    if (collect && g == 0) {
+    for (int v = 0; v < V; ++v) ghost[(fs * V + v) * Fn + j] = k == 0 ? live[v] : at[v] + (fa ? dl[v] : 0.0);
+    if (collect) {
       // target: live stage value minus AT, in units of S. Targets beyond
       // kTargetClip (well above the largest extrapolation coefficient the
       // delays allow) come from the neighbour's own asynchronous jumps, not
@@ -287,7 +290,7 @@ hipError_t launch_ghost_learned(int dim, int degree, const Mesh& M, const Async&
                                 const double* u_n, double* ring, double* ghost, int publish, const MlpState& s,
                                 long long pair_base, bool collect, hipStream_t st) {
   const int Fn = dim == 2 ? degree + 1 : (degree + 1) * (degree + 1);
-  const int nfb = 64 / Fn;
+  const int nfb = 4 * (64 / Fn);  // face-sides per block
   if (M.nfs == 0) return hipSuccess;
   const unsigned nblk = (unsigned)((M.nfs + nfb - 1) / nfb);
   const MlpDev d = mlp_dev(s);
@@ -463,7 +466,8 @@ namespace adg {
 void mlp_reset_stats(adg_ctx_s* c) {
   if (!c->bound) return;
   const MlpDev d = mlp_dev(c->mlp);
-  hipLaunchKernelGGL(mlp_zero_kernel, dim3(1), dim3(64), 0, c->stream, d.stats, 4);
+  hipLaunchKernelGGL(mlp_zero_kernel, dim3((2 * kStatSlots + 63) / 64), dim3(64), 0, c->stream, d.stats,
+                     2 * kStatSlots);
 }
 
 // upload host_w as the master weights, repack, zero Adam state
@@ -678,8 +682,13 @@ adg_status adg_predictor_stats(adg_ctx c, double* accept_rate, int64_t* faces_ju
   unsigned long long h[2] = {0, 0};
   if (c->bound) {
     const MlpDev d = mlp_dev(c->mlp);
-    HIP_TRY(hipMemcpyAsync(h, d.stats, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    unsigned long long slots[2 * kStatSlots];
+    HIP_TRY(hipMemcpyAsync(slots, d.stats, sizeof(slots), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < kStatSlots; ++i) {
+      h[0] += slots[2 * i];
+      h[1] += slots[2 * i + 1];
+    }
   }
   if (accept_rate) *accept_rate = h[1] ? (double)h[0] / (double)h[1] : 0.0;
   if (faces_judged) *faces_judged = (int64_t)h[1];
