@@ -42,9 +42,21 @@ WORKLOADS = {
     "vortex1024_p4_at3_uniformL3_fp64": dict(
         cfg=dict(dim=2, degree=4, cells=(1024, 1024, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
         asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=0),
+    # uniform delays up to 4 need CFL 0.05 to stay stable over long runs
     "wave128_p2_at3_uniformL4": dict(
         cfg=dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1)),
-        asy=dict(ghost=2, delay_kind=1, L=4, levels=3, seed=0), problem=1, precision=0),
+        asy=dict(ghost=2, delay_kind=1, L=4, levels=3, seed=0), problem=1, precision=0, cfl=0.05),
+    # the learned ghost predictor (untrained, Glorot-initialised network from
+    # a fixed seed: inference and the per-face judge cost the same whatever
+    # the weights; faces the judge rejects fall back to AT)
+    "wave128_p2_learned_uniformL4": dict(
+        cfg=dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1)),
+        asy=dict(ghost=3, delay_kind=1, L=4, levels=3, seed=0, learned_tol=1e-6), problem=1, precision=0,
+        cfl=0.05, net_seed=1),
+    # the paper's own communication-avoiding algorithm with AT fluxes
+    "vortex256_p3_fluxat3_caaL3": dict(
+        cfg=dict(dim=2, degree=3, cells=(256, 256, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
+        asy=dict(ghost=5, delay_kind=2, L=3, levels=3, seed=0), problem=0, precision=0),
 }
 DEFAULT = "vortex256_p3_at3_uniformL3"
 
@@ -53,11 +65,14 @@ def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, ghost, levels):
     """Minimum HBM bytes of one fused stage launch, averaged over the 3 stages
     of a step: the stage input read once, u^n read on stages 2 and 3, the
     output written (8 B each per DoF: 64/3 B per DoF); at PE-boundary faces
-    the ring levels read (one for stale traces, `levels` for AT) and, at
-    stage 0, one level written (nfs_nodes_vars values per level)."""
+    the ring levels read (one for stale traces, `levels` for AT, the
+    predictor's ghost buffer for learned traces) and, at stage 0, one level
+    written (nfs_nodes_vars values per level). The flux-history modes are
+    counted by their state traffic only (their flux ring traffic depends on
+    the schedule), so their figure is a lower bound."""
     ring = 0.0
-    if ghost in (1, 2) and nfs_nodes_vars > 0:
-        ring = 8.0 * nfs_nodes_vars * ((1 if ghost == 1 else levels) + 1.0 / 3.0)
+    if ghost in (1, 2, 3) and nfs_nodes_vars > 0:
+        ring = 8.0 * nfs_nodes_vars * ((levels if ghost == 2 else 1) + 1.0 / 3.0)
     return ndof * 64.0 / 3.0 + ring
 
 
@@ -112,7 +127,7 @@ def cpu_baseline(w, target_s=15.0):
     o = O.Oracle(dim=c["dim"], p=c["degree"], cells=c["cells"], parts=c["parts"], lo=c["lo"], hi=c["hi"],
                  ghost=a["ghost"], delay_kind=a["delay_kind"], L=a["L"], levels=a["levels"], seed=a["seed"])
     o.init_problem(w["problem"])
-    dt = o.stable_dt(0.1)
+    dt = o.stable_dt(w.get("cfl", 0.1))
     t0 = time.perf_counter()
     o.step(1, dt)
     t1 = time.perf_counter()
@@ -148,7 +163,10 @@ def main():
     c, a = w["cfg"], w["asy"]
     s = Solver(device="cuda:0", precision=w["precision"], **c, **a)
     s.init_problem(w["problem"])
-    dt = s.stable_dt(0.1)
+    if a["ghost"] == B.ADG_GHOST_LEARNED:
+        s.predictor_init(w["net_seed"])
+    cfl = w.get("cfl", 0.1)
+    dt = s.stable_dt(cfl)
     s.step(args.warmup, dt)
     torch.cuda.synchronize()
 
@@ -193,9 +211,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "dim": c["dim"], "degree": c["degree"],
                    "cells": list(c["cells"][: c["dim"]]), "parts": list(c["parts"][: c["dim"]]),
-                   "ghost": ["sync", "stale", "at", "learned"][a["ghost"]], "levels": a["levels"],
+                   "ghost": ["sync", "stale", "at", "learned", "flux_stale", "flux_at"][a["ghost"]],
+                   "levels": a["levels"],
                    "delay": ["fixed", "uniform", "caa"][a["delay_kind"]], "L": a["L"], "seed": a["seed"],
-                   "dofs": s.ndof, "elements": s.E, "dt": dt, "cfl": 0.1},
+                   "dofs": s.ndof, "elements": s.E, "dt": dt, "cfl": cfl},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "rhs_stage", "avg_launch_us": avg_s * 1e6, "launches": rhs_n,

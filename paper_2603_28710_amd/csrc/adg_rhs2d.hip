@@ -119,13 +119,16 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
   }
   __syncthreads();
 
-  // the live neighbour traces of the two x faces, loaded now so that their
-  // latency hides behind the volume work (the y faces' would cost the
-  // registers of a third wavefront per SIMD)
+  // the live neighbour traces, loaded now so that their latency hides behind
+  // the volume work. In FP64 all four faces: the neighbour rows one element
+  // row away are then read while they are still in L2 (the FP64 kernels run
+  // at the same wavefronts per SIMD either way); in FP32 the x faces only,
+  // where the extra registers would cost occupancy
   const ElemPos pos = elem_pos(M, valid ? e : 0);
-  double nbv[2][P];
+  constexpr int NB = sizeof(T) == 8 ? 4 : 2;
+  double nbv[NB][P];
 #pragma unroll
-  for (int f = 0; f < 2; ++f) {
+  for (int f = 0; f < NB; ++f) {
     const unsigned nb = (unsigned)neighbour_of(M, valid ? e : 0, pos, f);
     const double* gp = u_in + (size_t)nb * (V * Pd) + v * Pd;
 #pragma unroll
@@ -142,8 +145,9 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
     const T e1 = v == 1 ? (T)1 : (T)0, e2 = v == 2 ? (T)1 : (T)0, e3 = v == 3 ? (T)1 : (T)0;
     const T* row = sX + le * PER;
     // one Gauss row per iteration keeps the live state small; the
-    // row-dependent operator entries come from the device copy of the table
-    const ops::Ops<P>& OD = ops::kOps<P>;
+    // row-dependent operator entries come from a device table laid out by
+    // row (one wide scalar load per row)
+    const ops::RowOps<P>& OR = ops::kRowOps<P>;
 #pragma unroll 1
     for (int qy = 0; qy < Q; ++qy) {
       T tx[P], ty[P];
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
       }
 #pragma unroll
       for (int iy = 0; iy < P; ++iy) {
-        const T bw = (T)OD.BW[iy][qy], gw = (T)OD.GW[iy][qy];
+        const T bw = (T)OR.r[qy][1][iy], gw = (T)OR.r[qy][2][iy];
 #pragma unroll
         for (int ix = 0; ix < P; ++ix) k[iy * P + ix] = fmx(gw, ty[ix], fmx(bw, tx[ix], k[iy * P + ix]));
       }
@@ -212,9 +216,9 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
           for (int j = 0; j < P; ++j) dst[j] = u[fnode<P>(f, j)];
         }
         if (fs < 0 || ((src == kSrcRing || flux_mode) && kd == 0)) {
-          if (a == 0) {
+          if (NB == 4 || a == 0) {
 #pragma unroll
-            for (int j = 0; j < P; ++j) g[j] = nbv[s][j];
+            for (int j = 0; j < P; ++j) g[j] = nbv[NB == 4 ? f : s][j];
           } else {
             const unsigned nb = (unsigned)neighbour_of(M, e, pos, f);
             const double* gp = u_in + (size_t)nb * (V * Pd) + v * Pd;

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
                                                          const double* __restrict__ ghost) {
   constexpr int Q = P + 1, V = 5, NE = kNE3, Pd = P * P * P, Fn = P * P, Fq = Q * Q;
   constexpr ops::Ops<P> O = ops::make_ops<P>();
-  const ops::Ops<P>& OD = ops::kOps<P>;  // entries indexed at run time
+  const ops::RowOps<P>& OR = ops::kRowOps<P>;  // entries indexed at run time, by Gauss plane
   // per element: the state at the points of one Gauss plane [Fq][V] during
   // the volume, the own and neighbour traces of one face [2][Fq][V] during
   // the faces; one spare element slot for the idle lanes; the stride is
@@ -91,9 +91,9 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
       T bq[P], bw[P], gw[P];
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        bq[i] = (T)OD.B[qz][i];
-        bw[i] = (T)OD.BW[i][qz];
-        gw[i] = (T)OD.GW[i][qz];
+        bq[i] = (T)OR.r[qz][0][i];
+        bw[i] = (T)OR.r[qz][1][i];
+        gw[i] = (T)OR.r[qz][2][i];
       }
       // this lane's variable on the plane: z combination, then x, then y
       {

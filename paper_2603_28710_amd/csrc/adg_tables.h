@@ -180,5 +180,27 @@ constexpr Ops<P> make_ops() {
 template <int P>
 inline constexpr Ops<P> kOps = make_ops<P>();
 
+// the entries a sweep over Gauss index q reads at run time, contiguous per q
+// (one wide scalar load): B[q][j], BW[j][q], GW[j][q] for j < P
+template <int P>
+struct alignas(64) RowOps {
+  double r[P + 1][3][P];
+};
+
+template <int P>
+constexpr RowOps<P> make_rowops() {
+  RowOps<P> t{};
+  for (int q = 0; q <= P; ++q)
+    for (int j = 0; j < P; ++j) {
+      t.r[q][0][j] = kOps<P>.B[q][j];
+      t.r[q][1][j] = kOps<P>.BW[j][q];
+      t.r[q][2][j] = kOps<P>.GW[j][q];
+    }
+  return t;
+}
+
+template <int P>
+inline constexpr RowOps<P> kRowOps = make_rowops<P>();
+
 }  // namespace ops
 }  // namespace adg

@@ -45,7 +45,9 @@ def run(workload, steps):
     w = bench.WORKLOADS[workload]
     s = Solver(device="cuda:0", precision=w["precision"], **w["cfg"], **w["asy"])
     s.init_problem(w["problem"])
-    dt = s.stable_dt(0.1)
+    if w["asy"]["ghost"] == 3:
+        s.predictor_init(w["net_seed"])
+    dt = s.stable_dt(w.get("cfl", 0.1))
     s.step(steps, dt)
     torch.cuda.synchronize()
     src = torch.ones(COPY_DOUBLES, dtype=torch.float64, device="cuda:0")
