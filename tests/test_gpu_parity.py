@@ -155,6 +155,34 @@ def test_async_at_uniform_3d(oracle_mod, S, seed):
     assert r <= TOL
 
 
+@pytest.mark.parametrize("p,cells,ghost,kind,L,levels,precision", [
+    (3, (8, 8, 8), 2, 0, 2, 3, 0),   # the 64^3 density-wave settings: AT3, fixed L=2
+    (3, (8, 8, 8), 2, 1, 2, 3, 0),
+    (3, (8, 8, 8), 1, 1, 2, 1, 0),
+    (3, (8, 8, 8), 5, 2, 3, 3, 0),
+    (3, (8, 8, 8), 2, 1, 2, 3, 1),   # FP32 contractions: within 1e-6
+    (4, (4, 4, 4), 2, 1, 2, 3, 0),
+    (4, (4, 4, 4), 4, 2, 3, 1, 0),
+])
+def test_async_3d_high_degree(oracle_mod, S, p, cells, ghost, kind, L, levels, precision):
+    O = oracle_mod
+    say(f"case: density wave 3D p={p} {cells} parts 2^3 ghost={ghost} kind={kind} L={L} levels={levels} "
+        f"precision={precision}, 8 steps")
+    cfg = dict(dim=3, cells=cells, parts=(2, 2, 2), hi=(1, 1, 1), ghost=ghost, delay_kind=kind, L=L,
+               levels=levels, seed=3)
+    o = O.Oracle(p=p, **cfg)
+    o.init_problem(O.DENSITY_WAVE)
+    o.set_state(o.state() + inputs.perturbation(o.ndof, 5, 1e-3))
+    s = S(degree=p, precision=precision, **cfg)
+    s.upload(o.state())
+    dt = o.stable_dt(0.1)
+    o.step(8, dt)
+    s.step(8, dt)
+    r = rel_l2(s.download(), o.state(), 3, s=s)
+    say("  rel L2", r)
+    assert r <= (TOL if precision == 0 else 1e-6)
+
+
 @pytest.mark.parametrize("ghost,precision", [(4, 0), (5, 0), (5, 1)])
 def test_flux_history_3d(oracle_mod, S, ghost, precision):
     # Alg. caa-std / caa-at with stored fluxes on hexahedra: FP64 against the
