@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libadg.so")
-SOURCES = ["adg_rhs.hip", "adg_rhs2d.hip", "adg_rhs3d.hip", "adg_aux.hip", "adg_mlp.hip", "adg_api.cpp"]
+SOURCES = ["adg_rhs.hip", "adg_rhs2d.hip", "adg_rhs3d.hip", "adg_rhs3d_split.hip", "adg_aux.hip", "adg_mlp.hip",
+           "adg_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -320,6 +320,11 @@ hipError_t launch_rhs_stage_2d(int degree, int precision, const Mesh& M, const A
 hipError_t launch_rhs_stage_3d(int degree, int precision, const Mesh& M, const Async& A, const Stage& S,
                                const double* u_in, const double* u_n, double* out, int src, double* ring,
                                const double* ghost, hipStream_t st);
+// the d = 3 stage kernel for degree 3, each element variable split over a
+// pair of lanes (one wavefront per 6 elements); launch_rhs_stage forwards to it
+hipError_t launch_rhs_stage_3d_split(int degree, int precision, const Mesh& M, const Async& A, const Stage& S,
+                                     const double* u_in, const double* u_n, double* out, int src, double* ring,
+                                     const double* ghost, hipStream_t st);
 hipError_t launch_init(int dim, int degree, const Mesh& M, int problem, const Prm& prm, double* u,
                        const double* tab64, hipStream_t st);
 hipError_t launch_norms(int dim, int degree, const Mesh& M, int what, int problem, const Prm& prm, double t,

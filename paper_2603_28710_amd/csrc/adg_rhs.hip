@@ -1,6 +1,9 @@
-// adg_rhs.hip — the fused SSP-RK3 stage of the DG right-hand side on gfx950.
+// adg_rhs.hip — the fused SSP-RK3 stage of the DG right-hand side on gfx950:
+// the LDS-staged kernel (hexahedra of degree 4) and the dispatch of every
+// stage launch to its kernel (quadrilaterals: adg_rhs2d.hip; hexahedra of
+// degree 1 and 2: adg_rhs3d.hip; degree 3: adg_rhs3d_split.hip).
 //
-// One workgroup (256 threads) owns NE consecutive elements (x fastest) and
+// One workgroup (one wavefront) owns NE consecutive elements (x fastest) and
 // computes, in LDS and registers, k = M_e^{-1} L_h(u_in) for each of them
 // (Sec. 2.1, eq. weakform-dealii / weakform-compact-dealii), then the
 // Shu-Osher combine out = a u_n + b (u_in + dt k) in FP64.
@@ -515,7 +518,7 @@ static hipError_t launch_rhs_prec(int dim, int degree, const Mesh& M, const Asyn
                                   const double* ghost, const T* tab, hipStream_t st) {
 #define ADG_RHS_CASE(d, p) \
   if (dim == d && degree == p) return launch_rhs_t<T, d, p>(M, A, S, u_in, u_n, out, src, ring, ghost, tab, st);
-  ADG_RHS_CASE(3, 3) ADG_RHS_CASE(3, 4)
+  ADG_RHS_CASE(3, 4)
 #undef ADG_RHS_CASE
   return hipErrorInvalidValue;
 }
@@ -527,6 +530,8 @@ hipError_t launch_rhs_stage(int dim, int degree, int precision, const Mesh& M, c
     return launch_rhs_stage_2d(degree, precision, M, A, S, u_in, u_n, out, src, ring, ghost, st);
   if (degree <= 2)
     return launch_rhs_stage_3d(degree, precision, M, A, S, u_in, u_n, out, src, ring, ghost, st);
+  if (degree == 3)
+    return launch_rhs_stage_3d_split(degree, precision, M, A, S, u_in, u_n, out, src, ring, ghost, st);
   if (precision == 1)
     return launch_rhs_prec<float>(dim, degree, M, A, S, u_in, u_n, out, src, ring, ghost, tab32, st);
   return launch_rhs_prec<double>(dim, degree, M, A, S, u_in, u_n, out, src, ring, ghost, tab64, st);

@@ -22,8 +22,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_DOUBLES = 32 * 1024 * 1024  # 256 MiB read + 256 MiB written per copy
 
 
-KERNEL_SOURCES = ("adg_rhs.hip", "adg_rhs2d.hip", "adg_rhs3d.hip", "adg_device.h", "adg_internal.h",
-                  "adg_tables.h")
+KERNEL_SOURCES = ("adg_rhs.hip", "adg_rhs2d.hip", "adg_rhs3d.hip", "adg_rhs3d_split.hip", "adg_device.h",
+                  "adg_internal.h", "adg_tables.h")
 
 
 def source_hash():
