@@ -21,14 +21,14 @@
 //             k(iz, iy, ix) += BW[iz][qz] A(iy, ix) + GW[iz][qz] C(iy, ix)
 //           (BW = M1^{-1} B^T W, GW = M1^{-1} B^T D^T W;
 //           eq. weakform-dealii / weakform-compact-dealii).
-//   faces:  one face at a time. On x and z faces each lane holds 8 face
-//           nodes (its two rows), interpolates them along the face axis it
-//           holds whole, swaps, and finishes the interpolation; a y face
-//           lies in one lane's rows and that lane interpolates it alone.
-//           One lane per (element, point) evaluates the LLF flux (eq. lfflux
-//           / lfflux-lambda) in canonical (left, right) order; each lane
-//           lifts its variable with BW along both tangential axes onto its
-//           own face nodes and adds the column of M1^{-1} at that face.
+//   faces:  one face at a time, the pair splitting its two sides: lane 0
+//           reads the own face nodes (again, from the stage input) and
+//           publishes them, lane 1 builds the neighbour trace; each
+//           interpolates its side to the face's Gauss points. One lane per
+//           (element, point) evaluates the LLF flux (eq. lfflux /
+//           lfflux-lambda) in canonical (left, right) order; each lane lifts
+//           its variable with BW along both tangential axes onto the face
+//           nodes of its own rows and adds the column of M1^{-1} at that face.
 //   stage:  out = a u_n + b (u_in + dt k) in FP64 from the FP64 registers.
 //
 // The ring publish (stage 0), the delay schedule, the AT extrapolation, the
@@ -262,80 +262,54 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
   const bool flux_mode = src == kSrcFlux;
   const long long ring_level = M.nfs * V * (flux_mode ? Fq : Fn);  // values per ring level
   const bool publish = src == kSrcRing && A.stage == 0;
-  // The face nodes a lane holds, as (c, j): slot c of its list and the
-  // face-local index j = j0 + P j1 of the trace layout.
-  //   a = 0: j0 = iy = 2h + jj, j1 = iz: slot c = j1 * 2 + jj (8 nodes)
-  //   a = 2: j0 = ix, j1 = iy = 2h + jj: slot c = jj * P + j0 (8 nodes)
-  //   a = 1: the face's row lies in lane h = s: j0 = ix, j1 = iz: c = j (16)
   auto face_pass = [&](auto fc) {
     constexpr int f = decltype(fc)::value;
     constexpr int a = f >> 1, s = f & 1, ia = s ? P - 1 : 0;
-    constexpr int NN = a == 1 ? Fn : 2 * P;  // nodes held per lane
-    const bool owner = a != 1 || h == s;
-    // face-local index of slot c, and this lane's own value there
-    auto fj = [&](int c) -> int {
-      if constexpr (a == 0) return 2 * h + (c & 1) + P * (c >> 1);
-      else if constexpr (a == 2) return (c % P) + P * (2 * h + c / P);
-      else return c;
-    };
-    // element-local node of slot c on the face plane i (this element's face:
-    // i = ia; the neighbour's across it: i = P - 1 - ia)
-    auto face_node = [&](int c, int i) -> int {
-      if constexpr (a == 0) return nodeS<P>(0, i, 2 * h + (c & 1), c >> 1);
-      else if constexpr (a == 2) return nodeS<P>(2, i, c % P, 2 * h + c / P);
-      else return nodeS<P>(1, i, c % P, c / P);
-    };
     __syncthreads();  // sX is rewritten
-    // the own face nodes, read again from the stage input (an L2 hit): the
-    // registers of the element data are needed by the faces' work
-    double own[NN];
+    // The pair splits the two sides of the face: lane h = 0 reads the own
+    // trace (the face nodes of the stage input, an L2 hit) and publishes it,
+    // lane h = 1 builds the neighbour trace (live values; the delayed / AT /
+    // learned trace at a PE-boundary face). Face nodes j = j0 + P j1.
+    double g[Fn];
 #pragma unroll
-    for (int c = 0; c < NN; ++c) own[c] = 0.0;
-    if (owner) {
-#pragma unroll
-      for (int c = 0; c < NN; ++c) own[c] = u_in[col + face_node(c, ia)];
-    }
-    auto own_node = [&](int c) -> double { return own[c]; };
-    auto nb_node = [&](int c) -> int { return face_node(c, P - 1 - ia); };
-    double g[NN];
-#pragma unroll
-    for (int c = 0; c < NN; ++c) g[c] = 0.0;
+    for (int j = 0; j < Fn; ++j) g[j] = 0.0;
     long long fs = -1;
     int kd = 0;
     if (valid) {
       fs = async_on ? face_side_at(M, pos, f) : -1;
       if (fs >= 0 && (src == kSrcRing || flux_mode)) kd = delay_of(M, A, sub_at(M, pos.sc), f);
-      if (owner) {
+      if (h == 0) {
+#pragma unroll
+        for (int j = 0; j < Fn; ++j) g[j] = u_in[col + nodeS<P>(a, ia, j % P, j / P)];
         if (fs >= 0 && publish) {
           double* dst = ring + A.slot_n * ring_level + fed_face_side(M, pos, f) * V * Fn + v * Fn;
 #pragma unroll
-          for (int c = 0; c < NN; ++c) dst[fj(c)] = own_node(c);
+          for (int j = 0; j < Fn; ++j) dst[j] = g[j];
         }
-        if (fs < 0 || ((src == kSrcRing || flux_mode) && kd == 0)) {
-          const unsigned nb = (unsigned)neighbour_of(M, e, pos, f);
-          const double* gp = u_in + (size_t)nb * (V * Pd) + v * Pd;
+      } else if (fs < 0 || ((src == kSrcRing || flux_mode) && kd == 0)) {
+        const unsigned nb = (unsigned)neighbour_of(M, e, pos, f);
+        const double* gp = u_in + (size_t)nb * (V * Pd) + v * Pd;
 #pragma unroll
-          for (int c = 0; c < NN; ++c) g[c] = gp[nb_node(c)];
-        } else if (flux_mode) {
-          // silent step: the face uses the stored flux, no trace needed
-        } else if (src == kSrcGhost) {
-          const double* gp = ghost + fs * V * Fn + v * Fn;
+        for (int j = 0; j < Fn; ++j) g[j] = gp[nodeS<P>(a, P - 1 - ia, j % P, j / P)];
+      } else if (flux_mode) {
+        // silent step: the face uses the stored flux, no trace needed
+      } else if (src == kSrcGhost) {
+        const double* gp = ghost + fs * V * Fn + v * Fn;
 #pragma unroll
-          for (int c = 0; c < NN; ++c) g[c] = gp[fj(c)];
-        } else if (A.ghost == 1) {
-          // standard flux on the trace kd steps old (eq. delayed-flux)
-          const double* gp = ring + ring_slot(A, kd) * ring_level + fs * V * Fn + v * Fn;
+        for (int j = 0; j < Fn; ++j) g[j] = gp[j];
+      } else if (A.ghost == 1) {
+        // standard flux on the trace kd steps old (eq. delayed-flux)
+        const double* gp = ring + ring_slot(A, kd) * ring_level + fs * V * Fn + v * Fn;
 #pragma unroll
-          for (int c = 0; c < NN; ++c) g[c] = gp[fj(c)];
-        } else {
-          // AT extrapolation to the stage time, tau = kd + c_m (eq. at-flux)
-          const double tau = kd + A.c_m;
-          for (int l = 0; l < A.levels; ++l) {
-            const double wl = at_weight(l, A.levels, tau);
-            const double* gp = ring + ring_slot(A, kd + l) * ring_level + fs * V * Fn + v * Fn;
+        for (int j = 0; j < Fn; ++j) g[j] = gp[j];
+      } else {
+        // AT extrapolation to the stage time, tau = kd + c_m (eq. at-flux)
+        const double tau = kd + A.c_m;
+        for (int l = 0; l < A.levels; ++l) {
+          const double wl = at_weight(l, A.levels, tau);
+          const double* gp = ring + ring_slot(A, kd + l) * ring_level + fs * V * Fn + v * Fn;
 #pragma unroll
-            for (int c = 0; c < NN; ++c) g[c] = fma(wl, gp[fj(c)], g[c]);
-          }
+          for (int j = 0; j < Fn; ++j) g[j] = fma(wl, gp[j], g[j]);
         }
       }
     }
@@ -343,66 +317,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
       sFsF[le] = fs;
       sKdF[le] = kd;
     }
-    // own and neighbour traces at the Gauss points m = q0 + Q q1 of the face,
-    // one side at a time (sd = 0: own nodes, 1: neighbour's)
-    auto trace_side = [&](auto sdc) {
-      constexpr int sd = decltype(sdc)::value;
-      auto val = [&](int c) -> T { return sd == 0 ? (T)own_node(c) : (T)g[c]; };
-      T* dst = mine + sd * Fq * V + v;
-      if constexpr (a == 1) {
-        if (owner) {
-          T X[P][Q];
+    // this lane's side of the trace at the Gauss points (q0 + Q q1)
+    {
+      T X[P][Q];
 #pragma unroll
-          for (int j1 = 0; j1 < P; ++j1)
+      for (int j1 = 0; j1 < P; ++j1)
 #pragma unroll
-            for (int q0 = 0; q0 < Q; ++q0) {
-              T acc = (T)O.B[q0][0] * val(j1 * P);
+        for (int q0 = 0; q0 < Q; ++q0) {
+          T acc = (T)O.B[q0][0] * (T)g[j1 * P];
 #pragma unroll
-              for (int j0 = 1; j0 < P; ++j0) acc = fmx((T)O.B[q0][j0], val(j1 * P + j0), acc);
-              X[j1][q0] = acc;
-            }
-#pragma unroll
-          for (int q1 = 0; q1 < Q; ++q1)
-#pragma unroll
-            for (int q0 = 0; q0 < Q; ++q0) {
-              T acc = (T)O.B[q1][0] * X[0][q0];
-#pragma unroll
-              for (int j1 = 1; j1 < P; ++j1) acc = fmx((T)O.B[q1][j1], X[j1][q0], acc);
-              dst[(q1 * Q + q0) * V] = acc;
-            }
+          for (int j0 = 1; j0 < P; ++j0) acc = fmx((T)O.B[q0][j0], (T)g[j1 * P + j0], acc);
+          X[j1][q0] = acc;
         }
-      } else {
-        // along the axis the lane holds whole (a = 0: z, index q1; a = 2:
-        // x, index q0), swap with the partner, then along the split axis
-        // over all four rows
-        T W[P][Q];
+      T* dst = mine + h * Fq * V + v;
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj)
+      for (int q1 = 0; q1 < Q; ++q1)
 #pragma unroll
-          for (int q = 0; q < Q; ++q) {
-            T acc = (T)O.B[q][0] * val(a == 0 ? jj : jj * P);
+        for (int q0 = 0; q0 < Q; ++q0) {
+          T acc = (T)O.B[q1][0] * X[0][q0];
 #pragma unroll
-            for (int i = 1; i < P; ++i) acc = fmx((T)O.B[q][i], val(a == 0 ? i * 2 + jj : jj * P + i), acc);
-            const T p = pair_swap(acc);
-            W[jj][q] = hi ? p : acc;
-            W[2 + jj][q] = hi ? acc : p;
-          }
-        if (h == 0) {
-#pragma unroll
-          for (int qa = 0; qa < Q; ++qa)
-#pragma unroll
-            for (int qb = 0; qb < Q; ++qb) {
-              // a = 0: qa = q0 (the split axis y), qb = q1 (z); a = 2: qa = q1 (y), qb = q0 (x)
-              T acc = (T)O.B[qa][0] * W[0][qb];
-#pragma unroll
-              for (int i = 1; i < P; ++i) acc = fmx((T)O.B[qa][i], W[i][qb], acc);
-              dst[(a == 0 ? qa + Q * qb : qb + Q * qa) * V] = acc;
-            }
+          for (int j1 = 1; j1 < P; ++j1) acc = fmx((T)O.B[q1][j1], X[j1][q0], acc);
+          dst[(q1 * Q + q0) * V] = acc;
         }
-      }
-    };
-    trace_side(std::integral_constant<int, 0>{});
-    trace_side(std::integral_constant<int, 1>{});
+    }
     __syncthreads();
     // numerical flux, one lane per (element, face point), in place of the
     // own trace, scaled by -(n.e_a) 2/h_a
