@@ -62,6 +62,40 @@ __device__ __forceinline__ void num_flux(const T* wl, const T* wr, int a, T gamm
   for (int v = 0; v < V; ++v) G[v] = (T)0.5 * (Fl[v] + Fr[v]) + hl * (wl[v] - wr[v]);
 }
 
+// n <= NMAX consecutive doubles between global memory and LDS, by the whole
+// wavefront in 16-byte pieces (both addresses 16-byte aligned), four loads in
+// flight per lane before their stores: a wavefront's elements are one
+// contiguous range, so staging them through LDS turns per-lane strided
+// accesses into coalesced ones
+template <int NMAX>
+__device__ __forceinline__ void wave_copy(double* dst, const double* src, int n) {
+  constexpr int IT = (NMAX / 2 + 63) / 64;
+  const int lane = threadIdx.x, n2 = n >> 1;
+  const double2* s2 = reinterpret_cast<const double2*>(src);
+  double2* d2 = reinterpret_cast<double2*>(dst);
+  // past the end a lane copies piece 0 again (the same value to the same
+  // place), which keeps the loop free of branches
+#pragma unroll 1
+  for (int k0 = 0; k0 < IT; k0 += 4) {
+    const int i0 = lane + 64 * k0, i1 = i0 + 64, i2 = i0 + 128, i3 = i0 + 192;
+    const int j0 = i0 < n2 ? i0 : 0, j1 = i1 < n2 ? i1 : 0, j2 = i2 < n2 ? i2 : 0, j3 = i3 < n2 ? i3 : 0;
+    const double2 a0 = s2[j0], a1 = s2[j1], a2 = s2[j2], a3 = s2[j3];
+    d2[j0] = a0;
+    d2[j1] = a1;
+    d2[j2] = a2;
+    d2[j3] = a3;
+  }
+  if ((n & 1) && lane == 0) dst[n - 1] = src[n - 1];
+}
+template <int NMAX>
+__device__ __forceinline__ void wave_copy_in(double* lds, const double* g, int n) {
+  wave_copy<NMAX>(lds, g, n);
+}
+template <int NMAX>
+__device__ __forceinline__ void wave_copy_out(double* g, const double* lds, int n) {
+  wave_copy<NMAX>(g, lds, n);
+}
+
 // logical block index: the hardware deals consecutive blocks round-robin to
 // the 8 XCDs; remap so each XCD walks a contiguous range of elements and its
 // L2 holds the neighbours it reads

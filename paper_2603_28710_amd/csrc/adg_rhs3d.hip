@@ -61,18 +61,26 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
   // padded so 16-byte reads of consecutive elements spread over the banks
   constexpr int PER0 = 2 * Fq * V;
   constexpr int PER = sizeof(T) == 8 ? PER0 + (6 - PER0 % 4) % 4 : PER0 + (12 - PER0 % 8) % 8;
-  __shared__ __align__(16) T sX[(NE + 1) * PER];
+  // the same LDS stages the wavefront's element data (FP64) at the start and
+  // the end of the stage
+  constexpr int kXB = (NE + 1) * PER * (int)sizeof(T), kDB = NE * V * Pd * 8;
+  __shared__ __align__(16) unsigned char sRaw[kXB > kDB ? kXB : kDB];
+  T* sX = reinterpret_cast<T*>(sRaw);
+  double* sD = reinterpret_cast<double*>(sRaw);
   __shared__ long long sFsF[NE + 1];  // flux-history modes: face-side of the current face, or -1
   __shared__ int sKdF[NE + 1];        // and its delay
 
   const int lane = threadIdx.x, le = lane / V, v = lane - le * V;  // le == NE: idle lane
-  const long long e = (long long)xcd_block() * NE + le;
+  const long long e0 = (long long)xcd_block() * NE, e = e0 + le;
+  const int ne = M.E - e0 < NE ? (int)(M.E - e0) : NE;
   const bool valid = le < NE && e < M.E;
-  const long long col = (valid ? e : 0) * (V * Pd) + v * Pd;  // this lane's P^3 values
 
   double u[Pd];
+  wave_copy_in<NE * V * Pd>(sD, u_in + e0 * V * Pd, ne * V * Pd);
+  __syncthreads();
 #pragma unroll
-  for (int i = 0; i < Pd; ++i) u[i] = valid ? u_in[col + i] : 0.0;
+  for (int i = 0; i < Pd; ++i) u[i] = valid ? sD[(le * V + v) * Pd + i] : 0.0;
+  __syncthreads();
 
   T k[Pd];
 #pragma unroll
@@ -367,18 +375,22 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
   face_pass(std::integral_constant<int, 4>{});
   face_pass(std::integral_constant<int, 5>{});
 
-  // ---- SSP-RK3 combine in FP64
+  // ---- SSP-RK3 combine in FP64, through LDS (u_n may be the output)
+  __syncthreads();
+  if (S.a != 0.0) wave_copy_in<NE * V * Pd>(sD, u_n + e0 * V * Pd, ne * V * Pd);
+  __syncthreads();
   if (valid) {
-    double* o = out + col;
+    double* o = sD + (le * V + v) * Pd;
     if (S.a == 0.0) {
 #pragma unroll
       for (int i = 0; i < Pd; ++i) o[i] = S.b * (u[i] + S.dt * (double)k[i]);
     } else {
-      const double* un = u_n + col;
 #pragma unroll
-      for (int i = 0; i < Pd; ++i) o[i] = S.a * un[i] + S.b * (u[i] + S.dt * (double)k[i]);
+      for (int i = 0; i < Pd; ++i) o[i] = S.a * o[i] + S.b * (u[i] + S.dt * (double)k[i]);
     }
   }
+  __syncthreads();
+  wave_copy_out<NE * V * Pd>(out + e0 * V * Pd, sD, ne * V * Pd);
 }
 
 template <typename T, int P>
