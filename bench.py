@@ -131,7 +131,7 @@ def cpu_baseline(w, target_s=15.0):
     t0 = time.perf_counter()
     o.step(1, dt)
     t1 = time.perf_counter()
-    n = max(1, min(50, int(target_s / max(t1 - t0, 1e-3)) - 1))
+    n = max(1, min(2000, int(target_s / max(t1 - t0, 1e-3)) - 1))
     t2 = time.perf_counter()
     o.step(n, dt)
     t3 = time.perf_counter()

@@ -10,6 +10,8 @@ summarize:  reads the two counter CSVs, scales the stage kernel's per-dispatch
             bench.py picks up (it is ignored once the kernel source changes).
 kstats:     turns the kernel_stats.csv of `rocprofv3 --kernel-trace --stats`
             into a short text table, headed by the command that produced it.
+sqstats:    per-wavefront averages of the SQ counter passes (instruction
+            mix, issue and wait cycles) of the stage kernel.
 """
 import argparse
 import csv
@@ -136,6 +138,47 @@ def kstats(stats_csv, command, out):
     print("\n".join(lines))
 
 
+SQ_PASSES = {
+    "A": "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM SQ_INSTS_VALU_FMA_F64 "
+         "SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64",
+    "B": "SQ_WAVES SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY SQ_ACTIVE_INST_VALU "
+         "SQ_ACTIVE_INST_SCA SQ_ACTIVE_INST_LDS",
+}
+
+
+def sqstats(csvs, workload, out):
+    """per-wavefront averages of the SQ counters of the stage kernel, from
+    one counter CSV per pass (rocprofv3 collects each pass in its own run)"""
+    per = {}
+    kname = None
+    for path in csvs:
+        disp = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if "rhs_stage" not in row["Kernel_Name"]:
+                    continue
+                kname = kname or _short(row["Kernel_Name"])
+                d = disp.setdefault(row["Dispatch_Id"], {})
+                d[row["Counter_Name"]] = d.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+        for d in disp.values():
+            w = d.get("SQ_WAVES", 0.0)
+            for c, val in d.items():
+                if c != "SQ_WAVES" and w > 0:
+                    per.setdefault(c, []).append(val / w)
+    cmd = ("rocprofv3 --pmc {counters} --output-format csv -d <dir> -o p -- python3 "
+           "paper_2603_28710_amd/profile_traffic.py run --steps 2 --workload " + workload)
+    lines = [f"# rocprofv3 SQ counters of {kname}, per wavefront (kernel sources sha256/16 {source_hash()})",
+             f"# workload {workload}; one run per pass:"]
+    lines += [f"#   pass {k}: " + cmd.format(counters=v) for k, v in SQ_PASSES.items()]
+    lines += ["# (the cycle counters SQ_WAVE_CYCLES, SQ_WAIT_* and SQ_ACTIVE_* tick once per 4 clocks)", ""]
+    for c in sorted(per):
+        v = per[c]
+        lines.append(f"{c:28s} {sum(v) / len(v):12.1f}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -151,11 +194,17 @@ def main():
     k.add_argument("--stats", required=True)
     k.add_argument("--command", required=True)
     k.add_argument("--out", required=True)
+    q = sub.add_parser("sqstats")
+    q.add_argument("--csv", nargs="+", required=True)
+    q.add_argument("--workload", default="vortex256_p3_at3_uniformL3")
+    q.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd == "run":
         run(a.workload, a.steps)
     elif a.cmd == "summarize":
         summarize(a.fetch, a.write, a.workload, a.out)
+    elif a.cmd == "sqstats":
+        sqstats(a.csv, a.workload, a.out)
     else:
         kstats(a.stats, a.command, a.out)
 
