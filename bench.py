@@ -30,6 +30,14 @@ WORKLOADS = {
     "vortex256_p3_at3_uniformL3": dict(
         cfg=dict(dim=2, degree=3, cells=(256, 256, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
         asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=0),
+    # synchronous references of the 256^2 vortex and the 64^3 density wave
+    # (no ring, no delays): the cost of the asynchronous machinery on one GPU
+    "vortex256_p3_sync": dict(
+        cfg=dict(dim=2, degree=3, cells=(256, 256, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
+        asy=dict(ghost=0, delay_kind=0, L=0, levels=3, seed=0), problem=0, precision=0),
+    "wave64_p3_sync": dict(
+        cfg=dict(dim=3, degree=3, cells=(64, 64, 64), parts=(4, 4, 4), lo=(0, 0, 0), hi=(1, 1, 1)),
+        asy=dict(ghost=0, delay_kind=0, L=0, levels=3, seed=0), problem=1, precision=0),
     "vortex16_p2_sync": dict(
         cfg=dict(dim=2, degree=2, cells=(16, 16, 1), parts=(1, 1, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
         asy=dict(ghost=0, delay_kind=0, L=0, levels=3, seed=0), problem=0, precision=0),
