@@ -281,6 +281,9 @@ __host__ __device__ inline int delay_of(const Mesh& M, const Async& A, int sub, 
   return (int)(k < cap ? k : cap);
 }
 
+// the most AT levels a run may use (async.levels)
+constexpr int kMaxLevels = 4;
+
 // AT weight of stored level l (0 = newest) among nlev <= 4 levels for the
 // extrapolation to the fractional delay tau (eq. at-flux): the Lagrange weight
 // prod_{i != l} (tau + i) / (i - l), which solves the moment constraints of

@@ -380,9 +380,13 @@ __global__ __launch_bounds__(kNT3) void rhs_stage_kernel(Mesh M, Async A, Stage 
         double acc[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) acc[v] = 0.0;
-        for (int l = 0; l < A.levels; ++l) {
-          const double wl = at_weight(l, A.levels, tau);
-          const double* g = ring + ring_slot(A, k + l) * ring_level + fs + j;
+        // at most kMaxLevels levels; past A.levels the newest is read again
+        // with weight 0, so every load is issued before the first is used
+#pragma unroll
+        for (int l = 0; l < kMaxLevels; ++l) {
+          const bool on = l < A.levels;
+          const double wl = on ? at_weight(l, A.levels, tau) : 0.0;
+          const double* g = ring + ring_slot(A, k + (on ? l : 0)) * ring_level + fs + j;
 #pragma unroll
           for (int v = 0; v < V; ++v) acc[v] += wl * g[v * Fn];
         }
@@ -432,9 +436,13 @@ __global__ __launch_bounds__(kNT3) void rhs_stage_kernel(Mesh M, Async A, Stage 
           for (int v = 0; v < V; ++v) acc[v] = fp[ring_slot(A, fkd) * ring_level + v * Fq];
         } else {
           const double tau = fkd + A.c_m;
-          for (int l = 0; l < A.levels; ++l) {
-            const double w = at_weight(l, A.levels, tau);
-            const double* lp = fp + ring_slot(A, fkd + l) * ring_level;
+          // at most kMaxLevels levels; past A.levels the newest is read again
+          // with weight 0, so every load is issued before the first is used
+#pragma unroll
+          for (int l = 0; l < kMaxLevels; ++l) {
+            const bool on = l < A.levels;
+            const double w = on ? at_weight(l, A.levels, tau) : 0.0;
+            const double* lp = fp + ring_slot(A, fkd + (on ? l : 0)) * ring_level;
 #pragma unroll
             for (int v = 0; v < V; ++v) acc[v] = fma(w, lp[v * Fq], acc[v]);
           }

@@ -239,9 +239,13 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
         } else {
           // AT extrapolation to the stage time, tau = kd + c_m (eq. at-flux)
           const double tau = kd + A.c_m;
-          for (int l = 0; l < A.levels; ++l) {
-            const double wl = at_weight(l, A.levels, tau);
-            const double* gp = ring + ring_slot(A, kd + l) * ring_level + fs * V * P + v * P;
+          // at most kMaxLevels levels; past A.levels the newest is read again
+          // with weight 0, so every load is issued before the first is used
+#pragma unroll
+          for (int l = 0; l < kMaxLevels; ++l) {
+            const bool on = l < A.levels;
+            const double wl = on ? at_weight(l, A.levels, tau) : 0.0;
+            const double* gp = ring + ring_slot(A, kd + (on ? l : 0)) * ring_level + fs * V * P + v * P;
 #pragma unroll
             for (int j = 0; j < P; ++j) g[j] = fma(wl, gp[j], g[j]);
           }
@@ -299,9 +303,13 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
               for (int vv = 0; vv < 4; ++vv) acc[vv] = fp[ring_slot(A, fkd) * ring_level + vv * Q];
             } else {
               const double tau = fkd + A.c_m;
-              for (int l = 0; l < A.levels; ++l) {
-                const double w = at_weight(l, A.levels, tau);
-                const double* lp = fp + ring_slot(A, fkd + l) * ring_level;
+              // at most kMaxLevels levels; past A.levels the newest is read again
+              // with weight 0, so every load is issued before the first is used
+#pragma unroll
+              for (int l = 0; l < kMaxLevels; ++l) {
+                const bool on = l < A.levels;
+                const double w = on ? at_weight(l, A.levels, tau) : 0.0;
+                const double* lp = fp + ring_slot(A, fkd + (on ? l : 0)) * ring_level;
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv) acc[vv] = fma(w, lp[vv * Q], acc[vv]);
               }
