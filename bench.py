@@ -46,7 +46,8 @@ WORKLOADS = {
         asy=dict(ghost=2, delay_kind=0, L=2, levels=3, seed=0), problem=1, precision=0),
     "vortex1024_p4_at3_uniformL3_fp32": dict(
         cfg=dict(dim=2, degree=4, cells=(1024, 1024, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
-        asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=1),
+        asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=1,
+        reference="vortex1024_p4_at3_uniformL3_fp64"),
     "vortex1024_p4_at3_uniformL3_fp64": dict(
         cfg=dict(dim=2, degree=4, cells=(1024, 1024, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
         asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=0),
@@ -60,7 +61,7 @@ WORKLOADS = {
     "wave128_p2_learned_uniformL4": dict(
         cfg=dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1)),
         asy=dict(ghost=3, delay_kind=1, L=4, levels=3, seed=0, learned_tol=1e-6), problem=1, precision=0,
-        cfl=0.05, net_seed=1),
+        cfl=0.05, net_seed=1, reference="wave128_p2_at3_uniformL4"),
     # the paper's own communication-avoiding algorithm with AT fluxes
     "vortex256_p3_fluxat3_caaL3": dict(
         cfg=dict(dim=2, degree=3, cells=(256, 256, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
@@ -148,6 +149,41 @@ def cpu_baseline(w, target_s=15.0):
             "sample": f"full mesh, {n} SSP-RK3 steps after 1 warm-up step ({t3 - t2:.1f} s)"}
 
 
+def run_steps(w, steps, warmup):
+    """a solver of workload w stepped warmup + steps times at the workload's
+    CFL; returns (solver, dt, wall seconds of the timed steps)"""
+    import torch
+
+    from paper_2603_28710_amd import binding as B
+    from paper_2603_28710_amd.solver import Solver
+
+    c, a = w["cfg"], w["asy"]
+    s = Solver(device="cuda:0", precision=w["precision"], **c, **a)
+    s.init_problem(w["problem"])
+    if a["ghost"] == B.ADG_GHOST_LEARNED:
+        s.predictor_init(w["net_seed"])
+    dt = s.stable_dt(w.get("cfl", 0.1))
+    s.step(warmup, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.step_status(steps, dt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if st != 0:
+        raise RuntimeError(B.adg_last_error())
+    return s, dt, t1 - t0
+
+
+def matched_error(s, sec, ref_name, steps, warmup):
+    """the workload's FP64 reference (same mesh, initial state, dt and step
+    count) run after the timed region: relative L2 difference of the states
+    (density, momentum, energy) and the reference's time over this one's"""
+    r, _, rsec = run_steps(WORKLOADS[ref_name], steps, warmup)
+    diff = s.diff_norm(r.download())
+    r.close()
+    return {"reference": ref_name, "rel_l2_vs_reference": list(diff), "speedup_vs_reference": rsec / sec}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +268,8 @@ def main():
         "ghost_kernel": {"avg_launch_us": gh_ms / max(gh_n, 1) * 1e3, "launches": gh_n},
         "l2_error_vs_exact": err,
     }
+    if "reference" in w:
+        out["matched_error"] = matched_error(s, sec, w["reference"], args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
