@@ -57,7 +57,7 @@ WORKLOADS = {
         asy=dict(ghost=2, delay_kind=1, L=4, levels=3, seed=0), problem=1, precision=0, cfl=0.05),
     # the learned ghost predictor (untrained, Glorot-initialised network from
     # a fixed seed: inference and the per-face judge cost the same whatever
-    # the weights; faces the judge rejects fall back to AT)
+    # the weights; a face whose correction exceeds the bound keeps AT)
     "wave128_p2_learned_uniformL4": dict(
         cfg=dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1)),
         asy=dict(ghost=3, delay_kind=1, L=4, levels=3, seed=0, learned_tol=1e-6), problem=1, precision=0,
@@ -268,6 +268,9 @@ def main():
         "ghost_kernel": {"avg_launch_us": gh_ms / max(gh_n, 1) * 1e3, "launches": gh_n},
         "l2_error_vs_exact": err,
     }
+    if a["ghost"] == B.ADG_GHOST_LEARNED:
+        rate, judged = s.predictor_stats()
+        out["ghost_kernel"].update({"faces_judged": judged, "accept_rate": rate})
     if "reference" in w:
         out["matched_error"] = matched_error(s, sec, w["reference"], args.steps, args.warmup)
     if not args.no_cpu_baseline:

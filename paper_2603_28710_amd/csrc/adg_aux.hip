@@ -81,7 +81,7 @@ __device__ void aux_sweep(const double* in, double* out, const double* A, int NI
 }
 
 template <int D, int P, int Q>
-__global__ __launch_bounds__(256) void init_kernel(Mesh M, int problem, Prm prm,
+__global__ __launch_bounds__(kThreads) void init_kernel(Mesh M, int problem, Prm prm,
                                                    double* __restrict__ u, const double* __restrict__ tab) {
   using Dm = AuxDims<D, P, Q>;
   constexpr int V = Dm::V, Pd = Dm::Pd, Qd = Dm::Qd;
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void init_kernel(Mesh M, int problem, Prm prm,
 // what: 0 error vs exact (3 comps), 1 integrals (V), 2 diff vs ref (6),
 //       3 check: non-finite, non-physical counts (2), 4 max wave speed (1)
 template <int D, int P, int Q>
-__global__ __launch_bounds__(256) void norms_kernel(Mesh M, int what, int problem, Prm prm,
+__global__ __launch_bounds__(kThreads) void norms_kernel(Mesh M, int what, int problem, Prm prm,
                                                     double t, const double* __restrict__ u,
                                                     const double* __restrict__ ref, const double* __restrict__ tab,
                                                     double* __restrict__ partial) {
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void norms_kernel(Mesh M, int what, int proble
   constexpr int V = Dm::V, Pd = Dm::Pd, Qd = Dm::Qd;
   constexpr TabOff to = tab_off(P, Q);
   __shared__ double sA[V * Qd], sB[V * Qd];
-  __shared__ double red[256 * 6];
+  __shared__ double red[kThreads * 6];
   double acc[6] = {0, 0, 0, 0, 0, 0};
   const double gamma = M.gamma;
   for (long long e = blockIdx.x; e < M.E; e += gridDim.x) {
@@ -204,31 +204,31 @@ __global__ __launch_bounds__(256) void norms_kernel(Mesh M, int what, int proble
   }
   // fixed-order tree reduction inside the block
   const int nc = 6;
-  for (int k = 0; k < nc; ++k) red[k * 256 + threadIdx.x] = acc[k];
+  for (int k = 0; k < nc; ++k) red[k * kThreads + threadIdx.x] = acc[k];
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s)
       for (int k = 0; k < nc; ++k) {
-        const double a = red[k * 256 + threadIdx.x], b = red[k * 256 + threadIdx.x + s];
-        red[k * 256 + threadIdx.x] = what == 4 ? (a > b ? a : b) : a + b;
+        const double a = red[k * kThreads + threadIdx.x], b = red[k * kThreads + threadIdx.x + s];
+        red[k * kThreads + threadIdx.x] = what == 4 ? (a > b ? a : b) : a + b;
       }
     __syncthreads();
   }
-  if (threadIdx.x < nc) partial[blockIdx.x * nc + threadIdx.x] = red[threadIdx.x * 256];
+  if (threadIdx.x < nc) partial[blockIdx.x * nc + threadIdx.x] = red[threadIdx.x * kThreads];
 }
 
-__global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ partial, int nblk, int ncomp, int op,
+__global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restrict__ partial, int nblk, int ncomp, int op,
                                                      double* __restrict__ out) {
-  __shared__ double red[256];
+  __shared__ double red[kThreads];
   for (int k = 0; k < ncomp; ++k) {
     double a = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) {
+    for (int b = threadIdx.x; b < nblk; b += kThreads) {
       const double x = partial[b * 6 + k];
       a = op ? (x > a ? x : a) : a + x;
     }
     red[threadIdx.x] = a;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
       if ((int)threadIdx.x < s) {
         const double x = red[threadIdx.x], y = red[threadIdx.x + s];
         red[threadIdx.x] = op ? (x > y ? x : y) : x + y;
@@ -248,8 +248,8 @@ hipError_t launch_init(int dim, int degree, const Mesh& M, int problem, const Pr
                        const double* tab64, hipStream_t st) {
 #define ADG_INIT_CASE(d, p)                                                                                    \
   if (dim == d && degree == p) {                                                                               \
-    hipLaunchKernelGGL((init_kernel<d, p + 1, p + 2>), dim3((unsigned)M.E), dim3(256), 0, st, M, problem, prm, u, \
-                       tab64);                                                                                 \
+    hipLaunchKernelGGL((init_kernel<d, p + 1, p + 2>), dim3((unsigned)M.E), dim3(kThreads), 0, st, M, problem, \
+                       prm, u, tab64);                                                                         \
     return hipGetLastError();                                                                                  \
   }
   ADG_INIT_CASE(2, 1) ADG_INIT_CASE(2, 2) ADG_INIT_CASE(2, 3) ADG_INIT_CASE(2, 4)
@@ -263,8 +263,8 @@ hipError_t launch_norms(int dim, int degree, const Mesh& M, int what, int proble
                         hipStream_t st) {
 #define ADG_NORM_CASE(d, p)                                                                                 \
   if (dim == d && degree == p) {                                                                            \
-    hipLaunchKernelGGL((norms_kernel<d, p + 1, p + 2>), dim3(nblk), dim3(256), 0, st, M, what, problem, prm, t, \
-                       u, ref, tab64, partial);                                                             \
+    hipLaunchKernelGGL((norms_kernel<d, p + 1, p + 2>), dim3(nblk), dim3(kThreads), 0, st, M, what, problem, \
+                       prm, t, u, ref, tab64, partial);                                                     \
     return hipGetLastError();                                                                               \
   }
   ADG_NORM_CASE(2, 1) ADG_NORM_CASE(2, 2) ADG_NORM_CASE(2, 3) ADG_NORM_CASE(2, 4)
@@ -274,7 +274,7 @@ hipError_t launch_norms(int dim, int degree, const Mesh& M, int what, int proble
 }
 
 hipError_t launch_reduce(const double* partial, int nblk, int ncomp, int op, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, partial, nblk, ncomp, op, out);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, st, partial, nblk, ncomp, op, out);
   return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@ constexpr int kMaxQ = 6;   // Gauss points per direction
 constexpr int kMaxV = 5;
 constexpr int kMlpK = 4;   // past levels read by the learned predictor
 constexpr int kMlpH = 64;  // hidden width
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;  // block size of the set-up and diagnostic kernels
 
 // Offsets into the per-context table (doubles; a float copy has the same
 // offsets). B: interpolation nodes->Gauss [Q][P]; BT: its transpose [P][Q];
