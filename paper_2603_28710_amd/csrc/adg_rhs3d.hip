@@ -4,7 +4,12 @@
 // One wavefront owns 12 consecutive elements (x fastest); lane (e, v) keeps
 // the P^3 nodal values of variable v of element e in registers (lanes 60-63
 // idle) and applies the tensor-product operators of that variable there. LDS
-// carries only what the nonlinear fluxes need (all V variables at a point).
+// carries what the nonlinear fluxes need (all V variables at a point) and,
+// at the start and in the combine, the wavefront's element data: its 12
+// elements are one contiguous range, moved between global memory and LDS by
+// coalesced 16-byte accesses of the whole wavefront (a lane's own values lie
+// P^3 doubles from the next lane's, so direct per-lane accesses would touch
+// one cache line per lane and instruction).
 //
 //   volume: one Gauss plane q_z at a time. The lane combines its nodal
 //           planes along z (B), interpolates the result in x and y, and
@@ -23,7 +28,7 @@
 //           lfflux-lambda) in canonical (left, right) order; each lane lifts
 //           its variable with BW along the two tangential axes and adds the
 //           column of M1^{-1} at that face.
-//   stage:  out = a u_n + b (u_in + dt k) in FP64 from the FP64 registers.
+//   stage:  out = a u_n + b (u_in + dt k) in FP64, u_n and out through LDS.
 //
 // The ring publish (stage 0, stale and AT modes), the delay schedule, the AT
 // extrapolation and the flux history follow the same rules as the other
