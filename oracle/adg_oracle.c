@@ -22,6 +22,8 @@
  *   - AT coefficients from the moment constraints, with the stage-fractional
  *     delay of the naive RK coupling (Sec. 3.2, eq. at-flux-constraints,
  *     Table at-flux-coeffs).
+ *   - the two-register LSERK(2,2) and LSERK(3,3) of Sec. 2.3 (eq. lserk-dg,
+ *     Table lserk-scheme), besides the default SSP-RK3.
  * Readings where the paper is silent (time integrator SSP-RK3, what is delayed,
  * delay draws, warm-up, learned correction) are the ones listed in the design
  * notes; each is marked "reading" below.
@@ -278,6 +280,29 @@ static const double SSP_A[3] = {0.0, 0.75, 1.0 / 3.0};
 static const double SSP_B[3] = {1.0, 0.25, 2.0 / 3.0};
 static const double SSP_C[3] = {0.0, 1.0, 0.5};
 
+/* LSERK(s,o) of eq. lserk-dg with the digits of Table lserk-scheme:
+ *   k_m = M^-1 L(r_m),  r_{m+1} = w + dt a_m k_m,  w <- w + dt b_m k_m,
+ * r_1 = w = u^n, the new state the final w. The w on the right of both
+ * updates is the running accumulator (reading: the equation's w^n). Stage
+ * times from the scheme itself: c_1 = 0, c_m = b_1 + ... + b_{m-2} + a_{m-1}
+ * (for LSERK(3,3) 0.632124764, where the table prints 0.632125000). */
+static const double LS22_A[2] = {1.0, 0.0};
+static const double LS22_B[2] = {0.5, 0.5};
+static const double LS33_A[3] = {0.755726352, 0.386954477, 0.0};
+static const double LS33_B[3] = {0.245170287, 0.184896052, 0.569933661};
+
+static int n_stages(const orc_solver* s) { return s->c.integrator == 1 ? 2 : 3; }
+
+static double stage_time(const orc_solver* s, int m) {
+  if (s->c.integrator == 0) return SSP_C[m];
+  const double* a = s->c.integrator == 1 ? LS22_A : LS33_A;
+  const double* b = s->c.integrator == 1 ? LS22_B : LS33_B;
+  if (m == 0) return 0.0;
+  double c = a[m - 1];
+  for (int j = 0; j < m - 1; ++j) c += b[j];
+  return c;
+}
+
 static int64_t elem_of(const orc_solver* s, int64_t i, int64_t j, int64_t k) {
   return i + s->nc[0] * (j + s->nc[1] * k);
 }
@@ -323,7 +348,7 @@ void* orc_create(const orc_cfg* cfg) {
   orc_solver* s = (orc_solver*)xmalloc(sizeof(orc_solver));
   s->c = *cfg;
   int D = cfg->dim;
-  if (D < 2 || D > 3 || cfg->p < 1 || cfg->p > 5) {
+  if (D < 2 || D > 3 || cfg->p < 1 || cfg->p > 5 || cfg->integrator < 0 || cfg->integrator > 2) {
     free(s);
     return NULL;
   }
@@ -729,7 +754,7 @@ static void ghost_face(orc_solver* s, const double* uin, int64_t e, int f, int s
     return;
   }
   int lev = s->c.levels;
-  double tau = k + SSP_C[stage];
+  double tau = k + stage_time(s, stage);
   double c[MAXN];
   orc_at_weights(lev, tau, c);
   if (s->c.ghost == 2) {
@@ -757,7 +782,7 @@ static void ghost_face(orc_solver* s, const double* uin, int64_t e, int f, int s
       gn[j * V + v] = a;
     }
     double x[32], y[MAXV], S3;
-    orc_learned_features(s, T, tau, SSP_C[stage], x, &S3);
+    orc_learned_features(s, T, tau, stage_time(s, stage), x, &S3);
     if (s->has_mlp) {
       mlp_bf16_forward(s, x, y);
     } else {
@@ -819,7 +844,7 @@ static void face_fluxes(orc_solver* s, const double* uin, int stage, int use_gho
         size_t lvl = (size_t)E * D * Fq * V;
         size_t off = ((size_t)e * D + a) * Fq * V;
         double c[MAXN];
-        if (k > 0 && s->c.ghost == 5) orc_at_weights(s->c.levels, k + SSP_C[stage], c);
+        if (k > 0 && s->c.ghost == 5) orc_at_weights(s->c.levels, k + stage_time(s, stage), c);
         for (int fq = 0; fq < Fq; ++fq) {
           if (k == 0) {
             trace_at(s, uin, e, fR, fq, wm);
@@ -979,15 +1004,35 @@ int orc_step(void* vs, int64_t nsteps, double dt) {
   size_t nd = (size_t)orc_ndof(s);
   for (int64_t it = 0; it < nsteps; ++it) {
     if (s->hist) memcpy(s->hist + (size_t)(s->n % s->R) * nd, s->u, sizeof(double) * nd);
-    double* in[3] = {s->u, s->ua, s->ub};
-    double* outp[3] = {s->ua, s->ub, s->u};
-    for (int m = 0; m < 3; ++m) {
-      full_rhs(s, in[m], m, 1, s->kb);
-      double a = SSP_A[m], b = SSP_B[m];
-      const double* ui = in[m];
-      double* uo = outp[m];
+    if (s->c.integrator == 0) {
+      double* in[3] = {s->u, s->ua, s->ub};
+      double* outp[3] = {s->ua, s->ub, s->u};
+      for (int m = 0; m < 3; ++m) {
+        full_rhs(s, in[m], m, 1, s->kb);
+        double a = SSP_A[m], b = SSP_B[m];
+        const double* ui = in[m];
+        double* uo = outp[m];
 #pragma omp parallel for schedule(static)
-      for (int64_t i = 0; i < (int64_t)nd; ++i) uo[i] = a * s->u[i] + b * (ui[i] + dt * s->kb[i]);
+        for (int64_t i = 0; i < (int64_t)nd; ++i) uo[i] = a * s->u[i] + b * (ui[i] + dt * s->kb[i]);
+      }
+    } else {
+      /* two registers besides the state: r (stage input) and the next r */
+      const double* la = s->c.integrator == 1 ? LS22_A : LS33_A;
+      const double* lb = s->c.integrator == 1 ? LS22_B : LS33_B;
+      double *r = s->ua, *rn = s->ub;
+      memcpy(r, s->u, sizeof(double) * nd);
+      for (int m = 0; m < n_stages(s); ++m) {
+        full_rhs(s, r, m, 1, s->kb);
+        const int last = m == n_stages(s) - 1;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < (int64_t)nd; ++i) {
+          if (!last) rn[i] = s->u[i] + dt * la[m] * s->kb[i];
+          s->u[i] = s->u[i] + dt * lb[m] * s->kb[i];
+        }
+        double* t = r;
+        r = rn;
+        rn = t;
+      }
     }
     s->n += 1;
     s->t += dt;

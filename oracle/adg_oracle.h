@@ -39,6 +39,8 @@ typedef struct orc_cfg {
   int32_t levels;       /* AT levels (order of the extrapolation) */
   uint64_t seed;        /* seed of the delay draws */
   double learned_tol;   /* accept bound on the learned correction (physical units) */
+  int32_t integrator;   /* 0 SSP-RK3 (Shu-Osher), 1 LSERK(2,2), 2 LSERK(3,3): the two-register
+                           low-storage schemes of eq. lserk-dg with Table lserk-scheme */
 } orc_cfg;
 
 enum { ORC_VORTEX = 0, ORC_DENSITY_WAVE = 1, ORC_CONSTANT = 2 };

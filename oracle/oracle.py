@@ -14,6 +14,7 @@ SYNC, STALE, AT, LEARNED, FLUX_STALE, FLUX_AT = 0, 1, 2, 3, 4, 5
 FIXED, UNIFORM, CAA = 0, 1, 2
 VORTEX, DENSITY_WAVE, CONSTANT = 0, 1, 2
 LLF, RUSANOV = 0, 1
+SSPRK3, LSERK22, LSERK33 = 0, 1, 2
 
 
 class OrcCfg(C.Structure):
@@ -23,7 +24,7 @@ class OrcCfg(C.Structure):
         ("lo", C.c_double * 3), ("hi", C.c_double * 3),
         ("gamma", C.c_double), ("flux", C.c_int32), ("ghost", C.c_int32),
         ("delay_kind", C.c_int32), ("L", C.c_int32), ("levels", C.c_int32),
-        ("seed", C.c_uint64), ("learned_tol", C.c_double),
+        ("seed", C.c_uint64), ("learned_tol", C.c_double), ("integrator", C.c_int32),
     ]
 
 
@@ -124,7 +125,7 @@ class Oracle:
 
     def __init__(self, dim=2, p=2, nq=0, cells=(16, 16, 1), parts=(1, 1, 1), lo=(0, 0, 0),
                  hi=(10, 10, 1), gamma=1.4, flux=LLF, ghost=SYNC, delay_kind=FIXED, L=0, levels=3,
-                 seed=0, learned_tol=1e-6):
+                 seed=0, learned_tol=1e-6, integrator=0):
         c = OrcCfg()
         c.dim, c.p, c.nq = dim, p, nq
         for k in range(3):
@@ -134,6 +135,7 @@ class Oracle:
             c.hi[k] = float(hi[k]) if k < len(hi) else 1.0
         c.gamma, c.flux, c.ghost, c.delay_kind = gamma, flux, ghost, delay_kind
         c.L, c.levels, c.seed, c.learned_tol = L, levels, seed, learned_tol
+        c.integrator = integrator
         self.cfg = c
         self.dim, self.p = dim, p
         self.P = p + 1

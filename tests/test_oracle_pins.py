@@ -436,3 +436,108 @@ def test_learned_silent_net_accepted_bad_net_rejected(oracle_mod):
         assert (rej == 0 and acc > 0) if accept else (acc == 0 and rej > 0)
         states.append(o.state())
     np.testing.assert_array_equal(states[0], states[1])
+
+
+# ------------------------------------------------------------ LSERK (Sec. 2.3)
+
+# Table lserk-scheme as printed: a_m, b_m (LSERK(2,2) and LSERK(3,3))
+LSERK_TABLE = {
+    1: ([1.0], [0.5, 0.5]),
+    2: ([0.755726352, 0.386954477], [0.245170287, 0.184896052, 0.569933661]),
+}
+
+
+def _butcher(a, b):
+    # the two-register recurrence r_{m+1} = w + dt a_m k_m, w += dt b_m k_m as
+    # a Butcher tableau: stage m+1 sees b_1..b_{m-1} and a_m
+    s = len(b)
+    A = np.zeros((s, s))
+    for m in range(1, s):
+        A[m, :m - 1] = b[:m - 1]
+        A[m, m - 1] = a[m - 1]
+    return A, np.array(b), A.sum(axis=1)
+
+
+@pytest.mark.parametrize("integ,order", [(1, 2), (2, 3)])
+def test_lserk_table_order_conditions(integ, order):
+    A, b, c = _butcher(*LSERK_TABLE[integ])
+    assert b.sum() == pytest.approx(1.0, abs=1e-9)
+    assert b @ c == pytest.approx(0.5, abs=1e-9)
+    if order >= 3:
+        assert b @ c ** 2 == pytest.approx(1 / 3, abs=2e-9)
+        assert b @ (A @ c) == pytest.approx(1 / 6, abs=2e-9)
+
+
+@pytest.mark.parametrize("integ", [1, 2])
+def test_lserk_step_is_its_butcher_tableau(oracle_mod, integ):
+    # one oracle step against the same scheme composed from the synchronous
+    # operator in Butcher form (a different representation of eq. lserk-dg)
+    O = oracle_mod
+    cfg = dict(dim=2, p=3, cells=(6, 5, 1), hi=(10, 10, 1))
+    o = O.Oracle(integrator=integ, **cfg)
+    o.init_problem(O.VORTEX)
+    u0 = o.state() + inputs.perturbation(o.ndof, 21, 1e-3)
+    o.set_state(u0)
+    dt = o.stable_dt(0.1)
+    A, b, _ = _butcher(*LSERK_TABLE[integ])
+    ks = []
+    for m in range(len(b)):
+        ks.append(o.rhs(u0 + dt * sum(A[m, j] * ks[j] for j in range(m))) if m else o.rhs(u0))
+    ref = u0 + dt * sum(b[m] * ks[m] for m in range(len(b)))
+    assert o.step(1, dt) == 0
+    np.testing.assert_allclose(o.state(), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("integ,order", [(1, 2), (2, 3)])
+def test_lserk_order_in_time(oracle_mod, integ, order):
+    O = oracle_mod
+    sols = []
+    for nst in (20, 40, 80):
+        o = O.Oracle(dim=2, p=4, cells=(4, 4, 1), hi=(1, 1, 1), integrator=integ)
+        o.init_problem(O.DENSITY_WAVE)
+        o.step(nst, 0.05 / nst * 4)
+        sols.append(o.state())
+    d1 = np.linalg.norm(sols[0] - sols[1])
+    d2 = np.linalg.norm(sols[1] - sols[2])
+    assert 2 ** (order - 0.2) < d1 / d2 < 2 ** (order + 0.2)
+
+
+@pytest.mark.parametrize("integ", [1, 2])
+def test_lserk_zero_delay_is_bitwise_synchronous(oracle_mod, integ):
+    O = oracle_mod
+    base = dict(dim=2, p=2, cells=(8, 8, 1), parts=(4, 2, 1), hi=(10, 10, 1), integrator=integ)
+    ref = O.Oracle(**base)
+    ref.init_problem(O.VORTEX)
+    dt = ref.stable_dt(0.1)
+    ref.step(6, dt)
+    o = O.Oracle(ghost=O.AT, delay_kind=O.FIXED, L=0, levels=3, **base)
+    o.init_problem(O.VORTEX)
+    o.step(6, dt)
+    np.testing.assert_array_equal(o.state(), ref.state())
+
+
+def test_lserk33_at_recovers_sync_under_delays(oracle_mod):
+    # the stage times c_m of LSERK(3,3) enter the AT fractional delay
+    O = oracle_mod
+    common = dict(parts=(4, 4, 1), kind=O.UNIFORM, L=2, cfl=0.05)
+    e_sync = _sweep_integ(O, 2, (8, 16, 32), ghost=O.SYNC, cfl=0.05, parts=(4, 4, 1))
+    e_st = _sweep_integ(O, 2, (8, 16, 32), ghost=O.STALE, **common)
+    e_at = _sweep_integ(O, 2, (8, 16, 32), ghost=O.AT, **common)
+    s_st = np.log2(e_st[:-1] / e_st[1:])
+    s_at = np.log2(e_at[:-1] / e_at[1:])
+    assert s_st[-1][0] < 1.4
+    assert s_at[-1][0] > 2.85
+    np.testing.assert_allclose(e_at, e_sync, rtol=0.02)
+
+
+def _sweep_integ(O, integ, ns, ghost=0, kind=0, L=0, cfl=0.1, tend=0.2, parts=(1, 1, 1)):
+    errs = []
+    for n in ns:
+        o = O.Oracle(dim=2, p=2, cells=(n, n, 1), parts=parts, hi=(1, 1, 1), ghost=ghost, delay_kind=kind, L=L,
+                     levels=3, integrator=integ)
+        o.init_problem(O.DENSITY_WAVE)
+        dt = cfl * (1.0 / n) / (2 ** 1.5 * 2.75)
+        nst = int(math.ceil(tend / dt))
+        assert o.step(nst, tend / nst) == 0
+        errs.append(o.error_norms(O.DENSITY_WAVE, tend))
+    return np.array(errs)
