@@ -17,8 +17,9 @@
  *   - AT extrapolation over past levels with the stage-fractional delay of the
  *     naive RK coupling: Sec. 3.2, eq. at-flux, at-flux-constraints,
  *     Table at-flux-coeffs; applied here to neighbour traces.
- *   - Time integration: explicit SSP-RK3 in Shu-Osher form (the paper's
- *     two-register LSERK of Sec. 2.3 is the same class of low-storage scheme).
+ *   - Time integration: explicit SSP-RK3 in Shu-Osher form (default), or the
+ *     paper's two-register LSERK(2,2) / LSERK(3,3) of Sec. 2.3 (eq. lserk-dg,
+ *     Table lserk-scheme; stage times from the scheme's own a and b).
  *
  * Conventions shared by every entry point
  *   - Every function returns adg_status: ADG_OK (0) or a negative code. No
@@ -63,7 +64,14 @@ typedef int32_t adg_status;
 #define ADG_FLUX_LLF 0     /* eq. lfflux with lambda as printed (includes the factor 1/2) */
 #define ADG_FLUX_RUSANOV 1 /* lambda = max(|u.n| + c) over both sides */
 /* time integrator */
-#define ADG_SSPRK3 0
+#define ADG_SSPRK3 0  /* three stages, Shu-Osher form; three state registers */
+/* LSERK(s,o) of eq. lserk-dg: k_m = M^-1 L(r_m), r_{m+1} = w + dt a_m k_m,
+ * w <- w + dt b_m k_m with r_1 = w = u^n and the digits of Table
+ * lserk-scheme; the stage times c_1 = 0, c_m = b_1 + .. + b_{m-2} + a_{m-1}
+ * enter the AT fractional delay tau = k + c_m. Uses the same three registers
+ * (u_n, u_a, u_b); the state is in u_n after every step. */
+#define ADG_LSERK22 1
+#define ADG_LSERK33 2
 /* arithmetic of the volume/face contractions and inverse mass */
 #define ADG_FP64 0
 #define ADG_FP32_CONTRACT 1 /* contractions in FP32; RK state, AT weights, norms in FP64 */
@@ -97,7 +105,7 @@ typedef struct adg_config {
   double lo[3], hi[3]; /* periodic box */
   double gamma;        /* ratio of specific heats (> 1) */
   int32_t flux;        /* ADG_FLUX_* */
-  int32_t integrator;  /* ADG_SSPRK3 */
+  int32_t integrator;  /* ADG_SSPRK3, ADG_LSERK22 or ADG_LSERK33 */
   int32_t precision;   /* ADG_FP64 or ADG_FP32_CONTRACT */
   int32_t check_every; /* 0: adg_step never checks the state; k>0: every k steps and at the end */
 } adg_config;

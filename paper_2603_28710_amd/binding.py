@@ -15,7 +15,7 @@ ADG_OK = 0
 ADG_ERR_INVALID, ADG_ERR_UNBOUND, ADG_ERR_HIP = -1, -2, -3
 ADG_ERR_NONFINITE, ADG_ERR_NONPHYSICAL, ADG_ERR_STATE = -4, -5, -6
 ADG_FLUX_LLF, ADG_FLUX_RUSANOV = 0, 1
-ADG_SSPRK3 = 0
+ADG_SSPRK3, ADG_LSERK22, ADG_LSERK33 = 0, 1, 2
 ADG_FP64, ADG_FP32_CONTRACT = 0, 1
 ADG_GHOST_SYNC, ADG_GHOST_STALE, ADG_GHOST_AT, ADG_GHOST_LEARNED = 0, 1, 2, 3
 ADG_GHOST_FLUX_STALE, ADG_GHOST_FLUX_AT = 4, 5
@@ -276,7 +276,7 @@ def adg_last_error():
 
 
 def make_config(dim=2, degree=2, cells=(16, 16, 1), parts=(1, 1, 1), lo=(0, 0, 0), hi=(10, 10, 1),
-                gamma=1.4, flux=ADG_FLUX_LLF, precision=ADG_FP64, check_every=0, n_q=0):
+                gamma=1.4, flux=ADG_FLUX_LLF, precision=ADG_FP64, check_every=0, n_q=0, integrator=ADG_SSPRK3):
     c = adg_config()
     c.dim, c.degree, c.n_q = dim, degree, n_q
     for k in range(3):
@@ -284,7 +284,7 @@ def make_config(dim=2, degree=2, cells=(16, 16, 1), parts=(1, 1, 1), lo=(0, 0, 0
         c.parts[k] = int(parts[k]) if k < len(parts) else 1
         c.lo[k] = float(lo[k]) if k < len(lo) else 0.0
         c.hi[k] = float(hi[k]) if k < len(hi) else 1.0
-    c.gamma, c.flux, c.integrator, c.precision, c.check_every = gamma, flux, ADG_SSPRK3, precision, check_every
+    c.gamma, c.flux, c.integrator, c.precision, c.check_every = gamma, flux, integrator, precision, check_every
     return c
 
 

@@ -72,6 +72,24 @@ namespace {
 const double kSspA[3] = {0.0, 0.75, 1.0 / 3.0};
 const double kSspB[3] = {1.0, 0.25, 2.0 / 3.0};
 const double kSspC[3] = {0.0, 1.0, 0.5};
+// LSERK(2,2), LSERK(3,3): a_m and b_m as printed in Table lserk-scheme
+const double kLs22A[2] = {1.0, 0.0}, kLs22B[2] = {0.5, 0.5};
+const double kLs33A[3] = {0.755726352, 0.386954477, 0.0}, kLs33B[3] = {0.245170287, 0.184896052, 0.569933661};
+
+int n_stages(int integrator) { return integrator == ADG_LSERK22 ? 2 : 3; }
+
+// stage time fraction c_m: SSP-RK3's, or c_1 = 0, c_m = b_1 + .. + b_{m-2} +
+// a_{m-1} for the low-storage schemes (their own a and b, not the table's
+// rounded c column)
+double stage_time(int integrator, int m) {
+  if (integrator == ADG_SSPRK3) return kSspC[m];
+  const double* a = integrator == ADG_LSERK22 ? kLs22A : kLs33A;
+  const double* b = integrator == ADG_LSERK22 ? kLs22B : kLs33B;
+  if (m == 0) return 0.0;
+  double c = a[m - 1];
+  for (int j = 0; j < m - 1; ++j) c += b[j];
+  return c;
+}
 
 adg_status check_async(const adg_config& c, const adg_async& a) {
   (void)c;
@@ -120,7 +138,7 @@ Async make_async(const adg_ctx_s* c, int stage) {
   A.n = c->n;
   A.n_rel = c->n - c->hist_start;
   A.stage = stage;
-  A.c_m = kSspC[stage];
+  A.c_m = stage_time(c->cfg.integrator, stage);
   A.tol = c->as.learned_tol;
   A.slot_n = c->R > 0 ? (int)(c->n % c->R) : 0;
   unsigned mod = 1;
@@ -204,8 +222,27 @@ adg_status adg::prof_end(adg_ctx_s* c) {
   } while (0)
 
 static adg_status run_stage(adg_ctx_s* c, int m, double dt, bool learned_collect, long long pair_base) {
+  // registers per stage. SSP-RK3: inputs u_n, u_a, u_b; outputs u_a, u_b,
+  // u_n. LSERK (w the accumulator, r the stage input; no stage writes the
+  // register its neighbours read):
+  //   (2,2): r1 = w0 = u_n -> w1 u_a, r2 u_b;  r2 = u_b, w1 = u_a -> w2 u_n
+  //   (3,3): as (2,2) at m = 0; r2 = u_b, w1 = u_a -> w2 u_n, r3 u_a (in
+  //          place over w1); r3 = u_a, w2 = u_n -> w3 u_n (in place)
+  const int ig = c->cfg.integrator;
   double* in[3] = {c->u_n, c->u_a, c->u_b};
   double* out[3] = {c->u_a, c->u_b, c->u_n};
+  double* wreg = c->u_n;  // the operand read as u_n by the combine
+  double* out2 = nullptr;
+  if (ig != ADG_SSPRK3) {
+    double* lin[3] = {c->u_n, c->u_b, c->u_a};
+    double* lw[3] = {c->u_n, c->u_a, c->u_n};
+    double* lout[3] = {c->u_a, c->u_n, c->u_n};
+    double* lout2[3] = {c->u_b, ig == ADG_LSERK33 ? c->u_a : nullptr, nullptr};
+    in[m] = lin[m];
+    wreg = lw[m];
+    out[m] = lout[m];
+    out2 = lout2[m];
+  }
   Async A = make_async(c, m);
   double* ghost = scratch_d(c, c->ghost_off);
   // stale and AT traces are built inside the stage kernel from the ring; the
@@ -224,9 +261,15 @@ static adg_status run_stage(adg_ctx_s* c, int m, double dt, bool learned_collect
       src = kSrcRing;
     }
   }
-  Stage S{kSspA[m], kSspB[m], dt};
+  Stage S{kSspA[m % 3], kSspB[m % 3], dt, 0, 0.0, 0.0, nullptr};
+  if (ig != ADG_SSPRK3) {
+    S.lserk = 1;
+    S.bw = ig == ADG_LSERK22 ? kLs22B[m] : kLs33B[m];
+    S.ar = ig == ADG_LSERK22 ? kLs22A[m] : kLs33A[m];
+    S.out2 = out2;
+  }
   PROF_TRY(prof_begin(c, ADG_KERNEL_RHS));
-  HIP_TRY(launch_rhs_stage(c->D, c->p, c->cfg.precision, c->mesh, A, S, in[m], c->u_n, out[m], src, c->ring,
+  HIP_TRY(launch_rhs_stage(c->D, c->p, c->cfg.precision, c->mesh, A, S, in[m], wreg, out[m], src, c->ring,
                            ghost, c->d_tab64, c->d_tab32, c->stream));
   PROF_TRY(prof_end(c));
   return ADG_OK;
@@ -239,7 +282,7 @@ adg_status adg::adg_step_impl(adg_ctx c, int64_t n_steps, double dt, bool collec
   if (c->as.ghost != 0 && c->mesh.nfs > 0 && c->R > 0 && !c->ring) return fail(ADG_ERR_UNBOUND, "ring not bound");
   const int ce = c->cfg.check_every;
   for (int64_t it = 0; it < n_steps; ++it) {
-    for (int m = 0; m < 3; ++m) {
+    for (int m = 0; m < n_stages(c->cfg.integrator); ++m) {
       // collection writes one pair slot per PE-boundary face node and stage
       const long long per = c->mesh.nfs * (long long)c->Fn;
       const bool col = collect && per > 0 && c->mlp.n_pairs + per <= c->mlp.max_pairs;
@@ -273,7 +316,8 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
   if (c.n_q != 0 && c.n_q != c.degree + 2) return fail(ADG_ERR_INVALID, "n_q must be 0 or degree+2");
   if (!(c.gamma > 1.0)) return fail(ADG_ERR_INVALID, "gamma must be > 1");
   if (c.flux != ADG_FLUX_LLF && c.flux != ADG_FLUX_RUSANOV) return fail(ADG_ERR_INVALID, "unknown flux");
-  if (c.integrator != ADG_SSPRK3) return fail(ADG_ERR_INVALID, "only ADG_SSPRK3 is available");
+  if (c.integrator != ADG_SSPRK3 && c.integrator != ADG_LSERK22 && c.integrator != ADG_LSERK33)
+    return fail(ADG_ERR_INVALID, "unknown integrator");
   if (c.precision != ADG_FP64 && c.precision != ADG_FP32_CONTRACT) return fail(ADG_ERR_INVALID, "unknown precision");
   if (c.check_every < 0) return fail(ADG_ERR_INVALID, "check_every must be >= 0");
   for (int k = 0; k < c.dim; ++k) {

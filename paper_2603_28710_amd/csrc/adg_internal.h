@@ -129,7 +129,14 @@ struct Prm {
 };
 
 struct Stage {
-  double a, b, dt;  // out = a u_n + b (u_in + dt k)
+  double a, b, dt;  // SSP-RK3 (Shu-Osher): out = a u_n + b (u_in + dt k)
+  // LSERK (eq. lserk-dg), when lserk != 0: u_n holds the accumulator w;
+  // out = w + dt bw k (the new accumulator) and, unless out2 is null,
+  // out2 = w + dt ar k (the next stage's input). out2 may be u_n itself:
+  // each element reads its own w before writing.
+  int lserk;
+  double bw, ar;
+  double* out2;
 };
 
 // ---- device helpers shared by several kernels -------------------------------

@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kNT3) void rhs_stage_kernel(Mesh M, Async A, Stage 
       const double x = gin[i];
       sU[i] = (T)x;
       if (sizeof(T) == 4) ur[k] = x;
-      if (S.a != 0.0) un[k] = gn[i];
+      if (S.a != 0.0 || S.lserk) un[k] = gn[i];
     }
   }
   __syncthreads();
@@ -494,15 +494,21 @@ __global__ __launch_bounds__(kNT3) void rhs_stage_kernel(Mesh M, Async A, Stage 
     __syncthreads();
   }
 
-  // ---- SSP-RK3 combine in FP64
+  // ---- the stage combine in FP64
   double* gout = out + e0 * Dm::SZP;
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
     const int i = tid + k * kNT3;
     if (i < ne * Dm::SZP) {
-      const double ui = sizeof(T) == 8 ? (double)sU[i] : ur[k];
-      const double y = ui + S.dt * (double)sR[i];
-      gout[i] = S.a == 0.0 ? S.b * y : S.a * un[k] + S.b * y;
+      if (S.lserk) {
+        // LSERK: u_n holds the accumulator w (read at the start)
+        gout[i] = un[k] + S.dt * S.bw * (double)sR[i];
+        if (S.out2) S.out2[e0 * Dm::SZP + i] = un[k] + S.dt * S.ar * (double)sR[i];
+      } else {
+        const double ui = sizeof(T) == 8 ? (double)sU[i] : ur[k];
+        const double y = ui + S.dt * (double)sR[i];
+        gout[i] = S.a == 0.0 ? S.b * y : S.a * un[k] + S.b * y;
+      }
     }
   }
 }

@@ -353,8 +353,20 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
     }
   }
 
-  // ---- SSP-RK3 combine in FP64
-  if (valid) {
+  // ---- the stage combine in FP64
+  if (valid && S.lserk) {
+    // LSERK: u_n holds the accumulator w (read before either write)
+    double wv[Pd];
+    load_col<P>(u_n + col, wv);
+    double* o = out + col;
+#pragma unroll
+    for (int i = 0; i < Pd; ++i) o[i] = wv[i] + S.dt * S.bw * (double)k[i];
+    if (S.out2) {
+      double* o2 = S.out2 + col;
+#pragma unroll
+      for (int i = 0; i < Pd; ++i) o2[i] = wv[i] + S.dt * S.ar * (double)k[i];
+    }
+  } else if (valid) {
     double* o = out + col;
     if (S.a == 0.0) {
 #pragma unroll

@@ -380,8 +380,33 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
   face_pass(std::integral_constant<int, 4>{});
   face_pass(std::integral_constant<int, 5>{});
 
-  // ---- SSP-RK3 combine in FP64, through LDS (u_n may be the output)
+  // ---- the stage combine in FP64, through LDS (u_n may be the output)
   __syncthreads();
+  if (S.lserk) {
+    // LSERK: u_n holds the accumulator w; the new w to out, the next
+    // stage input (if any) to out2
+    wave_copy_in<NE * V * Pd>(sD, u_n + e0 * V * Pd, ne * V * Pd);
+    __syncthreads();
+    double wv[Pd];
+#pragma unroll
+    for (int i = 0; i < Pd; ++i) wv[i] = valid ? sD[(le * V + v) * Pd + i] : 0.0;
+    if (valid) {
+#pragma unroll
+      for (int i = 0; i < Pd; ++i) sD[(le * V + v) * Pd + i] = wv[i] + S.dt * S.bw * (double)k[i];
+    }
+    __syncthreads();
+    wave_copy_out<NE * V * Pd>(out + e0 * V * Pd, sD, ne * V * Pd);
+    if (S.out2) {
+      __syncthreads();
+      if (valid) {
+#pragma unroll
+        for (int i = 0; i < Pd; ++i) sD[(le * V + v) * Pd + i] = wv[i] + S.dt * S.ar * (double)k[i];
+      }
+      __syncthreads();
+      wave_copy_out<NE * V * Pd>(S.out2 + e0 * V * Pd, sD, ne * V * Pd);
+    }
+    return;
+  }
   if (S.a != 0.0) wave_copy_in<NE * V * Pd>(sD, u_n + e0 * V * Pd, ne * V * Pd);
   __syncthreads();
   if (valid) {

@@ -488,7 +488,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
 #pragma unroll
       for (int i = 0; i < 2 * P; ++i) {
         const int n = iz * 2 * P + i;
-        o[i] = S.a == 0.0 ? S.b * (ui[i] + S.dt * (double)k[n]) : S.a * un[i] + S.b * (ui[i] + S.dt * (double)k[n]);
+        if (S.lserk) {
+          // LSERK: u_n holds the accumulator w (read before either write)
+          const double w = un[i];
+          o[i] = w + S.dt * S.bw * (double)k[n];
+          if (S.out2) S.out2[col + iz * P * P + 2 * h * P + i] = w + S.dt * S.ar * (double)k[n];
+        } else {
+          o[i] = S.a == 0.0 ? S.b * (ui[i] + S.dt * (double)k[n])
+                            : S.a * un[i] + S.b * (ui[i] + S.dt * (double)k[n]);
+        }
       }
     }
   }

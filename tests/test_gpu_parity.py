@@ -333,3 +333,44 @@ def test_fp32_contraction_within_1e6_of_fp64(oracle_mod, S):
             f"fp32 vs fp64 {r3264:.2e}")
         assert r64 <= TOL
         assert r32 <= 1e-6 and r3264 <= 1e-6
+
+
+# --------------------------------------------------------------- LSERK (Sec. 2.3)
+
+@pytest.mark.parametrize("dim,p,integ,ghost,kind,L,levels,precision", [
+    (2, 3, 1, 0, 0, 0, 3, 0),
+    (2, 3, 2, 0, 0, 0, 3, 0),
+    (2, 3, 2, 2, 1, 3, 3, 0),
+    (2, 3, 1, 1, 0, 2, 1, 0),
+    (2, 3, 2, 5, 2, 3, 3, 0),
+    (2, 4, 2, 2, 1, 2, 3, 1),   # FP32 contractions: within 1e-6
+    (3, 2, 2, 2, 1, 2, 3, 0),
+    (3, 3, 2, 2, 0, 2, 3, 0),
+    (3, 4, 1, 2, 1, 2, 3, 0),
+])
+def test_lserk_against_oracle(oracle_mod, S, dim, p, integ, ghost, kind, L, levels, precision):
+    # the two-register schemes move the state through all three registers
+    # (the second LSERK(3,3) stage writes its next input over the accumulator
+    # it reads) and end every step in u_n
+    O = oracle_mod
+    say(f"case: LSERK integrator={integ} dim={dim} p={p} ghost={ghost} kind={kind} L={L} levels={levels} "
+        f"precision={precision}, 10 steps")
+    if dim == 2:
+        cfg = dict(dim=2, cells=(36, 20, 1), parts=(4, 2, 1), hi=(10, 10, 1))
+        prob = O.VORTEX
+    else:
+        n = {2: 8, 3: 8, 4: 4}[p]
+        cfg = dict(dim=3, cells=(n, n, n), parts=(2, 2, 2), hi=(1, 1, 1))
+        prob = O.DENSITY_WAVE
+    cfg.update(ghost=ghost, delay_kind=kind, L=L, levels=levels, seed=5, integrator=integ)
+    o = O.Oracle(p=p, **cfg)
+    o.init_problem(prob)
+    o.set_state(o.state() + inputs.perturbation(o.ndof, 9, 1e-3))
+    s = S(degree=p, precision=precision, **cfg)
+    s.upload(o.state())
+    dt = 0.5 * o.stable_dt(0.1)
+    o.step(10, dt)
+    s.step(10, dt)
+    r = rel_l2(s.download(), o.state(), dim, s=s)
+    say("  rel L2", r)
+    assert r <= (TOL if precision == 0 else 1e-6)
