@@ -62,6 +62,11 @@ WORKLOADS = {
         cfg=dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1)),
         asy=dict(ghost=3, delay_kind=1, L=4, levels=3, seed=0, learned_tol=1e-6), problem=1, precision=0,
         cfl=0.05, net_seed=1, reference="wave128_p2_at3_uniformL4"),
+    # the paper's low-storage LSERK(3,3) instead of SSP-RK3 (same stage kernel)
+    "vortex256_p3_at3_uniformL3_lserk33": dict(
+        cfg=dict(dim=2, degree=3, cells=(256, 256, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1),
+                 integrator=2),
+        asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=0),
     # the paper's own communication-avoiding algorithm with AT fluxes
     "vortex256_p3_fluxat3_caaL3": dict(
         cfg=dict(dim=2, degree=3, cells=(256, 256, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
@@ -70,10 +75,13 @@ WORKLOADS = {
 DEFAULT = "vortex256_p3_at3_uniformL3"
 
 
-def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, ghost, levels):
-    """Minimum HBM bytes of one fused stage launch, averaged over the 3 stages
-    of a step: the stage input read once, u^n read on stages 2 and 3, the
-    output written (8 B each per DoF: 64/3 B per DoF); at PE-boundary faces
+def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, ghost, levels, integrator=0):
+    """Minimum HBM bytes of one fused stage launch, averaged over the stages
+    of a step: for SSP-RK3 the stage input read once, u^n read on stages 2
+    and 3, the output written (8 B each per DoF: 64/3 B per DoF); for
+    LSERK(2,2) / (3,3) the input, the accumulator w (except at the first
+    stage, where it is the input) and two outputs (one at the last stage):
+    24 and 80/3 B per DoF; at PE-boundary faces
     the ring levels read (one for stale traces, `levels` for AT, the
     predictor's ghost buffer for learned traces) and, at stage 0, one level
     written (nfs_nodes_vars values per level). The flux-history modes are
@@ -82,7 +90,8 @@ def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, ghost, levels):
     ring = 0.0
     if ghost in (1, 2, 3) and nfs_nodes_vars > 0:
         ring = 8.0 * nfs_nodes_vars * ((levels if ghost == 2 else 1) + 1.0 / 3.0)
-    return ndof * 64.0 / 3.0 + ring
+    per_dof = {0: 64.0 / 3.0, 1: 24.0, 2: 80.0 / 3.0}[integrator]
+    return ndof * per_dof + ring
 
 
 def algorithmic_flops_per_element(dim, P, Q):
@@ -133,8 +142,10 @@ def cpu_baseline(w, target_s=15.0):
         threads = min(len(os.sched_getaffinity(0)), 16)
         os.environ["OMP_NUM_THREADS"] = str(threads)
     c, a = w["cfg"], w["asy"]
+    integ = c.get("integrator", 0)
     o = O.Oracle(dim=c["dim"], p=c["degree"], cells=c["cells"], parts=c["parts"], lo=c["lo"], hi=c["hi"],
-                 ghost=a["ghost"], delay_kind=a["delay_kind"], L=a["L"], levels=a["levels"], seed=a["seed"])
+                 ghost=a["ghost"], delay_kind=a["delay_kind"], L=a["L"], levels=a["levels"], seed=a["seed"],
+                 integrator=integ)
     o.init_problem(w["problem"])
     dt = o.stable_dt(w.get("cfl", 0.1))
     t0 = time.perf_counter()
@@ -144,9 +155,11 @@ def cpu_baseline(w, target_s=15.0):
     t2 = time.perf_counter()
     o.step(n, dt)
     t3 = time.perf_counter()
-    return {"value": o.ndof * 3 * n / (t3 - t2), "unit": "DOF-updates/s per RK stage", "cores": threads,
+    return {"value": o.ndof * (2 if integ == 1 else 3) * n / (t3 - t2), "unit": "DOF-updates/s per RK stage",
+            "cores": threads,
             "kind": "oracle",
-            "sample": f"full mesh, {n} SSP-RK3 steps after 1 warm-up step ({t3 - t2:.1f} s)"}
+            "sample": f"full mesh, {n} {['SSP-RK3', 'LSERK(2,2)', 'LSERK(3,3)'][integ]} steps after 1 warm-up "
+                      f"step ({t3 - t2:.1f} s)"}
 
 
 def run_steps(w, steps, warmup):
@@ -227,11 +240,12 @@ def main():
     B.adg_profile(s.h, 0)
 
     sec = t1 - t0
-    stages = 3 * args.steps
+    stages = (2 if c.get("integrator", 0) == B.ADG_LSERK22 else 3) * args.steps
     value = s.ndof * stages / sec
     nfs = B.adg_delay(s.h, s.time()[0], 0, 0)[1]
     Fn = (c["degree"] + 1) ** (c["dim"] - 1)
-    bytes_launch = algorithmic_bytes_per_launch(s.ndof, nfs * s.V * Fn, a["ghost"], a["levels"])
+    bytes_launch = algorithmic_bytes_per_launch(s.ndof, nfs * s.V * Fn, a["ghost"], a["levels"],
+                                                c.get("integrator", 0))
     avg_s = rhs_ms / max(rhs_n, 1) / 1e3
     achieved = bytes_launch / avg_s / 1e9
     P, Q = c["degree"] + 1, c["degree"] + 2
@@ -258,7 +272,8 @@ def main():
                    "ghost": ["sync", "stale", "at", "learned", "flux_stale", "flux_at"][a["ghost"]],
                    "levels": a["levels"],
                    "delay": ["fixed", "uniform", "caa"][a["delay_kind"]], "L": a["L"], "seed": a["seed"],
-                   "dofs": s.ndof, "elements": s.E, "dt": dt, "cfl": cfl},
+                   "dofs": s.ndof, "elements": s.E, "dt": dt, "cfl": cfl,
+                   "integrator": ["ssprk3", "lserk22", "lserk33"][c.get("integrator", 0)]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "rhs_stage", "avg_launch_us": avg_s * 1e6, "launches": rhs_n,

@@ -355,9 +355,15 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
 
   // ---- the stage combine in FP64
   if (valid && S.lserk) {
-    // LSERK: u_n holds the accumulator w (read before either write)
+    // LSERK: u_n holds the accumulator w (read before either write); at the
+    // first stage it is the stage input itself, already in registers
     double wv[Pd];
-    load_col<P>(u_n + col, wv);
+    if (u_n == u_in) {
+#pragma unroll
+      for (int i = 0; i < Pd; ++i) wv[i] = u[i];
+    } else {
+      load_col<P>(u_n + col, wv);
+    }
     double* o = out + col;
 #pragma unroll
     for (int i = 0; i < Pd; ++i) o[i] = wv[i] + S.dt * S.bw * (double)k[i];

@@ -77,3 +77,11 @@ def test_sq_summary_is_per_wavefront(tmp_path):
     PT.sqstats([str(p)], "x", str(out))
     line = [ln for ln in out.read_text().splitlines() if ln.startswith("SQ_INSTS_VALU")][0]
     assert float(line.split()[1]) == pytest.approx(10.0)
+
+
+def test_algorithmic_bytes_lserk():
+    # LSERK: input, accumulator (not at the first stage) and two outputs (one
+    # at the last stage): (2,2) (24 + 24) / 2, (3,3) (24 + 32 + 24) / 3 B per DoF
+    nd = 1000
+    assert bench.algorithmic_bytes_per_launch(nd, 0, 0, 3, integrator=1) == pytest.approx(nd * 24.0)
+    assert bench.algorithmic_bytes_per_launch(nd, 0, 0, 3, integrator=2) == pytest.approx(nd * 80.0 / 3.0)
