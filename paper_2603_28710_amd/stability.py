@@ -9,7 +9,9 @@ largest stable value found by bisection between lo and hi.
 
     python -m paper_2603_28710_amd.stability [--t-end 4] [--cells 64] [--degree 2]
 
-prints one JSON line per (mode, L) with the bracket [stable, unstable].
+prints one JSON line per (mode, L) with the bracket [stable, unstable]. The
+learned mode trains its network first (pairs from the same mesh and
+schedule at CFL 0.1), then runs with an accept bound of LEARNED_TOL.
 """
 import argparse
 import json
@@ -21,7 +23,28 @@ MODES = {
     "flux_stale_caa": dict(ghost=4, delay_kind=2),
     "flux_at_caa": dict(ghost=5, delay_kind=2),
     "at_uniform": dict(ghost=2, delay_kind=1),
+    # the learned predictor over AT, trained first on the same mesh and
+    # schedule (see train_predictor); its accept bound is LEARNED_TOL
+    "learned_caa": dict(ghost=3, delay_kind=2),
 }
+LEARNED_TOL = 1e-4
+
+
+def train_predictor(make, cfl, steps=400, every=40, epochs=8):
+    """network weights trained on pairs the solver built by make() collects
+    at CFL cfl: `every` steps, then 4 collected steps, up to `steps` steps"""
+    s = make()
+    dt = s.stable_dt(cfl)
+    s.predictor_bind(4_000_000)
+    done = 0
+    while done + every + 4 <= steps:
+        s.step(every, dt)
+        s.predictor_collect(4, dt)
+        done += every + 4
+    s.predictor_train(epochs=epochs, batch=1024, lr=1e-3, seed=1)
+    w = s.predictor_get()
+    s.close()
+    return w
 
 
 def runs_stably(make, sigma, t_end):
@@ -71,10 +94,13 @@ def main():
 
     n = a.cells
 
-    def maker(mode, L):
+    def maker(mode, L, weights=None):
         def make():
+            extra = dict(learned_tol=LEARNED_TOL) if MODES[mode]["ghost"] == 3 else {}
             s = Solver(dim=2, degree=a.degree, cells=(n, n, 1), parts=(a.parts, a.parts, 1), lo=(0, 0, 0),
-                       hi=(10, 10, 1), check_every=a.check, levels=a.levels, L=L, seed=0, **MODES[mode])
+                       hi=(10, 10, 1), check_every=a.check, levels=a.levels, L=L, seed=0, **MODES[mode], **extra)
+            if weights is not None:
+                s.predictor_set(weights)
             s.init_problem(0)
             return s
         return make
@@ -85,7 +111,8 @@ def main():
         for L in a.L:
             if L == 0 and mode in ("stale_caa", "flux_stale_caa"):
                 continue
-            lo, hi = max_stable_cfl(maker(mode, L), a.t_end)
+            w = train_predictor(maker(mode, L), 0.1) if MODES[mode]["ghost"] == 3 else None
+            lo, hi = max_stable_cfl(maker(mode, L, w), a.t_end)
             print(json.dumps({"mode": mode, "L": L, "stable": lo, "unstable": hi, "cells": n,
                               "degree": a.degree, "t_end": a.t_end}), flush=True)
 
