@@ -23,7 +23,10 @@
  *     delay of the naive RK coupling (Sec. 3.2, eq. at-flux-constraints,
  *     Table at-flux-coeffs).
  *   - the two-register LSERK(2,2) and LSERK(3,3) of Sec. 2.3 (eq. lserk-dg,
- *     Table lserk-scheme), besides the default SSP-RK3.
+ *     Table lserk-scheme), besides the default SSP-RK3;
+ *   - the Dirichlet box of the vortex test (Sec. 5.1): the exact solution at
+ *     the stage time is the exterior state of every boundary face, besides
+ *     the default periodic box.
  * Readings where the paper is silent (time integrator SSP-RK3, what is delayed,
  * delay draws, warm-up, learned correction) are the ones listed in the design
  * notes; each is marked "reading" below.
@@ -266,6 +269,7 @@ typedef struct {
   int R, Qh;
   int64_t n;
   double t;
+  double dt; /* the running step's length (stage times of the boundary data) */
   /* learned predictor */
   int has_mlp, nin, nh, nout;
   float* mlp;
@@ -323,6 +327,15 @@ static int64_t neighbour(const orc_solver* s, int64_t e, int f) {
   return elem_of(s, ijk[0], ijk[1], ijk[2]);
 }
 
+/* does face f of element e lie on the boundary of a Dirichlet box? */
+static int on_boundary(const orc_solver* s, int64_t e, int f) {
+  if (!s->c.bc) return 0;
+  int64_t ijk[3];
+  elem_ijk(s, e, ijk);
+  int a = f / 2;
+  return (f & 1) ? ijk[a] == s->nc[a] - 1 : ijk[a] == 0;
+}
+
 int64_t orc_subdomain(void* vs, int64_t e) {
   orc_solver* s = (orc_solver*)vs;
   int64_t ijk[3], sid = 0, mul = 1;
@@ -348,7 +361,8 @@ void* orc_create(const orc_cfg* cfg) {
   orc_solver* s = (orc_solver*)xmalloc(sizeof(orc_solver));
   s->c = *cfg;
   int D = cfg->dim;
-  if (D < 2 || D > 3 || cfg->p < 1 || cfg->p > 5 || cfg->integrator < 0 || cfg->integrator > 2) {
+  if (D < 2 || D > 3 || cfg->p < 1 || cfg->p > 5 || cfg->integrator < 0 || cfg->integrator > 2 ||
+      cfg->bc < 0 || cfg->bc > 1 || (cfg->bc && (cfg->bc_problem < 0 || cfg->bc_problem > 2 || cfg->ghost == 3))) {
     free(s);
     return NULL;
   }
@@ -534,7 +548,7 @@ int64_t orc_nface_sides(void* vs) {
   int64_t c = 0;
   for (int64_t e = 0; e < s->E; ++e)
     for (int f = 0; f < s->nf; ++f)
-      if (orc_subdomain(s, e) != orc_subdomain(s, neighbour(s, e, f))) ++c;
+      if (!on_boundary(s, e, f) && orc_subdomain(s, e) != orc_subdomain(s, neighbour(s, e, f))) ++c;
   return c;
 }
 
@@ -813,6 +827,39 @@ static void ghost_face(orc_solver* s, const double* uin, int64_t e, int f, int s
 /* right-hand side (Sec. 2.1, eq. weakform-dealii, weakform-compact-dealii) */
 /* ------------------------------------------------------------------------ */
 
+static void exact_state(const orc_solver* s, int problem, const double* prm, const double* x, double t,
+                        double* w);
+
+/* exterior state of the boundary face f of element e at time t, at the face
+ * Gauss points g[fq][v]: the exact solution that prescribes the boundary data
+ * (Sec. 5.1) taken at the face's GLL nodes and interpolated to the Gauss
+ * points the way a neighbour's trace is (reading: the data enter as a trace) */
+static void boundary_face(const orc_solver* s, int64_t e, int f, double t, double* g) {
+  int D = s->D, V = s->V, P = s->P, Fn = s->Fn, Fq = s->Fq, a = f / 2;
+  int64_t ijk[3];
+  elem_ijk(s, e, ijk);
+  double wn[64 * MAXV];
+  for (int j = 0; j < Fn; ++j) {
+    double x[3] = {0.0, 0.0, 0.0};
+    int r = j;
+    for (int k = 0; k < D; ++k) {
+      if (k == a) {
+        x[k] = (f & 1) ? s->c.hi[k] : s->c.lo[k];
+      } else {
+        x[k] = s->c.lo[k] + s->h[k] * (ijk[k] + 0.5 * (s->xl[r % P] + 1.0));
+        r /= P;
+      }
+    }
+    exact_state(s, s->c.bc_problem, s->c.bc_prm_set ? s->c.bc_prm : NULL, x, t, wn + j * V);
+  }
+  for (int fq = 0; fq < Fq; ++fq)
+    for (int v = 0; v < V; ++v) {
+      double acc = 0.0;
+      for (int j = 0; j < Fn; ++j) acc += s->lagF[fq * Fn + j] * wn[j * V + v];
+      g[fq * V + v] = acc;
+    }
+}
+
 static int is_pe_face(orc_solver* s, int64_t e, int64_t nb) {
   return orc_subdomain(s, e) != orc_subdomain(s, nb);
 }
@@ -824,6 +871,7 @@ static int is_pe_face(orc_solver* s, int64_t e, int64_t nb) {
 static void face_fluxes(orc_solver* s, const double* uin, int stage, int use_ghosts) {
   int D = s->D, V = s->V, Fq = s->Fq, nf = s->nf;
   int64_t E = s->E;
+  const double t_stage = s->t + stage_time(s, stage) * s->dt;
 #pragma omp parallel for schedule(static)
   for (int64_t e = 0; e < E; ++e) {
     double wm[MAXV], wp[MAXV], G[MAXV];
@@ -833,6 +881,19 @@ static void face_fluxes(orc_solver* s, const double* uin, int stage, int use_gho
       int64_t e2 = neighbour(s, e, fR);
       double* FR = s->Fnum + ((size_t)e * nf + fR) * Fq * V;
       double* FL = s->Fnum + ((size_t)e2 * nf + fL) * Fq * V;
+      if (on_boundary(s, e, fR)) {
+        /* Dirichlet box: e's +a face and e2's -a face are boundary faces; each
+         * takes the flux with the exact data as the exterior state */
+        boundary_face(s, e, fR, t_stage, gA);
+        boundary_face(s, e2, fL, t_stage, gB);
+        for (int fq = 0; fq < Fq; ++fq) {
+          trace_at(s, uin, e, fR, fq, wm);
+          trace_at(s, uin, e2, fL, fq, wp);
+          num_flux(s, wm, gA + fq * V, a, 1.0, FR + fq * V);
+          num_flux(s, wp, gB + fq * V, a, -1.0, FL + fq * V);
+        }
+        continue;
+      }
       int pe = use_ghosts && s->c.ghost != 0 && is_pe_face(s, e, e2);
       if (pe && s->c.ghost >= 4) {
         /* Alg. caa-std / caa-at: at the first stage of a communicating step
@@ -958,6 +1019,15 @@ void orc_stage_elements(void* vs, int stage, double dt, const double* u_in, cons
         int f = 2 * a + side;
         int64_t nb = neighbour(s, e, f);
         double* F = s->Fnum + ((size_t)e * nf + f) * Fq * V;
+        if (on_boundary(s, e, f)) {
+          double gb[64 * MAXV];
+          boundary_face(s, e, f, s->t + stage_time(s, stage) * dt, gb);
+          for (int fq = 0; fq < Fq; ++fq) {
+            trace_at(s, u_in, e, f, fq, wm);
+            num_flux(s, wm, gb + fq * V, a, side ? 1.0 : -1.0, F + fq * V);
+          }
+          continue;
+        }
         for (int fq = 0; fq < Fq; ++fq) {
           /* canonical orientation: left element first, then sign */
           if (side == 1) {
@@ -1002,6 +1072,7 @@ static int check_state(const orc_solver* s) {
 int orc_step(void* vs, int64_t nsteps, double dt) {
   orc_solver* s = (orc_solver*)vs;
   size_t nd = (size_t)orc_ndof(s);
+  s->dt = dt;
   for (int64_t it = 0; it < nsteps; ++it) {
     if (s->hist) memcpy(s->hist + (size_t)(s->n % s->R) * nd, s->u, sizeof(double) * nd);
     if (s->c.integrator == 0) {
@@ -1053,8 +1124,10 @@ static void exact_state(const orc_solver* s, int problem, const double* prm, con
     double mx = prm ? prm[3] : 1.0, my = prm ? prm[4] : 1.0;
     double Lx = s->c.hi[0] - s->c.lo[0], Ly = s->c.hi[1] - s->c.lo[1];
     double dx = x[0] - x0 - mx * t, dy = x[1] - y0 - my * t;
-    dx -= Lx * floor((dx + 0.5 * Lx) / Lx);
-    dy -= Ly * floor((dy + 0.5 * Ly) / Ly);
+    if (!s->c.bc) { /* periodic box: the nearest periodic image */
+      dx -= Lx * floor((dx + 0.5 * Lx) / Lx);
+      dy -= Ly * floor((dy + 0.5 * Ly) / Ly);
+    }
     double r2 = dx * dx + dy * dy;
     double ex = exp(1.0 - r2);
     double u = mx - beta * ex * dy / (2.0 * ORC_PI);

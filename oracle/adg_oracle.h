@@ -27,7 +27,7 @@ typedef struct orc_cfg {
   int32_t nq;           /* Gauss points per direction (0 -> p+2) */
   int32_t cells[3];     /* elements per direction */
   int32_t parts[3];     /* virtual subdomains per direction (block split) */
-  double lo[3], hi[3];  /* periodic box */
+  double lo[3], hi[3];  /* the box */
   double gamma;         /* ratio of specific heats */
   int32_t flux;         /* 0: local Lax-Friedrichs as printed (lambda with 1/2), 1: Rusanov */
   int32_t ghost;        /* 0 SYNC, 1 STALE (standard flux on old traces), 2 AT, 3 LEARNED,
@@ -41,6 +41,13 @@ typedef struct orc_cfg {
   double learned_tol;   /* accept bound on the learned correction (physical units) */
   int32_t integrator;   /* 0 SSP-RK3 (Shu-Osher), 1 LSERK(2,2), 2 LSERK(3,3): the two-register
                            low-storage schemes of eq. lserk-dg with Table lserk-scheme */
+  int32_t bc;           /* 0 periodic box; 1 Dirichlet on every side of the box (Sec. 5.1
+                           vortex): the exterior state of a boundary face is the exact
+                           solution of bc_problem at the stage time, and the exact
+                           solutions are not wrapped periodically */
+  int32_t bc_problem;   /* ORC_* problem that supplies the boundary data */
+  int32_t bc_prm_set;   /* 0: the problem's default parameters; 1: bc_prm */
+  double bc_prm[5];     /* parameters, as for orc_init_problem */
 } orc_cfg;
 
 enum { ORC_VORTEX = 0, ORC_DENSITY_WAVE = 1, ORC_CONSTANT = 2 };

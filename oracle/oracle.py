@@ -15,6 +15,7 @@ FIXED, UNIFORM, CAA = 0, 1, 2
 VORTEX, DENSITY_WAVE, CONSTANT = 0, 1, 2
 LLF, RUSANOV = 0, 1
 SSPRK3, LSERK22, LSERK33 = 0, 1, 2
+PERIODIC, DIRICHLET = 0, 1
 
 
 class OrcCfg(C.Structure):
@@ -25,6 +26,8 @@ class OrcCfg(C.Structure):
         ("gamma", C.c_double), ("flux", C.c_int32), ("ghost", C.c_int32),
         ("delay_kind", C.c_int32), ("L", C.c_int32), ("levels", C.c_int32),
         ("seed", C.c_uint64), ("learned_tol", C.c_double), ("integrator", C.c_int32),
+        ("bc", C.c_int32), ("bc_problem", C.c_int32), ("bc_prm_set", C.c_int32),
+        ("bc_prm", C.c_double * 5),
     ]
 
 
@@ -125,7 +128,7 @@ class Oracle:
 
     def __init__(self, dim=2, p=2, nq=0, cells=(16, 16, 1), parts=(1, 1, 1), lo=(0, 0, 0),
                  hi=(10, 10, 1), gamma=1.4, flux=LLF, ghost=SYNC, delay_kind=FIXED, L=0, levels=3,
-                 seed=0, learned_tol=1e-6, integrator=0):
+                 seed=0, learned_tol=1e-6, integrator=0, bc=0, bc_problem=0, bc_params=None):
         c = OrcCfg()
         c.dim, c.p, c.nq = dim, p, nq
         for k in range(3):
@@ -136,6 +139,13 @@ class Oracle:
         c.gamma, c.flux, c.ghost, c.delay_kind = gamma, flux, ghost, delay_kind
         c.L, c.levels, c.seed, c.learned_tol = L, levels, seed, learned_tol
         c.integrator = integrator
+        # bc = 1: Dirichlet box, the exterior state of each boundary face is
+        # the exact solution of bc_problem (bc_params, or its defaults)
+        c.bc, c.bc_problem = bc, bc_problem
+        c.bc_prm_set = 0 if bc_params is None else 1
+        if bc_params is not None:
+            for i in range(5):
+                c.bc_prm[i] = float(bc_params[i])
         self.cfg = c
         self.dim, self.p = dim, p
         self.P = p + 1

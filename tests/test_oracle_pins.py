@@ -541,3 +541,125 @@ def _sweep_integ(O, integ, ns, ghost=0, kind=0, L=0, cfl=0.1, tend=0.2, parts=(1
         assert o.step(nst, tend / nst) == 0
         errs.append(o.error_norms(O.DENSITY_WAVE, tend))
     return np.array(errs)
+
+
+# ------------------------------------------ Dirichlet box (Sec. 5.1 vortex)
+
+PAPER_VORTEX = (5.0, 0.0, 5.0, 1.0, 0.0)  # x0, y0, beta, mean flow (1, 0)
+
+
+@pytest.mark.parametrize("name,ghost,kind,L", [m for m in MODES if m[1] != 3])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_dirichlet_free_stream_preserved(oracle_mod, name, ghost, kind, L, dim):
+    # a boundary face whose exterior data equal the interior constant adds
+    # exactly the flux the missing neighbour would: a dropped boundary face or
+    # a wrong normal leaves a residual of the size of F(w).n / h
+    O = oracle_mod
+    cells = (6, 4, 4 if dim == 3 else 1)
+    parts = (3, 2, 2 if dim == 3 else 1)
+    o = O.Oracle(dim=dim, p=2, cells=cells, parts=parts, hi=(1, 2, 1), ghost=ghost, delay_kind=kind,
+                 L=L, levels=3, seed=3, bc=O.DIRICHLET, bc_problem=O.CONSTANT)
+    o.init_problem(O.CONSTANT)
+    u0 = o.state()
+    # round-off of the exterior data's interpolation, O(eps |F| / h)
+    assert np.abs(o.rhs(u0)).max() < 4e-12
+    assert o.step(8, 1e-3) == 0
+    np.testing.assert_allclose(o.state(), u0, rtol=0, atol=1e-13)
+
+
+def test_dirichlet_face_sides_exclude_the_boundary(oracle_mod):
+    # 6 x 4 cells in 2 x 2 subdomains: one interface line per axis; the
+    # periodic box adds the wrap-around lines
+    O = oracle_mod
+    per = O.Oracle(dim=2, p=1, cells=(6, 4, 1), parts=(2, 2, 1)).n_face_sides()
+    dir_ = O.Oracle(dim=2, p=1, cells=(6, 4, 1), parts=(2, 2, 1), bc=O.DIRICHLET).n_face_sides()
+    assert dir_ == 2 * 4 + 2 * 6 and per == 2 * dir_
+
+
+def test_dirichlet_vortex_is_not_wrapped(oracle_mod):
+    # at t = 4 the vortex of the paper's test sits at x = 9: on the box
+    # [0,2] x [-1,1] the exact solution is the free stream (e^(1-49) away),
+    # while a periodic image would put the core inside the box
+    O = oracle_mod
+    free = (1.0, 1.0, 0.0, 0.0, 1.0)
+    errs = {}
+    for bc in (O.DIRICHLET, O.PERIODIC):
+        o = O.Oracle(dim=2, p=2, cells=(8, 8, 1), lo=(0, -1, 0), hi=(2, 1, 1), bc=bc)
+        o.init_problem(O.CONSTANT, free)
+        errs[bc] = o.error_norms(O.VORTEX, 4.0, PAPER_VORTEX)
+    assert max(errs[O.DIRICHLET]) < 1e-13
+    assert errs[O.PERIODIC][0] > 0.1
+
+
+def _dirichlet_sweep(O, p, ns, problem, prm, lo, hi, tend, cfl=0.1, **kw):
+    errs = []
+    for n in ns:
+        o = O.Oracle(dim=2, p=p, cells=(n, n, 1), lo=lo, hi=hi, bc=O.DIRICHLET, bc_problem=problem,
+                     bc_params=prm, **kw)
+        o.init_problem(problem, prm)
+        dt = o.stable_dt(cfl)
+        nst = int(math.ceil(tend / dt))
+        assert o.step(nst, tend / nst) == 0
+        errs.append(o.error_norms(problem, tend, prm))
+    errs = np.array(errs)
+    return errs, np.log2(errs[:-1] / errs[1:])
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_dirichlet_density_wave_order_p_plus_1(oracle_mod, p):
+    # the wave enters through two sides and leaves through the other two:
+    # boundary data at wrong positions or a swapped exterior state stall the
+    # error at the boundary
+    O = oracle_mod
+    prm = (0.2, 1.0, 1.0, 0.0, 1.0)
+    errs, slopes = _dirichlet_sweep(O, p, (8, 16, 32), O.DENSITY_WAVE, prm, (0, 0, 0), (1, 1, 1), 0.2)
+    assert np.all(slopes[-1] > p + 1 - 0.2)
+
+
+def test_dirichlet_data_at_the_stage_times(oracle_mod):
+    # fixed fine space, halve dt: with the boundary data taken at each
+    # stage's time the successive differences shrink as dt^3 (observed 2^3.19);
+    # data frozen at t_n through the step give dt^1 (observed 2^1.03)
+    O = oracle_mod
+    prm = (0.2, 1.0, 1.0, 0.0, 1.0)
+    sols = []
+    for nst in (20, 40, 80):
+        o = O.Oracle(dim=2, p=4, cells=(4, 4, 1), hi=(1, 1, 1), bc=O.DIRICHLET, bc_problem=O.DENSITY_WAVE,
+                     bc_params=prm)
+        o.init_problem(O.DENSITY_WAVE, prm)
+        o.step(nst, 0.2 / nst)
+        sols.append(o.state())
+    d1 = np.linalg.norm(sols[0] - sols[1])
+    d2 = np.linalg.norm(sols[1] - sols[2])
+    assert d1 / d2 > 2 ** 2.5
+
+
+@pytest.mark.parametrize("p,slope", [(1, 1.7), (2, 2.5)])
+def test_dirichlet_paper_vortex_converges(oracle_mod, p, slope):
+    # the paper's vortex: [0,10] x [-5,5], mean flow (1,0), exact data on
+    # every side (Sec. 5.1)
+    O = oracle_mod
+    errs, slopes = _dirichlet_sweep(O, p, (8, 16, 32), O.VORTEX, PAPER_VORTEX, (0, -5, 0), (10, 5, 1), 0.5)
+    assert np.all(slopes[-1] > slope)
+
+
+def test_dirichlet_zero_delay_is_bitwise_synchronous(oracle_mod):
+    O = oracle_mod
+    base = dict(dim=2, p=2, cells=(8, 8, 1), parts=(4, 2, 1), lo=(0, -5, 0), hi=(10, 5, 1), bc=O.DIRICHLET,
+                bc_problem=O.VORTEX, bc_params=PAPER_VORTEX)
+    ref = O.Oracle(**base)
+    ref.init_problem(O.VORTEX, PAPER_VORTEX)
+    dt = ref.stable_dt(0.1)
+    ref.step(10, dt)
+    for ghost, kind, L in ((O.STALE, O.FIXED, 0), (O.AT, O.FIXED, 0), (O.FLUX_STALE, O.CAA, 1),
+                           (O.FLUX_AT, O.CAA, 0)):
+        o = O.Oracle(ghost=ghost, delay_kind=kind, L=L, levels=3, **base)
+        o.init_problem(O.VORTEX, PAPER_VORTEX)
+        o.step(10, dt)
+        np.testing.assert_array_equal(o.state(), ref.state())
+
+
+def test_dirichlet_rejects_learned_ghosts(oracle_mod):
+    O = oracle_mod
+    with pytest.raises(ValueError):
+        O.Oracle(dim=2, p=2, cells=(8, 8, 1), parts=(2, 2, 1), ghost=O.LEARNED, bc=O.DIRICHLET)
