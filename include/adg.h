@@ -20,6 +20,9 @@
  *   - Time integration: explicit SSP-RK3 in Shu-Osher form (default), or the
  *     paper's two-register LSERK(2,2) / LSERK(3,3) of Sec. 2.3 (eq. lserk-dg,
  *     Table lserk-scheme; stage times from the scheme's own a and b).
+ *   - Boundaries: a periodic box (default), or, for d = 2, the Dirichlet box of
+ *     the paper's vortex test (Sec. 5.1), whose boundary data come from the
+ *     exact solution.
  *
  * Conventions shared by every entry point
  *   - Every function returns adg_status: ADG_OK (0) or a negative code. No
@@ -91,8 +94,18 @@ typedef int32_t adg_status;
 #define ADG_DELAY_FIXED 0   /* k = L */
 #define ADG_DELAY_UNIFORM 1 /* k uniform in {0..L}, SplitMix64 draw from the seed */
 #define ADG_DELAY_CAA 2     /* Alg. caa-std (STALE, FLUX_STALE) / Alg. caa-at (AT, LEARNED, FLUX_AT) schedule */
+/* boundary of the box */
+#define ADG_BC_PERIODIC 0
+/* Dirichlet on every side (d = 2 only): a boundary face takes the numerical
+ * flux with the exact solution of the boundary problem (adg_set_boundary;
+ * adg_init_problem sets it too) as the exterior state, evaluated at the
+ * face's Gauss-Lobatto nodes at each stage's time t_n + c_m dt and
+ * interpolated to the face Gauss points like a neighbour's trace. Boundary
+ * faces are never PE faces. Exact solutions are not wrapped periodically. */
+#define ADG_BC_DIRICHLET 1
 /* analytic problems */
-#define ADG_VORTEX 0       /* isentropic vortex (Sec. 5.1), periodic; params x0,y0,beta,mean_u,mean_v */
+#define ADG_VORTEX 0       /* isentropic vortex (Sec. 5.1); params x0,y0,beta,mean_u,mean_v; in a
+                              periodic box the nearest periodic image of the centre */
 #define ADG_DENSITY_WAVE 1 /* rho = 1 + A sin(2 pi sum_k (x_k - u_k t)); params A,u1,u2,u3,p */
 #define ADG_CONSTANT 2     /* constant state; params rho,u1,u2,u3,p */
 
@@ -102,12 +115,13 @@ typedef struct adg_config {
   int32_t n_q;         /* Gauss points per direction; 0 means degree+2 (the only supported value) */
   int32_t cells[3];    /* elements per direction (cells[2] ignored in 2D) */
   int32_t parts[3];    /* virtual subdomains per direction; cells[k] % parts[k] == 0 */
-  double lo[3], hi[3]; /* periodic box */
+  double lo[3], hi[3]; /* the box */
   double gamma;        /* ratio of specific heats (> 1) */
   int32_t flux;        /* ADG_FLUX_* */
   int32_t integrator;  /* ADG_SSPRK3, ADG_LSERK22 or ADG_LSERK33 */
   int32_t precision;   /* ADG_FP64 or ADG_FP32_CONTRACT */
   int32_t check_every; /* 0: adg_step never checks the state; k>0: every k steps and at the end */
+  int32_t boundary;    /* ADG_BC_PERIODIC or ADG_BC_DIRICHLET (d = 2, not with ADG_GHOST_LEARNED) */
 } adg_config;
 
 typedef struct adg_async {
@@ -151,8 +165,14 @@ adg_status adg_download(adg_ctx ctx, double* host, size_t n);
 /* L2 projection of an analytic problem (ADG_VORTEX, ...) at t = 0 into u_n,
  * computed on the GPU. params may be NULL for the defaults (vortex
  * 5,5,5,1,1; density wave 0.2,1,1,1,1; constant 1,0.3,-0.2,0.1,1). Resets
- * n, t and the history. */
+ * n, t and the history, and makes the problem the boundary problem. */
 adg_status adg_init_problem(adg_ctx ctx, int32_t problem, const double* params);
+
+/* The analytic problem whose exact solution supplies the boundary data of an
+ * ADG_BC_DIRICHLET box (params as for adg_init_problem; NULL = defaults).
+ * Host-only, no HIP call. adg_step in a Dirichlet box returns
+ * ADG_ERR_STATE until a boundary problem is set. */
+adg_status adg_set_boundary(adg_ctx ctx, int32_t problem, const double* params);
 
 /* Change the asynchrony settings. The ring bound at adg_bind must be large
  * enough for the new depth (ADG_ERR_INVALID otherwise). The history restarts:

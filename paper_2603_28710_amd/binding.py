@@ -21,6 +21,7 @@ ADG_GHOST_SYNC, ADG_GHOST_STALE, ADG_GHOST_AT, ADG_GHOST_LEARNED = 0, 1, 2, 3
 ADG_GHOST_FLUX_STALE, ADG_GHOST_FLUX_AT = 4, 5
 ADG_DELAY_FIXED, ADG_DELAY_UNIFORM, ADG_DELAY_CAA = 0, 1, 2
 ADG_VORTEX, ADG_DENSITY_WAVE, ADG_CONSTANT = 0, 1, 2
+ADG_BC_PERIODIC, ADG_BC_DIRICHLET = 0, 1
 
 
 class adg_config(C.Structure):
@@ -28,7 +29,7 @@ class adg_config(C.Structure):
                 ("cells", C.c_int32 * 3), ("parts", C.c_int32 * 3),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("gamma", C.c_double),
                 ("flux", C.c_int32), ("integrator", C.c_int32), ("precision", C.c_int32),
-                ("check_every", C.c_int32)]
+                ("check_every", C.c_int32), ("boundary", C.c_int32)]
 
 
 class adg_async(C.Structure):
@@ -56,6 +57,7 @@ _SIGS = {
     "adg_upload": [_vp, _dp, C.c_size_t],
     "adg_download": [_vp, _dp, C.c_size_t],
     "adg_init_problem": [_vp, C.c_int32, _dp],
+    "adg_set_boundary": [_vp, C.c_int32, _dp],
     "adg_set_async": [_vp, C.POINTER(adg_async)],
     "adg_step": [_vp, C.c_int64, C.c_double],
     "adg_time": [_vp, C.POINTER(C.c_int64), _dp],
@@ -129,6 +131,10 @@ def adg_download(h, host_ptr, n):
 
 def adg_init_problem(h, problem, params_ptr=None):
     _call("adg_init_problem", h, problem, C.cast(params_ptr, _dp) if params_ptr else None)
+
+
+def adg_set_boundary(h, problem, params_ptr=None):
+    _call("adg_set_boundary", h, problem, C.cast(params_ptr, _dp) if params_ptr else None)
 
 
 def adg_set_async(h, asy):
@@ -276,7 +282,8 @@ def adg_last_error():
 
 
 def make_config(dim=2, degree=2, cells=(16, 16, 1), parts=(1, 1, 1), lo=(0, 0, 0), hi=(10, 10, 1),
-                gamma=1.4, flux=ADG_FLUX_LLF, precision=ADG_FP64, check_every=0, n_q=0, integrator=ADG_SSPRK3):
+                gamma=1.4, flux=ADG_FLUX_LLF, precision=ADG_FP64, check_every=0, n_q=0, integrator=ADG_SSPRK3,
+                boundary=ADG_BC_PERIODIC):
     c = adg_config()
     c.dim, c.degree, c.n_q = dim, degree, n_q
     for k in range(3):
@@ -285,6 +292,7 @@ def make_config(dim=2, degree=2, cells=(16, 16, 1), parts=(1, 1, 1), lo=(0, 0, 0
         c.lo[k] = float(lo[k]) if k < len(lo) else 0.0
         c.hi[k] = float(hi[k]) if k < len(hi) else 1.0
     c.gamma, c.flux, c.integrator, c.precision, c.check_every = gamma, flux, integrator, precision, check_every
+    c.boundary = boundary
     return c
 
 

@@ -1,6 +1,7 @@
 // adg_api.cpp — host runtime behind include/adg.h: configuration checks, the
 // 1D tables (Gauss-Lobatto nodes, Gauss rule, interpolation, collocation
-// derivative, inverse mass), the periodic box and its virtual subdomains, the
+// derivative, inverse mass), the box (periodic or Dirichlet) and its virtual
+// subdomains, the
 // SSP-RK3 stage loop with its ghost/ring launches, diagnostics and
 // checkpoints. All GPU work goes to the context's stream.
 #include <hip/hip_runtime.h>
@@ -92,8 +93,9 @@ double stage_time(int integrator, int m) {
 }
 
 adg_status check_async(const adg_config& c, const adg_async& a) {
-  (void)c;
   if (a.ghost < 0 || a.ghost > 5) return fail(ADG_ERR_INVALID, "async.ghost must be 0..5");
+  if (a.ghost == ADG_GHOST_LEARNED && c.boundary == ADG_BC_DIRICHLET)
+    return fail(ADG_ERR_INVALID, "the learned ghost predictor needs a periodic box");
   if (a.ghost >= ADG_GHOST_FLUX_STALE && a.delay_kind != ADG_DELAY_CAA)
     return fail(ADG_ERR_INVALID, "the flux-history modes need the CAA delay schedule");
   if (a.delay_kind < 0 || a.delay_kind > 2) return fail(ADG_ERR_INVALID, "async.delay_kind must be 0..2");
@@ -150,12 +152,18 @@ Async make_async(const adg_ctx_s* c, int stage) {
 
 double* scratch_d(adg_ctx_s* c, size_t off) { return reinterpret_cast<double*>(c->scratch + off); }
 
-adg_status run_norms(adg_ctx_s* c, int what, int problem, const double* params, const double* u, const double* ref,
-                     int ncomp, int op, double* host_out) {
+// an analytic problem's parameters: the caller's, or the defaults
+Prm problem_params(int problem, const double* params) {
   Prm prm{};
   const double def[3][5] = {{5, 5, 5, 1, 1}, {0.2, 1, 1, 1, 1}, {1, 0.3, -0.2, 0.1, 1}};
   const int pi = (problem >= 0 && problem <= 2) ? problem : 2;
   for (int i = 0; i < 5; ++i) prm.v[i] = params ? params[i] : def[pi][i];
+  return prm;
+}
+
+adg_status run_norms(adg_ctx_s* c, int what, int problem, const double* params, const double* u, const double* ref,
+                     int ncomp, int op, double* host_out) {
+  const Prm prm = problem_params(problem, params);
   const int nblk = norms_blocks(c->mesh.E);
   double* partial = scratch_d(c, c->partial_off);
   double* red = scratch_d(c, c->red_off);
@@ -261,7 +269,14 @@ static adg_status run_stage(adg_ctx_s* c, int m, double dt, bool learned_collect
       src = kSrcRing;
     }
   }
-  Stage S{kSspA[m % 3], kSspB[m % 3], dt, 0, 0.0, 0.0, nullptr};
+  Stage S{kSspA[m % 3], kSspB[m % 3], dt, 0, 0.0, 0.0, nullptr, nullptr};
+  if (c->mesh.bc) {
+    // the boundary data at this stage's time
+    double* bnd = scratch_d(c, c->bnd_off);
+    HIP_TRY(launch_bnd_fill(c->p, c->mesh, c->bc_problem, c->bc_prm, c->t + A.c_m * dt, c->d_tab64, bnd,
+                            c->stream));
+    S.bnd = bnd;
+  }
   if (ig != ADG_SSPRK3) {
     S.lserk = 1;
     S.bw = ig == ADG_LSERK22 ? kLs22B[m] : kLs33B[m];
@@ -280,6 +295,8 @@ adg_status adg::adg_step_impl(adg_ctx c, int64_t n_steps, double dt, bool collec
   if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
   if (n_steps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return fail(ADG_ERR_INVALID, "need n_steps >= 0, dt > 0");
   if (c->as.ghost != 0 && c->mesh.nfs > 0 && c->R > 0 && !c->ring) return fail(ADG_ERR_UNBOUND, "ring not bound");
+  if (c->mesh.bc && c->bc_problem < 0)
+    return fail(ADG_ERR_STATE, "a Dirichlet box needs its boundary problem (adg_set_boundary or adg_init_problem)");
   const int ce = c->cfg.check_every;
   for (int64_t it = 0; it < n_steps; ++it) {
     for (int m = 0; m < n_stages(c->cfg.integrator); ++m) {
@@ -320,6 +337,9 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
     return fail(ADG_ERR_INVALID, "unknown integrator");
   if (c.precision != ADG_FP64 && c.precision != ADG_FP32_CONTRACT) return fail(ADG_ERR_INVALID, "unknown precision");
   if (c.check_every < 0) return fail(ADG_ERR_INVALID, "check_every must be >= 0");
+  if (c.boundary != ADG_BC_PERIODIC && c.boundary != ADG_BC_DIRICHLET) return fail(ADG_ERR_INVALID, "unknown boundary");
+  if (c.boundary == ADG_BC_DIRICHLET && c.dim != 2)
+    return fail(ADG_ERR_INVALID, "Dirichlet boundaries are implemented for d = 2");
   for (int k = 0; k < c.dim; ++k) {
     if (c.cells[k] < 1 || c.parts[k] < 1) return fail(ADG_ERR_INVALID, "cells and parts must be >= 1");
     if (c.cells[k] % c.parts[k]) return fail(ADG_ERR_INVALID, "cells must be divisible by parts");
@@ -366,6 +386,12 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
   }
   M.gamma = c.gamma;
   M.flux = c.flux;
+  M.bc = c.boundary == ADG_BC_DIRICHLET ? 1 : 0;
+  M.bnd_off[0] = 0;
+  M.bnd_off[1] = M.nc[1];
+  M.bnd_off[2] = 2 * M.nc[1];
+  M.bnd_off[3] = 2 * M.nc[1] + M.nc[0];
+  M.nbf = M.bc ? 2 * (M.nc[0] + M.nc[1]) : 0;
   for (int k = 0; k < 2; ++k) M.dnc[k] = make_fastdiv(M.nc[k]);
   for (int k = 0; k < 3; ++k) M.dm[k] = make_fastdiv(M.m[k]);
   for (int k = 0; k < 2; ++k) M.dparts[k] = make_fastdiv(M.parts[k]);
@@ -410,6 +436,8 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
   s = align256(s + 16 * sizeof(double));
   x->mlp_off = s;
   s = align256(s + mlp_scratch_bytes(x->V));
+  x->bnd_off = s;
+  s = align256(s + (size_t)M.nbf * x->V * x->P * sizeof(double));
   x->scratch_bytes = s;
   mlp_init(x->mlp, x->V);
   *out = x;
@@ -493,15 +521,24 @@ adg_status adg_init_problem(adg_ctx c, int32_t problem, const double* params) {
   if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
   if (problem < 0 || problem > 2) return fail(ADG_ERR_INVALID, "unknown problem");
   if (problem == ADG_VORTEX && c->D != 2) return fail(ADG_ERR_INVALID, "the vortex is a 2D problem");
-  Prm prm{};
-  const double def[3][5] = {{5, 5, 5, 1, 1}, {0.2, 1, 1, 1, 1}, {1, 0.3, -0.2, 0.1, 1}};
-  for (int i = 0; i < 5; ++i) prm.v[i] = params ? params[i] : def[problem][i];
+  const Prm prm = problem_params(problem, params);
   HIP_TRY(launch_init(c->D, c->p, c->mesh, problem, prm, c->u_n, c->d_tab64, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  c->bc_problem = problem;
+  c->bc_prm = prm;
   c->n = 0;
   c->hist_start = 0;
   c->t = 0.0;
   mlp_reset_stats(c);
+  return ADG_OK;
+}
+
+adg_status adg_set_boundary(adg_ctx c, int32_t problem, const double* params) {
+  if (!c) return fail(ADG_ERR_INVALID, "null context");
+  if (problem < 0 || problem > 2) return fail(ADG_ERR_INVALID, "unknown problem");
+  if (problem == ADG_VORTEX && c->D != 2) return fail(ADG_ERR_INVALID, "the vortex is a 2D problem");
+  c->bc_problem = problem;
+  c->bc_prm = problem_params(problem, params);
   return ADG_OK;
 }
 

@@ -1,6 +1,8 @@
 // adg_aux.hip — gfx950 kernels outside the time-step hot loop: L2 projection
 // of the analytic problems, error norms, integrals, relative differences,
-// state checks, the wave-speed maximum, and a deterministic reduction.
+// state checks, the wave-speed maximum, a deterministic reduction, and the
+// exterior states of a Dirichlet box's boundary faces (one small launch per
+// stage, before the stage kernel).
 #include "adg_internal.h"
 
 namespace adg {
@@ -9,7 +11,8 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// exact solutions (Sec. 5.1 vortex with mean flow (mu, mv), periodic;
+// exact solutions (Sec. 5.1 vortex with mean flow (mu, mv): the nearest
+// periodic image in a periodic box, the vortex itself in a Dirichlet box;
 // density wave; constant state), conserved variables
 template <int D>
 __device__ void exact_state(int problem, const double* prm, const double* x, double t, double gamma,
@@ -18,8 +21,10 @@ __device__ void exact_state(int problem, const double* prm, const double* x, dou
     const double x0 = prm[0], y0 = prm[1], beta = prm[2], mu = prm[3], mv = prm[4];
     const double Lx = M.hi[0] - M.lo[0], Ly = M.hi[1] - M.lo[1];
     double dx = x[0] - x0 - mu * t, dy = x[1] - y0 - mv * t;
-    dx -= Lx * floor(dx / Lx + 0.5);
-    dy -= Ly * floor(dy / Ly + 0.5);
+    if (!M.bc) {
+      dx -= Lx * floor(dx / Lx + 0.5);
+      dy -= Ly * floor(dy / Ly + 0.5);
+    }
     const double g = exp(1.0 - (dx * dx + dy * dy));
     const double u = mu - beta * g * dy / (2.0 * kPi);
     const double v = mv + beta * g * dx / (2.0 * kPi);
@@ -240,6 +245,29 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restri
   }
 }
 
+// one thread per (boundary face, face node) of a Dirichlet box (d = 2): the
+// exact state at the node at time t, written as bnd[face][v][j]. Face node j
+// sits at the j-th Gauss-Lobatto node of the tangential axis, ascending, as
+// the stage kernel orders a neighbour's face trace.
+template <int P>
+__global__ __launch_bounds__(kThreads) void bnd_fill_kernel(Mesh M, int problem, Prm prm, double t,
+                                                       const double* __restrict__ tab, double* __restrict__ bnd) {
+  constexpr int V = 4;
+  constexpr TabOff to = tab_off(P, P + 1);
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= M.nbf * P) return;
+  const int bf = i / P, j = i - bf * P;
+  int f = 0;
+  for (int g = 1; g < 4; ++g)
+    if (bf >= M.bnd_off[g]) f = g;
+  const int a = f >> 1, b = a ^ 1, ct = bf - M.bnd_off[f];
+  double x[3] = {0.0, 0.0, 0.0}, w[kMaxV];
+  x[a] = (f & 1) ? M.hi[a] : M.lo[a];
+  x[b] = M.lo[b] + M.h[b] * (ct + 0.5 * (tab[to.XL + j] + 1.0));
+  exact_state<2>(problem, prm.v, x, t, M.gamma, M, w);
+  for (int v = 0; v < V; ++v) bnd[(bf * V + v) * P + j] = w[v];
+}
+
 }  // namespace
 
 int norms_blocks(long long E) { return (int)(E < 2048 ? E : 2048); }
@@ -276,6 +304,21 @@ hipError_t launch_norms(int dim, int degree, const Mesh& M, int what, int proble
 hipError_t launch_reduce(const double* partial, int nblk, int ncomp, int op, double* out, hipStream_t st) {
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, st, partial, nblk, ncomp, op, out);
   return hipGetLastError();
+}
+
+hipError_t launch_bnd_fill(int degree, const Mesh& M, int problem, const Prm& prm, double t, const double* tab64,
+                           double* bnd, hipStream_t st) {
+  if (M.dim != 2 || !M.bc || M.nbf <= 0) return hipErrorInvalidValue;
+  const unsigned nblk = (unsigned)((M.nbf * (degree + 1) + kThreads - 1) / kThreads);
+#define ADG_BND_CASE(p)                                                                                   \
+  if (degree == p) {                                                                                      \
+    hipLaunchKernelGGL((bnd_fill_kernel<p + 1>), dim3(nblk), dim3(kThreads), 0, st, M, problem, prm, t, tab64, \
+                       bnd);                                                                              \
+    return hipGetLastError();                                                                             \
+  }
+  ADG_BND_CASE(1) ADG_BND_CASE(2) ADG_BND_CASE(3) ADG_BND_CASE(4)
+#undef ADG_BND_CASE
+  return hipErrorInvalidValue;
 }
 
 }  // namespace adg

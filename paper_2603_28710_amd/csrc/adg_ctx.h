@@ -34,7 +34,10 @@ struct adg_ctx_s {
   size_t ndof = 0;
   int R = 0, Qh = 1;
   size_t ring_bytes = 0, ring_cap = 0, scratch_bytes = 0;
-  size_t ghost_off = 0, partial_off = 0, red_off = 0, mlp_off = 0;
+  size_t ghost_off = 0, partial_off = 0, red_off = 0, mlp_off = 0, bnd_off = 0;
+  // Dirichlet box: the problem whose exact solution gives the boundary data
+  int bc_problem = -1;
+  adg::Prm bc_prm{};
   double *u_n = nullptr, *u_a = nullptr, *u_b = nullptr, *ring = nullptr;
   char* scratch = nullptr;
   bool bound = false;

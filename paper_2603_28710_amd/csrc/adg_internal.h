@@ -75,9 +75,12 @@ __host__ __device__ inline unsigned fmod64(unsigned long long x, const FastMod64
   return fmodu(a * g.r62 + fmodu(b, g.f) * g.r31 + fmodu(c, g.f), g.f);
 }
 
-// Structured periodic box, block partition into virtual subdomains, and the
-// arithmetic enumeration of PE-boundary face-sides (a face-side is a pair
-// (receiving element, face) whose neighbour lies in another subdomain).
+// Structured box (periodic, or with Dirichlet sides in 2D), block partition
+// into virtual subdomains, and the arithmetic enumeration of PE-boundary
+// face-sides (a face-side is a pair (receiving element, face) whose neighbour
+// lies in another subdomain). The enumeration is that of the periodic box in
+// either case: in a Dirichlet box the slots of the boundary faces exist but
+// are never written or read.
 // Face-sides are grouped by receiving subdomain, then by face direction f
 // (f = 2a + side; side 0 is the -a face), then lexicographically over the
 // subdomain-local coordinates of the two other axes (lowest axis fastest).
@@ -96,6 +99,9 @@ struct Mesh {
   double detJf[3];   // face Jacobian for faces normal to axis a
   double gamma;
   int flux;
+  int bc;            // 0 periodic; 1 Dirichlet on every side (d = 2)
+  int bnd_off[4];    // first boundary face of side f: x- and x+ by iy, y- and y+ by ix
+  int nbf;           // boundary faces (0 in a periodic box)
   FastDiv dnc[2];    // division by nc[0], nc[1]
   FastDiv dm[3];     // division by m[k]
   FastDiv dparts[2]; // division by parts[0], parts[1]
@@ -137,6 +143,9 @@ struct Stage {
   int lserk;
   double bw, ar;
   double* out2;
+  // Dirichlet box: the exterior states of the boundary faces at this stage's
+  // time, [boundary face][V][P] at the face nodes (null in a periodic box)
+  const double* bnd;
 };
 
 // ---- device helpers shared by several kernels -------------------------------
@@ -214,10 +223,19 @@ __host__ __device__ inline int face_local_index(const Mesh& M, const int* l, int
   const int o0 = a == 0 ? 1 : 0, o1 = a == 2 ? 1 : 2;
   return M.dim == 3 ? l[o0] + M.m[o0] * l[o1] : l[o0];
 }
-// face_side for the element at p: its face-side of face f, or -1
+// index of face f of the element at p among the boundary faces of a Dirichlet
+// box, or -1
+__host__ __device__ inline int bnd_face_at(const Mesh& M, const ElemPos& p, int f) {
+  const int a = f >> 1;
+  if (!M.bc || p.c[a] != ((f & 1) ? M.nc[a] - 1 : 0)) return -1;
+  return M.bnd_off[f] + p.c[a ^ 1];
+}
+// face_side for the element at p: its face-side of face f, or -1 (also for a
+// boundary face of a Dirichlet box)
 __host__ __device__ inline long long face_side_at(const Mesh& M, const ElemPos& p, int f) {
   const int a = f >> 1;
   if (M.parts[a] < 2) return -1;
+  if (M.bc && p.c[a] == ((f & 1) ? M.nc[a] - 1 : 0)) return -1;
   if ((f & 1) ? (p.l[a] != M.m[a] - 1) : (p.l[a] != 0)) return -1;
   return (long long)sub_at(M, p.sc) * M.fs_sub + M.fs_off[f] + face_local_index(M, p.l, a);
 }
@@ -341,6 +359,10 @@ hipError_t launch_norms(int dim, int degree, const Mesh& M, int what, int proble
                         const double* u, const double* ref, const double* tab64, double* partial, int nblk,
                         hipStream_t st);
 hipError_t launch_reduce(const double* partial, int nblk, int ncomp, int op, double* out, hipStream_t st);
+// exterior states of the boundary faces of a Dirichlet box (d = 2) at time t:
+// bnd[boundary face][V][P], the exact solution at the face nodes
+hipError_t launch_bnd_fill(int degree, const Mesh& M, int problem, const Prm& prm, double t, const double* tab64,
+                           double* bnd, hipStream_t st);
 int norms_blocks(long long E);
 
 }  // namespace adg

@@ -15,8 +15,9 @@
 //           Gauss weights and the inverse 1D mass as one operator each
 //           (eq. weakform-dealii / weakform-compact-dealii; |J| cancels).
 //   faces:  per axis, every lane interpolates its own and the neighbour's
-//           face traces (live values, or the delayed / AT / learned trace at a
-//           PE-boundary face) to the Gauss points of both faces; one lane per
+//           face traces (live values, the delayed / AT / learned trace at a
+//           PE-boundary face, or the exact exterior state at a boundary face of
+//           a Dirichlet box) to the Gauss points of both faces; one lane per
 //           (element, face, point) evaluates the local Lax-Friedrichs flux of
 //           eq. lfflux / lfflux-lambda in canonical (left, right) order, in
 //           place; every lane lifts its variable with BW and adds the column
@@ -215,7 +216,13 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
 #pragma unroll
           for (int j = 0; j < P; ++j) dst[j] = u[fnode<P>(f, j)];
         }
-        if (fs < 0 || ((src == kSrcRing || flux_mode) && kd == 0)) {
+        const int bf = bnd_face_at(M, pos, f);
+        if (bf >= 0) {
+          // boundary face of a Dirichlet box: the exact exterior state
+          const double* gp = S.bnd + ((long long)bf * V + v) * P;
+#pragma unroll
+          for (int j = 0; j < P; ++j) g[j] = gp[j];
+        } else if (fs < 0 || ((src == kSrcRing || flux_mode) && kd == 0)) {
           if (NB == 4 || a == 0) {
 #pragma unroll
             for (int j = 0; j < P; ++j) g[j] = nbv[NB == 4 ? f : s][j];

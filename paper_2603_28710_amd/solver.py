@@ -73,6 +73,13 @@ class Solver:
             p = np.ascontiguousarray(params, dtype=np.float64)
             B.adg_init_problem(self.h, problem, p.ctypes.data)
 
+    def set_boundary(self, problem, params=None):
+        if params is None:
+            B.adg_set_boundary(self.h, problem)
+        else:
+            p = np.ascontiguousarray(params, dtype=np.float64)
+            B.adg_set_boundary(self.h, problem, p.ctypes.data)
+
     def step(self, n, dt):
         return B.check(B.adg_step(self.h, n, dt))
 

@@ -374,3 +374,83 @@ def test_lserk_against_oracle(oracle_mod, S, dim, p, integ, ghost, kind, L, leve
     r = rel_l2(s.download(), o.state(), dim, s=s)
     say("  rel L2", r)
     assert r <= (TOL if precision == 0 else 1e-6)
+
+
+# ------------------------------------------- Dirichlet box (Sec. 5.1 vortex)
+
+PAPER_VORTEX = (5.0, 0.0, 5.0, 1.0, 0.0)
+WAVE_IN = (0.2, 1.0, 1.0, 0.0, 1.0)  # density wave entering through x = 0 and y = 0
+
+
+@pytest.mark.parametrize("p,problem,ghost,kind,L,levels,integ,precision", [
+    (1, "wave", 0, 0, 0, 3, 0, 0), (2, "wave", 0, 0, 0, 3, 0, 0), (3, "wave", 0, 0, 0, 3, 0, 0),
+    (4, "wave", 0, 0, 0, 3, 0, 0), (3, "vortex", 0, 0, 0, 3, 0, 0),
+    (3, "wave", 1, 2, 4, 1, 0, 0), (3, "vortex", 2, 2, 4, 3, 0, 0), (1, "vortex", 2, 2, 4, 2, 0, 0),
+    (2, "wave", 2, 1, 3, 3, 0, 0), (3, "wave", 4, 2, 3, 1, 0, 0), (3, "wave", 5, 2, 4, 3, 0, 0),
+    (2, "wave", 2, 2, 4, 3, 2, 0), (3, "vortex", 0, 0, 0, 3, 1, 0), (4, "wave", 2, 1, 3, 3, 0, 1),
+])
+def test_dirichlet_box_against_oracle(oracle_mod, S, p, problem, ghost, kind, L, levels, integ, precision):
+    # every side carries the exact solution at the stage time; the density
+    # wave enters through two sides, so the boundary data vary along the
+    # faces and in time; 36 x 20 elements leave a ragged last wavefront
+    O = oracle_mod
+    say(f"case: Dirichlet box {problem} p={p} ghost={ghost} kind={kind} L={L} levels={levels} "
+        f"integrator={integ} precision={precision}, 20 steps")
+    if problem == "wave":
+        prob, prm, lo, hi = O.DENSITY_WAVE, WAVE_IN, (0, 0, 0), (1, 1, 1)
+    else:
+        prob, prm, lo, hi = O.VORTEX, PAPER_VORTEX, (0, -5, 0), (10, 5, 1)
+    cfg = dict(dim=2, cells=(36, 20, 1), parts=(4, 2, 1), lo=lo, hi=hi, ghost=ghost, delay_kind=kind, L=L,
+               levels=levels, seed=4, integrator=integ)
+    o = O.Oracle(p=p, bc=O.DIRICHLET, bc_problem=prob, bc_params=prm, **cfg)
+    o.init_problem(prob, prm)
+    o.set_state(o.state() + inputs.perturbation(o.ndof, 21, 1e-3))
+    s = S(degree=p, precision=precision, boundary=1, **cfg)
+    s.upload(o.state())
+    s.set_boundary(prob, prm)
+    dt = 0.5 * o.stable_dt(0.1)
+    o.step(20, dt)
+    s.step(20, dt)
+    r = rel_l2(s.download(), o.state(), 2, s=s)
+    say("  rel L2", r)
+    assert r <= (TOL if precision == 0 else 1e-6)
+
+
+def test_dirichlet_paper_vortex_norms_and_projection(oracle_mod, S):
+    # the paper's vortex in its Dirichlet box: the GPU projection, and the
+    # error norms against the unwrapped exact solution late in the run, when
+    # the vortex has moved towards the x = 10 side (a periodic image would
+    # reappear near x = 0)
+    O = oracle_mod
+    say("case: paper vortex 40x40 p=2, projection and error norms at t = 3.9")
+    cfg = dict(dim=2, cells=(40, 40, 1), lo=(0, -5, 0), hi=(10, 5, 1))
+    o = O.Oracle(p=2, bc=O.DIRICHLET, bc_problem=O.VORTEX, bc_params=PAPER_VORTEX, **cfg)
+    o.init_problem(O.VORTEX, PAPER_VORTEX)
+    s = S(degree=2, boundary=1, **cfg)
+    s.init_problem(O.VORTEX, PAPER_VORTEX)
+    assert rel_l2(s.download(), o.state(), 2, s=s) < 1e-13
+    s.upload(o.state())
+    s.set_boundary(O.VORTEX, PAPER_VORTEX)
+    dt = 3.9 / 800  # sigma ~ 0.12 in the CFL reading
+    o.step(800, dt)
+    s.step(800, dt)
+    assert rel_l2(s.download(), o.state(), 2, s=s) <= TOL
+    eo = np.array(o.error_norms(O.VORTEX, 3.9, PAPER_VORTEX))
+    es = np.array(s.error_norms(O.VORTEX, PAPER_VORTEX))
+    say("  error norms oracle", eo, "gpu", es)
+    np.testing.assert_allclose(es, eo, rtol=1e-9)
+    assert eo.max() < 0.05
+
+
+def test_dirichlet_needs_a_boundary_problem(oracle_mod, S, B):
+    O = oracle_mod
+    s = S(dim=2, degree=2, cells=(8, 8, 1), boundary=1)
+    s.upload(np.ones(s.ndof))
+    assert s.step_status(1, 1e-3) == B.ADG_ERR_STATE
+    s.set_boundary(O.CONSTANT, (1.0, 1.0, 0.0, 0.0, 1.0))
+    o = O.Oracle(dim=2, p=2, cells=(8, 8, 1), bc=O.DIRICHLET, bc_problem=O.CONSTANT,
+                 bc_params=(1.0, 1.0, 0.0, 0.0, 1.0))
+    o.init_problem(O.CONSTANT, (1.0, 1.0, 0.0, 0.0, 1.0))
+    s.upload(o.state())
+    s.step(5, 1e-3)
+    np.testing.assert_allclose(s.download(), o.state(), rtol=0, atol=1e-13)

@@ -42,6 +42,8 @@ def test_every_declared_symbol_is_exported(B):
     (dict(integrator=3), "integrator"),
     (dict(integrator=-1), "integrator"),
     (dict(lo=(1, 0, 0), hi=(1, 1, 1)), "hi"),
+    (dict(boundary=2), "boundary"),
+    (dict(dim=3, cells=(4, 4, 4), boundary=1), "Dirichlet"),
 ])
 def test_create_rejects_bad_config(B, kw, msg):
     with pytest.raises(B.AdgError) as ei:
@@ -56,6 +58,25 @@ def test_create_rejects_bad_config(B, kw, msg):
 def test_create_rejects_bad_async(B, kw):
     with pytest.raises(B.AdgError):
         B.adg_create(B.make_config(), B.make_async(**kw))
+
+
+def test_dirichlet_box_rejects_learned_ghosts_and_bad_problems(B):
+    with pytest.raises(B.AdgError) as ei:
+        B.adg_create(B.make_config(parts=(2, 2, 1), boundary=1), B.make_async(ghost=3, delay_kind=1, L=2))
+    assert "periodic" in str(ei.value)
+    h = B.adg_create(B.make_config(parts=(2, 2, 1), boundary=1), B.make_async(ghost=2, delay_kind=2, L=3))
+    with pytest.raises(B.AdgError):
+        B.adg_set_async(h, B.make_async(ghost=3, delay_kind=1, L=2))
+    with pytest.raises(B.AdgError):
+        B.adg_set_boundary(h, 3)
+    B.adg_set_boundary(h, B.ADG_VORTEX)
+    # the boundary-face slots of the periodic enumeration are kept: the ring
+    # layout does not depend on the boundary
+    _, _, rb, _ = B.adg_sizes(h)
+    h2 = B.adg_create(B.make_config(parts=(2, 2, 1)), B.make_async(ghost=2, delay_kind=2, L=3))
+    assert B.adg_sizes(h2)[2] == rb
+    B.adg_destroy(h)
+    B.adg_destroy(h2)
 
 
 def test_unbound_calls_fail_cleanly(B):
