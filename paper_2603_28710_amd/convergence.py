@@ -2,15 +2,22 @@
 
 The paper's accuracy study (Sec. 5.1, the convergence figures of the
 isentropic vortex) shows that delayed neighbour data with the standard flux
-degrades the scheme to first order, while AT extrapolation over past levels
-recovers the synchronous curve and its order p + 1. This tool repeats that
-sweep with the GPU solver: the vortex on [0,10]^2 with 8x8 virtual
-subdomains, n x n elements, degree p, run to t_end with a time step
-proportional to h^r (r = (p+1)/3 keeps SSP-RK3's time error below the
-spatial one at degree 3), and reports the L2 errors against the exact
-solution and the slopes between consecutive meshes.
+degrade the scheme to first order, while AT extrapolation over past levels
+recovers the synchronous curve and its order p + 1. Two settings:
 
-    python -m paper_2603_28710_amd.convergence [--ns 32 64 128 256] [--degree 3]
+* "periodic" (default): the vortex on the periodic box [0,10]^2 with mean
+  flow (1,1), 8x8 virtual subdomains, uniform random delays, SSP-RK3, to
+  t_end with a time step proportional to h^r (r = (p+1)/3 keeps SSP-RK3's
+  time error below the spatial one at degree 3).
+* "paper": the paper's own runs: the vortex of mean flow (1,0) in the
+  Dirichlet box [0,10] x [-5,5], t_end = 4, 16x16 subdomains (256 PEs), the
+  communication-avoiding schedules with L = 4, DG(1) with LSERK(2,2) and AT2
+  or DG(2) with LSERK(3,3) and AT3, CFL 0.05 for the synchronous and AT
+  schemes and 0.03 for the standard flux. Both readings of what is delayed
+  run: neighbour traces ("caa_std", "caa_at") and the stored fluxes of the
+  algorithms themselves ("flux_caa_std", "flux_caa_at").
+
+    python -m paper_2603_28710_amd.convergence [--setting paper] [--ns 32 64 128 256] [--degree 2]
 
 prints one JSON line per (mode, n) and one per mode with its slopes.
 """
@@ -24,32 +31,39 @@ MODES = {
     "at3_uniform": dict(ghost=2, delay_kind=1),
 }
 
+PAPER_VORTEX = (5.0, 0.0, 5.0, 1.0, 0.0)  # x0, y0, beta, mean flow (1, 0)
+PAPER_MODES = {
+    "sync": dict(ghost=0, delay_kind=0, L=0, cfl=0.05),
+    "caa_std": dict(ghost=1, delay_kind=2, cfl=0.03),
+    "caa_at": dict(ghost=2, delay_kind=2, cfl=0.05),
+    "flux_caa_std": dict(ghost=4, delay_kind=2, cfl=0.03),
+    "flux_caa_at": dict(ghost=5, delay_kind=2, cfl=0.05),
+}
 
-def run(mode, n, degree, L, parts, t_end, cfl, r, n_ref, seed=0, problem=0):
-    """L2 errors (density, momentum, energy) at t_end on the n x n mesh; the
-    step is the CFL step of the n_ref mesh scaled by (n_ref / n)^r"""
+
+def _run(n, degree, asy, box, t_end, dt_of, seed=0):
+    """L2 errors (density, momentum, energy) at t_end on the n x n mesh with
+    the time step dt_of(n), and the number of steps"""
     from paper_2603_28710_amd.solver import Solver
 
-    asy = dict(MODES[mode])
-    asy.setdefault("L", L)
-    levels = 1 if asy["ghost"] == 1 else 3
-
-    def make(m):
-        s = Solver(dim=2, degree=degree, cells=(m, m, 1), parts=(parts, parts, 1), lo=(0, 0, 0),
-                   hi=(10, 10, 1), levels=levels, seed=seed, **asy)
-        s.init_problem(problem)
-        return s
-
-    ref = make(n_ref)
-    dt_ref = ref.stable_dt(cfl)
-    ref.close()
-    dt = dt_ref * (n_ref / n) ** r
+    s = Solver(dim=2, degree=degree, cells=(n, n, 1), seed=seed, **box["cfg"], **asy)
+    s.init_problem(box["problem"], box["params"])
+    dt = dt_of(n)
     nst = int(math.ceil(t_end / dt))
-    s = make(n)
     s.step(nst, t_end / nst)
-    err = s.error_norms(problem)
+    err = s.error_norms(box["problem"], box["params"])
     s.close()
     return err, nst
+
+
+def _stable_dt(n, degree, box, cfl):
+    from paper_2603_28710_amd.solver import Solver
+
+    s = Solver(dim=2, degree=degree, cells=(n, n, 1), **box["cfg"])
+    s.init_problem(box["problem"], box["params"])
+    dt = s.stable_dt(cfl)
+    s.close()
+    return dt
 
 
 def slopes(errs):
@@ -57,12 +71,18 @@ def slopes(errs):
 
 
 def sweep(modes, ns, degree=3, L=3, parts=8, t_end=1.0, cfl=0.1, r=None, emit=print):
+    """the periodic setting"""
     r = (degree + 1) / 3.0 if r is None else r
+    box = dict(cfg=dict(parts=(parts, parts, 1), lo=(0, 0, 0), hi=(10, 10, 1)), problem=0, params=None)
+    dt_ref = _stable_dt(ns[0], degree, box, cfl)
     out = {}
     for mode in modes:
+        asy = dict(MODES[mode])
+        asy.setdefault("L", L)
+        asy["levels"] = 1 if asy["ghost"] == 1 else 3
         errs = []
         for n in ns:
-            err, nst = run(mode, n, degree, L, parts, t_end, cfl, r, ns[0])
+            err, nst = _run(n, degree, asy, box, t_end, lambda m: dt_ref * (ns[0] / m) ** r)
             errs.append(list(err))
             emit(json.dumps({"mode": mode, "n": n, "degree": degree, "L": L, "steps": nst, "l2": list(err)}))
         out[mode] = (errs, slopes(errs))
@@ -70,18 +90,48 @@ def sweep(modes, ns, degree=3, L=3, parts=8, t_end=1.0, cfl=0.1, r=None, emit=pr
     return out
 
 
+def paper_sweep(modes, ns, degree=2, L=4, parts=16, t_end=4.0, emit=print):
+    """the paper's setting: Dirichlet box, CAA schedules, LSERK(p+1, p+1),
+    AT over p + 1 levels, time step from the CFL number on each mesh"""
+    box = dict(cfg=dict(parts=(parts, parts, 1), lo=(0, -5, 0), hi=(10, 5, 1), boundary=1,
+                        integrator=1 if degree == 1 else 2),
+               problem=0, params=PAPER_VORTEX)
+    out = {}
+    for mode in modes:
+        m = dict(PAPER_MODES[mode])
+        cfl = m.pop("cfl")
+        m.setdefault("L", L)
+        m["levels"] = 1 if m["ghost"] in (1, 4) else degree + 1
+        errs = []
+        for n in ns:
+            err, nst = _run(n, degree, m, box, t_end, lambda k: _stable_dt(k, degree, box, cfl))
+            errs.append(list(err))
+            emit(json.dumps({"setting": "paper", "mode": mode, "n": n, "degree": degree, "L": m["L"], "cfl": cfl,
+                             "steps": nst, "l2": list(err)}))
+        out[mode] = (errs, slopes(errs))
+        emit(json.dumps({"setting": "paper", "mode": mode, "degree": degree, "slopes": out[mode][1]}))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--setting", choices=["periodic", "paper"], default="periodic")
     ap.add_argument("--ns", type=int, nargs="+", default=[32, 64, 128, 256])
-    ap.add_argument("--degree", type=int, default=3)
-    ap.add_argument("--L", type=int, default=3)
-    ap.add_argument("--parts", type=int, default=8)
-    ap.add_argument("--t-end", type=float, default=1.0)
+    ap.add_argument("--degree", type=int, default=None)
+    ap.add_argument("--L", type=int, default=None)
+    ap.add_argument("--parts", type=int, default=None)
+    ap.add_argument("--t-end", type=float, default=None)
     ap.add_argument("--cfl", type=float, default=0.1)
     ap.add_argument("--r", type=float, default=None)
-    ap.add_argument("--modes", nargs="+", default=list(MODES))
+    ap.add_argument("--modes", nargs="+", default=None)
     a = ap.parse_args()
-    sweep(a.modes, a.ns, a.degree, a.L, a.parts, a.t_end, a.cfl, a.r, emit=lambda s: print(s, flush=True))
+    emit = lambda s: print(s, flush=True)  # noqa: E731
+    if a.setting == "paper":
+        paper_sweep(a.modes or list(PAPER_MODES), a.ns, a.degree or 2, a.L or 4, a.parts or 16, a.t_end or 4.0,
+                    emit=emit)
+    else:
+        sweep(a.modes or list(MODES), a.ns, a.degree or 3, a.L or 3, a.parts or 8, a.t_end or 1.0, a.cfl, a.r,
+              emit=emit)
 
 
 if __name__ == "__main__":

@@ -1,4 +1,5 @@
-"""The paper's accuracy result on the GPU solver, at the 256^2 vortex
+"""The paper's accuracy result on the GPU solver: at the paper's own setting
+(Dirichlet box, CAA schedules, LSERK), and at the 256^2 vortex
 settings (8x8 virtual subdomains, degree 3, uniform random delays up to L=3):
 delayed traces with the standard flux lose the order of accuracy, AT
 extrapolation over three past levels recovers the synchronous errors and
@@ -33,3 +34,23 @@ def test_at_recovers_order_p_plus_1_stale_does_not():
     np.testing.assert_allclose(e_at, e_sync, rtol=0.01)   # the curves overlap
     assert np.all(s_st[-1] < 1.6)                 # standard flux on delayed traces: order lost
     assert np.all(e_st[-1] > 100 * e_sync[-1])
+
+
+@pytest.mark.parametrize("degree", [1, 2])
+def test_paper_setting_caa_at_matches_sync_caa_std_first_order(degree):
+    # the paper's own runs (the convergence figures of Sec. 5.1): vortex with
+    # mean flow (1,0) in the Dirichlet box [0,10] x [-5,5] to t = 4, 16x16
+    # subdomains, CAA schedules with L = 4, LSERK(p+1,p+1), AT over p+1
+    # levels; CFL 0.05 (sync, AT) and 0.03 (standard flux)
+    from paper_2603_28710_amd import convergence as C
+
+    say(f"case: paper vortex p={degree}, n = 32, 64, 128, sync / caa_std / caa_at, L=4, t=4")
+    res = C.paper_sweep(["sync", "caa_std", "caa_at"], [32, 64, 128], degree=degree, emit=say)
+    e_sync, s_sync = (np.array(x) for x in res["sync"])
+    e_std, s_std = (np.array(x) for x in res["caa_std"])
+    e_at, s_at = (np.array(x) for x in res["caa_at"])
+    assert np.all(s_sync[-1] > degree + 1 - 0.25)   # order p + 1
+    assert np.all(s_at[-1] > degree + 1 - 0.25)     # kept by AT
+    np.testing.assert_allclose(e_at, e_sync, rtol=0.05)
+    assert np.all(s_std[-1] < 1.2)                  # first order with the standard flux
+    assert np.all(e_std[-1] > 5 * e_sync[-1])
