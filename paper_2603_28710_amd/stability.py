@@ -7,11 +7,15 @@ is stable if `adg_step`, with the state checked every `check` steps, reports
 no non-finite or non-physical state up to t_end. The returned sigma is the
 largest stable value found by bisection between lo and hi.
 
-    python -m paper_2603_28710_amd.stability [--t-end 4] [--cells 64] [--degree 2]
+    python -m paper_2603_28710_amd.stability [--setting paper] [--t-end 4] [--cells 64] [--degree 2]
 
 prints one JSON line per (mode, L) with the bracket [stable, unstable]. The
 learned mode trains its network first (pairs from the same mesh and
 schedule at CFL 0.1), then runs with an accept bound of LEARNED_TOL.
+Settings: "periodic" (default) is the vortex of mean flow (1,1) on the
+periodic box [0,10]^2 with SSP-RK3; "paper" is the paper's own: mean flow
+(1,0) in the Dirichlet box [0,10] x [-5,5], LSERK(p+1,p+1) (the learned
+predictor needs a periodic box and is skipped there).
 """
 import argparse
 import json
@@ -28,6 +32,7 @@ MODES = {
     "learned_caa": dict(ghost=3, delay_kind=2),
 }
 LEARNED_TOL = 1e-4
+PAPER_VORTEX = (5.0, 0.0, 5.0, 1.0, 0.0)
 
 
 def train_predictor(make, cfl, steps=400, every=40, epochs=8):
@@ -80,6 +85,7 @@ def max_stable_cfl(make, t_end, lo=0.005, hi=1.0, iters=8):
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--setting", choices=["periodic", "paper"], default="periodic")
     ap.add_argument("--t-end", type=float, default=4.0)
     ap.add_argument("--cells", type=int, default=64)
     ap.add_argument("--parts", type=int, default=16)
@@ -93,27 +99,36 @@ def main():
     from paper_2603_28710_amd.solver import Solver
 
     n = a.cells
+    paper = a.setting == "paper"
+    if paper:
+        box = dict(lo=(0, -5, 0), hi=(10, 5, 1), boundary=1, integrator=1 if a.degree == 1 else 2)
+        params = PAPER_VORTEX
+    else:
+        box = dict(lo=(0, 0, 0), hi=(10, 10, 1))
+        params = None
 
     def maker(mode, L, weights=None):
         def make():
             extra = dict(learned_tol=LEARNED_TOL) if MODES[mode]["ghost"] == 3 else {}
-            s = Solver(dim=2, degree=a.degree, cells=(n, n, 1), parts=(a.parts, a.parts, 1), lo=(0, 0, 0),
-                       hi=(10, 10, 1), check_every=a.check, levels=a.levels, L=L, seed=0, **MODES[mode], **extra)
+            s = Solver(dim=2, degree=a.degree, cells=(n, n, 1), parts=(a.parts, a.parts, 1), check_every=a.check,
+                       levels=a.levels, L=L, seed=0, **box, **MODES[mode], **extra)
             if weights is not None:
                 s.predictor_set(weights)
-            s.init_problem(0)
+            s.init_problem(0, params)
             return s
         return make
 
     sync_lo, sync_hi = max_stable_cfl(maker("at_caa", 0), a.t_end)
     print(json.dumps({"mode": "sync", "L": 0, "stable": sync_lo, "unstable": sync_hi}), flush=True)
     for mode in a.modes:
+        if paper and MODES[mode]["ghost"] == 3:
+            continue
         for L in a.L:
             if L == 0 and mode in ("stale_caa", "flux_stale_caa"):
                 continue
             w = train_predictor(maker(mode, L), 0.1) if MODES[mode]["ghost"] == 3 else None
             lo, hi = max_stable_cfl(maker(mode, L, w), a.t_end)
-            print(json.dumps({"mode": mode, "L": L, "stable": lo, "unstable": hi, "cells": n,
+            print(json.dumps({"setting": a.setting, "mode": mode, "L": L, "stable": lo, "unstable": hi, "cells": n,
                               "degree": a.degree, "t_end": a.t_end}), flush=True)
 
 
