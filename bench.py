@@ -71,11 +71,19 @@ WORKLOADS = {
     "vortex256_p3_fluxat3_caaL3": dict(
         cfg=dict(dim=2, degree=3, cells=(256, 256, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
         asy=dict(ghost=5, delay_kind=2, L=3, levels=3, seed=0), problem=0, precision=0),
+    # the paper's own accuracy run at its finest mesh: the vortex of mean flow
+    # (1,0) in the Dirichlet box [0,10] x [-5,5], degree 2, 16x16 subdomains,
+    # Alg. caa-at with L = 4, AT3, LSERK(3,3), CFL 0.05
+    "paper_vortex256_p2_at3_caaL4_lserk33": dict(
+        cfg=dict(dim=2, degree=2, cells=(256, 256, 1), parts=(16, 16, 1), lo=(0, -5, 0), hi=(10, 5, 1),
+                 integrator=2, boundary=1),
+        asy=dict(ghost=2, delay_kind=2, L=4, levels=3, seed=0), problem=0, params=(5.0, 0.0, 5.0, 1.0, 0.0),
+        precision=0, cfl=0.05),
 }
 DEFAULT = "vortex256_p3_at3_uniformL3"
 
 
-def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, ghost, levels, integrator=0):
+def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, ghost, levels, integrator=0, bnd_values=0):
     """Minimum HBM bytes of one fused stage launch, averaged over the stages
     of a step: for SSP-RK3 the stage input read once, u^n read on stages 2
     and 3, the output written (8 B each per DoF: 64/3 B per DoF); for
@@ -86,12 +94,13 @@ def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, ghost, levels, integrator
     predictor's ghost buffer for learned traces) and, at stage 0, one level
     written (nfs_nodes_vars values per level). The flux-history modes are
     counted by their state traffic only (their flux ring traffic depends on
-    the schedule), so their figure is a lower bound."""
+    the schedule), so their figure is a lower bound. In a Dirichlet box the
+    stage also reads the boundary data (bnd_values values)."""
     ring = 0.0
     if ghost in (1, 2, 3) and nfs_nodes_vars > 0:
         ring = 8.0 * nfs_nodes_vars * ((levels if ghost == 2 else 1) + 1.0 / 3.0)
     per_dof = {0: 64.0 / 3.0, 1: 24.0, 2: 80.0 / 3.0}[integrator]
-    return ndof * per_dof + ring
+    return ndof * per_dof + ring + 8.0 * bnd_values
 
 
 def algorithmic_flops_per_element(dim, P, Q):
@@ -145,8 +154,8 @@ def cpu_baseline(w, target_s=15.0):
     integ = c.get("integrator", 0)
     o = O.Oracle(dim=c["dim"], p=c["degree"], cells=c["cells"], parts=c["parts"], lo=c["lo"], hi=c["hi"],
                  ghost=a["ghost"], delay_kind=a["delay_kind"], L=a["L"], levels=a["levels"], seed=a["seed"],
-                 integrator=integ)
-    o.init_problem(w["problem"])
+                 integrator=integ, bc=c.get("boundary", 0), bc_problem=w["problem"], bc_params=w.get("params"))
+    o.init_problem(w["problem"], w.get("params"))
     dt = o.stable_dt(w.get("cfl", 0.1))
     t0 = time.perf_counter()
     o.step(1, dt)
@@ -172,7 +181,7 @@ def run_steps(w, steps, warmup):
 
     c, a = w["cfg"], w["asy"]
     s = Solver(device="cuda:0", precision=w["precision"], **c, **a)
-    s.init_problem(w["problem"])
+    s.init_problem(w["problem"], w.get("params"))
     if a["ghost"] == B.ADG_GHOST_LEARNED:
         s.predictor_init(w["net_seed"])
     dt = s.stable_dt(w.get("cfl", 0.1))
@@ -219,7 +228,7 @@ def main():
     w = WORKLOADS[args.workload]
     c, a = w["cfg"], w["asy"]
     s = Solver(device="cuda:0", precision=w["precision"], **c, **a)
-    s.init_problem(w["problem"])
+    s.init_problem(w["problem"], w.get("params"))
     if a["ghost"] == B.ADG_GHOST_LEARNED:
         s.predictor_init(w["net_seed"])
     cfl = w.get("cfl", 0.1)
@@ -244,15 +253,22 @@ def main():
     value = s.ndof * stages / sec
     nfs = B.adg_delay(s.h, s.time()[0], 0, 0)[1]
     Fn = (c["degree"] + 1) ** (c["dim"] - 1)
+    # in a Dirichlet box (2D) the boundary faces keep unused slots in the
+    # face-side enumeration: count only the PE face-sides, 2 (parts_a - 1)
+    # interface lines of cells_b faces per axis a
+    if c.get("boundary", 0):
+        px, py = c["parts"][0], c["parts"][1]
+        nfs = 2 * (px - 1) * c["cells"][1] * (px > 1) + 2 * (py - 1) * c["cells"][0] * (py > 1)
+    bnd_values = 2 * (c["cells"][0] + c["cells"][1]) * s.V * (c["degree"] + 1) if c.get("boundary", 0) else 0
     bytes_launch = algorithmic_bytes_per_launch(s.ndof, nfs * s.V * Fn, a["ghost"], a["levels"],
-                                                c.get("integrator", 0))
+                                                c.get("integrator", 0), bnd_values)
     avg_s = rhs_ms / max(rhs_n, 1) / 1e3
     achieved = bytes_launch / avg_s / 1e9
     P, Q = c["degree"] + 1, c["degree"] + 2
     flops_launch = algorithmic_flops_per_element(c["dim"], P, Q) * s.E
     fpeak = FP32_PEAK_TFLOPS if w["precision"] else FP64_PEAK_TFLOPS
     traffic = load_traffic(args.workload)
-    err = s.error_norms(w["problem"]) if w["problem"] in (0, 1) else None
+    err = s.error_norms(w["problem"], w.get("params")) if w["problem"] in (0, 1) else None
 
     out = {
         "metric": "DOF-updates/s per RK stage",
@@ -273,7 +289,8 @@ def main():
                    "levels": a["levels"],
                    "delay": ["fixed", "uniform", "caa"][a["delay_kind"]], "L": a["L"], "seed": a["seed"],
                    "dofs": s.ndof, "elements": s.E, "dt": dt, "cfl": cfl,
-                   "integrator": ["ssprk3", "lserk22", "lserk33"][c.get("integrator", 0)]},
+                   "integrator": ["ssprk3", "lserk22", "lserk33"][c.get("integrator", 0)],
+                   "boundary": ["periodic", "dirichlet"][c.get("boundary", 0)]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "rhs_stage", "avg_launch_us": avg_s * 1e6, "launches": rhs_n,

@@ -271,11 +271,15 @@ static adg_status run_stage(adg_ctx_s* c, int m, double dt, bool learned_collect
   }
   Stage S{kSspA[m % 3], kSspB[m % 3], dt, 0, 0.0, 0.0, nullptr, nullptr};
   if (c->mesh.bc) {
-    // the boundary data at this stage's time
+    // the boundary data of every stage of the step, in one launch at stage 0
     double* bnd = scratch_d(c, c->bnd_off);
-    HIP_TRY(launch_bnd_fill(c->p, c->mesh, c->bc_problem, c->bc_prm, c->t + A.c_m * dt, c->d_tab64, bnd,
-                            c->stream));
-    S.bnd = bnd;
+    if (m == 0) {
+      StageTimes T{};
+      T.n = n_stages(ig);
+      for (int j = 0; j < T.n; ++j) T.t[j] = c->t + stage_time(ig, j) * dt;
+      HIP_TRY(launch_bnd_fill(c->p, c->mesh, c->bc_problem, c->bc_prm, T, c->d_tab64, bnd, c->stream));
+    }
+    S.bnd = bnd + (size_t)m * c->mesh.nbf * c->V * c->P;
   }
   if (ig != ADG_SSPRK3) {
     S.lserk = 1;
@@ -437,7 +441,7 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
   x->mlp_off = s;
   s = align256(s + mlp_scratch_bytes(x->V));
   x->bnd_off = s;
-  s = align256(s + (size_t)M.nbf * x->V * x->P * sizeof(double));
+  s = align256(s + (size_t)3 * M.nbf * x->V * x->P * sizeof(double));
   x->scratch_bytes = s;
   mlp_init(x->mlp, x->V);
   *out = x;

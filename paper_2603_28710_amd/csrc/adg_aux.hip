@@ -245,18 +245,23 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restri
   }
 }
 
-// one thread per (boundary face, face node) of a Dirichlet box (d = 2): the
-// exact state at the node at time t, written as bnd[face][v][j]. Face node j
-// sits at the j-th Gauss-Lobatto node of the tangential axis, ascending, as
-// the stage kernel orders a neighbour's face trace.
+// one thread per (stage, boundary face, face node) of a Dirichlet box
+// (d = 2): the exact state at the node at the stage's time, written as
+// bnd[stage][face][v][j]. Face node j sits at the j-th Gauss-Lobatto node of
+// the tangential axis, ascending, as the stage kernel orders a neighbour's
+// face trace.
 template <int P>
-__global__ __launch_bounds__(kThreads) void bnd_fill_kernel(Mesh M, int problem, Prm prm, double t,
+__global__ __launch_bounds__(kThreads) void bnd_fill_kernel(Mesh M, int problem, Prm prm, StageTimes T,
                                                        const double* __restrict__ tab, double* __restrict__ bnd) {
   constexpr int V = 4;
   constexpr TabOff to = tab_off(P, P + 1);
+  const int per = M.nbf * P;
   const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= M.nbf * P) return;
-  const int bf = i / P, j = i - bf * P;
+  if (i >= T.n * per) return;
+  const int m = i / per, r = i - m * per;
+  const int bf = r / P, j = r - bf * P;
+  const double t = T.t[m];
+  bnd += (long long)m * M.nbf * V * P;
   int f = 0;
   for (int g = 1; g < 4; ++g)
     if (bf >= M.bnd_off[g]) f = g;
@@ -306,10 +311,10 @@ hipError_t launch_reduce(const double* partial, int nblk, int ncomp, int op, dou
   return hipGetLastError();
 }
 
-hipError_t launch_bnd_fill(int degree, const Mesh& M, int problem, const Prm& prm, double t, const double* tab64,
-                           double* bnd, hipStream_t st) {
-  if (M.dim != 2 || !M.bc || M.nbf <= 0) return hipErrorInvalidValue;
-  const unsigned nblk = (unsigned)((M.nbf * (degree + 1) + kThreads - 1) / kThreads);
+hipError_t launch_bnd_fill(int degree, const Mesh& M, int problem, const Prm& prm, const StageTimes& t,
+                           const double* tab64, double* bnd, hipStream_t st) {
+  if (M.dim != 2 || !M.bc || M.nbf <= 0 || t.n < 1 || t.n > 3) return hipErrorInvalidValue;
+  const unsigned nblk = (unsigned)((t.n * M.nbf * (degree + 1) + kThreads - 1) / kThreads);
 #define ADG_BND_CASE(p)                                                                                   \
   if (degree == p) {                                                                                      \
     hipLaunchKernelGGL((bnd_fill_kernel<p + 1>), dim3(nblk), dim3(kThreads), 0, st, M, problem, prm, t, tab64, \

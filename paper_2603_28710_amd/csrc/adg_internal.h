@@ -134,6 +134,12 @@ struct Prm {
   double v[5];
 };
 
+// the times t_n + c_m dt of the n stages of one step
+struct StageTimes {
+  double t[3];
+  int n;
+};
+
 struct Stage {
   double a, b, dt;  // SSP-RK3 (Shu-Osher): out = a u_n + b (u_in + dt k)
   // LSERK (eq. lserk-dg), when lserk != 0: u_n holds the accumulator w;
@@ -359,10 +365,11 @@ hipError_t launch_norms(int dim, int degree, const Mesh& M, int what, int proble
                         const double* u, const double* ref, const double* tab64, double* partial, int nblk,
                         hipStream_t st);
 hipError_t launch_reduce(const double* partial, int nblk, int ncomp, int op, double* out, hipStream_t st);
-// exterior states of the boundary faces of a Dirichlet box (d = 2) at time t:
-// bnd[boundary face][V][P], the exact solution at the face nodes
-hipError_t launch_bnd_fill(int degree, const Mesh& M, int problem, const Prm& prm, double t, const double* tab64,
-                           double* bnd, hipStream_t st);
+// exterior states of the boundary faces of a Dirichlet box (d = 2) at the
+// stage times of one step: bnd[stage][boundary face][V][P], the exact
+// solution at the face nodes
+hipError_t launch_bnd_fill(int degree, const Mesh& M, int problem, const Prm& prm, const StageTimes& t,
+                           const double* tab64, double* bnd, hipStream_t st);
 int norms_blocks(long long E);
 
 }  // namespace adg
