@@ -46,7 +46,7 @@ def run(workload, steps):
 
     w = bench.WORKLOADS[workload]
     s = Solver(device="cuda:0", precision=w["precision"], **w["cfg"], **w["asy"])
-    s.init_problem(w["problem"])
+    s.init_problem(w["problem"], w.get("params"))
     if w["asy"]["ghost"] == 3:
         s.predictor_init(w["net_seed"])
     dt = s.stable_dt(w.get("cfl", 0.1))
