@@ -283,6 +283,11 @@ static const int NH_MLP = 64; /* hidden width */
 static const double SSP_A[3] = {0.0, 0.75, 1.0 / 3.0};
 static const double SSP_B[3] = {1.0, 0.25, 2.0 / 3.0};
 static const double SSP_C[3] = {0.0, 1.0, 0.5};
+/* SSP-RK2 (Heun) in the same form: u1 = u^n + dt L(u^n),
+ * u^{n+1} = u^n / 2 + (u1 + dt L(u1)) / 2, stage times 0 and 1 */
+static const double SSP2_A[2] = {0.0, 0.5};
+static const double SSP2_B[2] = {1.0, 0.5};
+static const double SSP2_C[2] = {0.0, 1.0};
 
 /* LSERK(s,o) of eq. lserk-dg with the digits of Table lserk-scheme:
  *   k_m = M^-1 L(r_m),  r_{m+1} = w + dt a_m k_m,  w <- w + dt b_m k_m,
@@ -295,10 +300,11 @@ static const double LS22_B[2] = {0.5, 0.5};
 static const double LS33_A[3] = {0.755726352, 0.386954477, 0.0};
 static const double LS33_B[3] = {0.245170287, 0.184896052, 0.569933661};
 
-static int n_stages(const orc_solver* s) { return s->c.integrator == 1 ? 2 : 3; }
+static int n_stages(const orc_solver* s) { return (s->c.integrator == 1 || s->c.integrator == 3) ? 2 : 3; }
 
 static double stage_time(const orc_solver* s, int m) {
   if (s->c.integrator == 0) return SSP_C[m];
+  if (s->c.integrator == 3) return SSP2_C[m];
   const double* a = s->c.integrator == 1 ? LS22_A : LS33_A;
   const double* b = s->c.integrator == 1 ? LS22_B : LS33_B;
   if (m == 0) return 0.0;
@@ -361,7 +367,7 @@ void* orc_create(const orc_cfg* cfg) {
   orc_solver* s = (orc_solver*)xmalloc(sizeof(orc_solver));
   s->c = *cfg;
   int D = cfg->dim;
-  if (D < 2 || D > 3 || cfg->p < 1 || cfg->p > 5 || cfg->integrator < 0 || cfg->integrator > 2 ||
+  if (D < 2 || D > 3 || cfg->p < 1 || cfg->p > 5 || cfg->integrator < 0 || cfg->integrator > 3 ||
       cfg->bc < 0 || cfg->bc > 1 || (cfg->bc && (cfg->bc_problem < 0 || cfg->bc_problem > 2 || cfg->ghost == 3))) {
     free(s);
     return NULL;
@@ -1075,12 +1081,13 @@ int orc_step(void* vs, int64_t nsteps, double dt) {
   s->dt = dt;
   for (int64_t it = 0; it < nsteps; ++it) {
     if (s->hist) memcpy(s->hist + (size_t)(s->n % s->R) * nd, s->u, sizeof(double) * nd);
-    if (s->c.integrator == 0) {
+    if (s->c.integrator == 0 || s->c.integrator == 3) {
+      const int rk2 = s->c.integrator == 3;
       double* in[3] = {s->u, s->ua, s->ub};
-      double* outp[3] = {s->ua, s->ub, s->u};
-      for (int m = 0; m < 3; ++m) {
+      double* outp[3] = {s->ua, rk2 ? s->u : s->ub, s->u};
+      for (int m = 0; m < n_stages(s); ++m) {
         full_rhs(s, in[m], m, 1, s->kb);
-        double a = SSP_A[m], b = SSP_B[m];
+        double a = rk2 ? SSP2_A[m] : SSP_A[m], b = rk2 ? SSP2_B[m] : SSP_B[m];
         const double* ui = in[m];
         double* uo = outp[m];
 #pragma omp parallel for schedule(static)

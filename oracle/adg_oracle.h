@@ -40,7 +40,8 @@ typedef struct orc_cfg {
   uint64_t seed;        /* seed of the delay draws */
   double learned_tol;   /* accept bound on the learned correction (physical units) */
   int32_t integrator;   /* 0 SSP-RK3 (Shu-Osher), 1 LSERK(2,2), 2 LSERK(3,3): the two-register
-                           low-storage schemes of eq. lserk-dg with Table lserk-scheme */
+                           low-storage schemes of eq. lserk-dg with Table lserk-scheme;
+                           3 SSP-RK2 (Heun, Shu-Osher form) */
   int32_t bc;           /* 0 periodic box; 1 Dirichlet on every side of the box (Sec. 5.1
                            vortex): the exterior state of a boundary face is the exact
                            solution of bc_problem at the stage time, and the exact

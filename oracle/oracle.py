@@ -14,7 +14,7 @@ SYNC, STALE, AT, LEARNED, FLUX_STALE, FLUX_AT = 0, 1, 2, 3, 4, 5
 FIXED, UNIFORM, CAA = 0, 1, 2
 VORTEX, DENSITY_WAVE, CONSTANT = 0, 1, 2
 LLF, RUSANOV = 0, 1
-SSPRK3, LSERK22, LSERK33 = 0, 1, 2
+SSPRK3, LSERK22, LSERK33, SSPRK2 = 0, 1, 2, 3
 PERIODIC, DIRICHLET = 0, 1
 
 

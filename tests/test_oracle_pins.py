@@ -663,3 +663,52 @@ def test_dirichlet_rejects_learned_ghosts(oracle_mod):
     O = oracle_mod
     with pytest.raises(ValueError):
         O.Oracle(dim=2, p=2, cells=(8, 8, 1), parts=(2, 2, 1), ghost=O.LEARNED, bc=O.DIRICHLET)
+
+
+# ---------------------------------------------------------- SSP-RK2 (Heun)
+
+def test_ssprk2_step_is_heun(oracle_mod):
+    # one oracle step against Heun's method composed from the synchronous
+    # operator: k1 = L(u), k2 = L(u + dt k1), u + dt (k1 + k2) / 2
+    O = oracle_mod
+    o = O.Oracle(dim=2, p=3, cells=(6, 5, 1), hi=(10, 10, 1), integrator=O.SSPRK2)
+    o.init_problem(O.VORTEX)
+    u0 = o.state() + inputs.perturbation(o.ndof, 23, 1e-3)
+    o.set_state(u0)
+    dt = o.stable_dt(0.1)
+    k1 = o.rhs(u0)
+    k2 = o.rhs(u0 + dt * k1)
+    ref = u0 + 0.5 * dt * (k1 + k2)
+    assert o.step(1, dt) == 0
+    np.testing.assert_allclose(o.state(), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+def test_ssprk2_second_order_in_time(oracle_mod):
+    O = oracle_mod
+    sols = []
+    for nst in (20, 40, 80):
+        o = O.Oracle(dim=2, p=4, cells=(4, 4, 1), hi=(1, 1, 1), integrator=O.SSPRK2)
+        o.init_problem(O.DENSITY_WAVE)
+        o.step(nst, 0.05 / nst * 4)
+        sols.append(o.state())
+    d1 = np.linalg.norm(sols[0] - sols[1])
+    d2 = np.linalg.norm(sols[1] - sols[2])
+    assert 2 ** 1.8 < d1 / d2 < 2 ** 2.2
+
+
+def test_ssprk2_at_recovers_sync_stale_does_not(oracle_mod):
+    # stage times (0, 1) enter tau = k + c_m; with AT the delayed run stays
+    # near the synchronous one, with stale traces it does not
+    O = oracle_mod
+    base = dict(dim=2, p=2, cells=(16, 16, 1), parts=(4, 4, 1), hi=(1, 1, 1), integrator=O.SSPRK2, seed=2)
+    runs = {}
+    for name, ghost, levels in (("sync", 0, 3), ("at", 2, 2), ("stale", 1, 1)):
+        o = O.Oracle(ghost=ghost, delay_kind=O.UNIFORM if ghost else O.FIXED, L=2 if ghost else 0, levels=levels,
+                     **base)
+        o.init_problem(O.DENSITY_WAVE)
+        dt = 0.5 * o.stable_dt(0.1)
+        assert o.step(40, dt) == 0
+        runs[name] = o.state()
+    d_at = np.linalg.norm(runs["at"] - runs["sync"])
+    d_st = np.linalg.norm(runs["stale"] - runs["sync"])
+    assert d_at < 0.05 * d_st
