@@ -89,7 +89,8 @@ def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, ghost, levels, integrator
     and 3, the output written (8 B each per DoF: 64/3 B per DoF); for
     LSERK(2,2) / (3,3) the input, the accumulator w (except at the first
     stage, where it is the input) and two outputs (one at the last stage):
-    24 and 80/3 B per DoF; at PE-boundary faces
+    24 and 80/3 B per DoF; for SSP-RK2 the input read, u^n read at the
+    second stage, the output written: 20 B per DoF; at PE-boundary faces
     the ring levels read (one for stale traces, `levels` for AT, the
     predictor's ghost buffer for learned traces) and, at stage 0, one level
     written (nfs_nodes_vars values per level). The flux-history modes are
@@ -99,7 +100,7 @@ def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, ghost, levels, integrator
     ring = 0.0
     if ghost in (1, 2, 3) and nfs_nodes_vars > 0:
         ring = 8.0 * nfs_nodes_vars * ((levels if ghost == 2 else 1) + 1.0 / 3.0)
-    per_dof = {0: 64.0 / 3.0, 1: 24.0, 2: 80.0 / 3.0}[integrator]
+    per_dof = {0: 64.0 / 3.0, 1: 24.0, 2: 80.0 / 3.0, 3: 20.0}[integrator]
     return ndof * per_dof + ring + 8.0 * bnd_values
 
 
@@ -164,10 +165,10 @@ def cpu_baseline(w, target_s=15.0):
     t2 = time.perf_counter()
     o.step(n, dt)
     t3 = time.perf_counter()
-    return {"value": o.ndof * (2 if integ == 1 else 3) * n / (t3 - t2), "unit": "DOF-updates/s per RK stage",
+    return {"value": o.ndof * (2 if integ in (1, 3) else 3) * n / (t3 - t2), "unit": "DOF-updates/s per RK stage",
             "cores": threads,
             "kind": "oracle",
-            "sample": f"full mesh, {n} {['SSP-RK3', 'LSERK(2,2)', 'LSERK(3,3)'][integ]} steps after 1 warm-up "
+            "sample": f"full mesh, {n} {['SSP-RK3', 'LSERK(2,2)', 'LSERK(3,3)', 'SSP-RK2'][integ]} steps after 1 warm-up "
                       f"step ({t3 - t2:.1f} s)"}
 
 
@@ -249,7 +250,7 @@ def main():
     B.adg_profile(s.h, 0)
 
     sec = t1 - t0
-    stages = (2 if c.get("integrator", 0) == B.ADG_LSERK22 else 3) * args.steps
+    stages = (2 if c.get("integrator", 0) in (B.ADG_LSERK22, B.ADG_SSPRK2) else 3) * args.steps
     value = s.ndof * stages / sec
     nfs = B.adg_delay(s.h, s.time()[0], 0, 0)[1]
     Fn = (c["degree"] + 1) ** (c["dim"] - 1)
@@ -289,7 +290,7 @@ def main():
                    "levels": a["levels"],
                    "delay": ["fixed", "uniform", "caa"][a["delay_kind"]], "L": a["L"], "seed": a["seed"],
                    "dofs": s.ndof, "elements": s.E, "dt": dt, "cfl": cfl,
-                   "integrator": ["ssprk3", "lserk22", "lserk33"][c.get("integrator", 0)],
+                   "integrator": ["ssprk3", "lserk22", "lserk33", "ssprk2"][c.get("integrator", 0)],
                    "boundary": ["periodic", "dirichlet"][c.get("boundary", 0)]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

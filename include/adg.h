@@ -75,6 +75,9 @@ typedef int32_t adg_status;
  * (u_n, u_a, u_b); the state is in u_n after every step. */
 #define ADG_LSERK22 1
 #define ADG_LSERK33 2
+/* SSP-RK2 (Heun) in Shu-Osher form: u1 = u^n + dt L(u^n),
+ * u^{n+1} = u^n / 2 + (u1 + dt L(u1)) / 2; stage times 0 and 1 */
+#define ADG_SSPRK2 3
 /* arithmetic of the volume/face contractions and inverse mass */
 #define ADG_FP64 0
 #define ADG_FP32_CONTRACT 1 /* contractions in FP32; RK state, AT weights, norms in FP64 */
@@ -118,7 +121,7 @@ typedef struct adg_config {
   double lo[3], hi[3]; /* the box */
   double gamma;        /* ratio of specific heats (> 1) */
   int32_t flux;        /* ADG_FLUX_* */
-  int32_t integrator;  /* ADG_SSPRK3, ADG_LSERK22 or ADG_LSERK33 */
+  int32_t integrator;  /* ADG_SSPRK3, ADG_LSERK22, ADG_LSERK33 or ADG_SSPRK2 */
   int32_t precision;   /* ADG_FP64 or ADG_FP32_CONTRACT */
   int32_t check_every; /* 0: adg_step never checks the state; k>0: every k steps and at the end */
   int32_t boundary;    /* ADG_BC_PERIODIC or ADG_BC_DIRICHLET (d = 2, not with ADG_GHOST_LEARNED) */

@@ -15,7 +15,7 @@ ADG_OK = 0
 ADG_ERR_INVALID, ADG_ERR_UNBOUND, ADG_ERR_HIP = -1, -2, -3
 ADG_ERR_NONFINITE, ADG_ERR_NONPHYSICAL, ADG_ERR_STATE = -4, -5, -6
 ADG_FLUX_LLF, ADG_FLUX_RUSANOV = 0, 1
-ADG_SSPRK3, ADG_LSERK22, ADG_LSERK33 = 0, 1, 2
+ADG_SSPRK3, ADG_LSERK22, ADG_LSERK33, ADG_SSPRK2 = 0, 1, 2, 3
 ADG_FP64, ADG_FP32_CONTRACT = 0, 1
 ADG_GHOST_SYNC, ADG_GHOST_STALE, ADG_GHOST_AT, ADG_GHOST_LEARNED = 0, 1, 2, 3
 ADG_GHOST_FLUX_STALE, ADG_GHOST_FLUX_AT = 4, 5

@@ -73,17 +73,20 @@ namespace {
 const double kSspA[3] = {0.0, 0.75, 1.0 / 3.0};
 const double kSspB[3] = {1.0, 0.25, 2.0 / 3.0};
 const double kSspC[3] = {0.0, 1.0, 0.5};
+// SSP-RK2 (Heun) in the same form: stages (a, b) = (0, 1), (1/2, 1/2), c = (0, 1)
+const double kSsp2A[2] = {0.0, 0.5}, kSsp2B[2] = {1.0, 0.5}, kSsp2C[2] = {0.0, 1.0};
 // LSERK(2,2), LSERK(3,3): a_m and b_m as printed in Table lserk-scheme
 const double kLs22A[2] = {1.0, 0.0}, kLs22B[2] = {0.5, 0.5};
 const double kLs33A[3] = {0.755726352, 0.386954477, 0.0}, kLs33B[3] = {0.245170287, 0.184896052, 0.569933661};
 
-int n_stages(int integrator) { return integrator == ADG_LSERK22 ? 2 : 3; }
+int n_stages(int integrator) { return (integrator == ADG_LSERK22 || integrator == ADG_SSPRK2) ? 2 : 3; }
 
 // stage time fraction c_m: SSP-RK3's, or c_1 = 0, c_m = b_1 + .. + b_{m-2} +
 // a_{m-1} for the low-storage schemes (their own a and b, not the table's
 // rounded c column)
 double stage_time(int integrator, int m) {
   if (integrator == ADG_SSPRK3) return kSspC[m];
+  if (integrator == ADG_SSPRK2) return kSsp2C[m];
   const double* a = integrator == ADG_LSERK22 ? kLs22A : kLs33A;
   const double* b = integrator == ADG_LSERK22 ? kLs22B : kLs33B;
   if (m == 0) return 0.0;
@@ -231,7 +234,8 @@ adg_status adg::prof_end(adg_ctx_s* c) {
 
 static adg_status run_stage(adg_ctx_s* c, int m, double dt, bool learned_collect, long long pair_base) {
   // registers per stage. SSP-RK3: inputs u_n, u_a, u_b; outputs u_a, u_b,
-  // u_n. LSERK (w the accumulator, r the stage input; no stage writes the
+  // u_n. SSP-RK2: u_n -> u_a, then u_a -> u_n (in place; each element reads
+  // its own u^n before writing). LSERK (w the accumulator, r the stage input; no stage writes the
   // register its neighbours read):
   //   (2,2): r1 = w0 = u_n -> w1 u_a, r2 u_b;  r2 = u_b, w1 = u_a -> w2 u_n
   //   (3,3): as (2,2) at m = 0; r2 = u_b, w1 = u_a -> w2 u_n, r3 u_a (in
@@ -241,7 +245,8 @@ static adg_status run_stage(adg_ctx_s* c, int m, double dt, bool learned_collect
   double* out[3] = {c->u_a, c->u_b, c->u_n};
   double* wreg = c->u_n;  // the operand read as u_n by the combine
   double* out2 = nullptr;
-  if (ig != ADG_SSPRK3) {
+  if (ig == ADG_SSPRK2) out[1] = c->u_n;  // u1 in u_a; the second stage in place over u_n
+  if (ig == ADG_LSERK22 || ig == ADG_LSERK33) {
     double* lin[3] = {c->u_n, c->u_b, c->u_a};
     double* lw[3] = {c->u_n, c->u_a, c->u_n};
     double* lout[3] = {c->u_a, c->u_n, c->u_n};
@@ -270,6 +275,10 @@ static adg_status run_stage(adg_ctx_s* c, int m, double dt, bool learned_collect
     }
   }
   Stage S{kSspA[m % 3], kSspB[m % 3], dt, 0, 0.0, 0.0, nullptr, nullptr};
+  if (ig == ADG_SSPRK2) {
+    S.a = kSsp2A[m];
+    S.b = kSsp2B[m];
+  }
   if (c->mesh.bc) {
     // the boundary data of every stage of the step, in one launch at stage 0
     double* bnd = scratch_d(c, c->bnd_off);
@@ -281,7 +290,7 @@ static adg_status run_stage(adg_ctx_s* c, int m, double dt, bool learned_collect
     }
     S.bnd = bnd + (size_t)m * c->mesh.nbf * c->V * c->P;
   }
-  if (ig != ADG_SSPRK3) {
+  if (ig == ADG_LSERK22 || ig == ADG_LSERK33) {
     S.lserk = 1;
     S.bw = ig == ADG_LSERK22 ? kLs22B[m] : kLs33B[m];
     S.ar = ig == ADG_LSERK22 ? kLs22A[m] : kLs33A[m];
@@ -337,7 +346,8 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
   if (c.n_q != 0 && c.n_q != c.degree + 2) return fail(ADG_ERR_INVALID, "n_q must be 0 or degree+2");
   if (!(c.gamma > 1.0)) return fail(ADG_ERR_INVALID, "gamma must be > 1");
   if (c.flux != ADG_FLUX_LLF && c.flux != ADG_FLUX_RUSANOV) return fail(ADG_ERR_INVALID, "unknown flux");
-  if (c.integrator != ADG_SSPRK3 && c.integrator != ADG_LSERK22 && c.integrator != ADG_LSERK33)
+  if (c.integrator != ADG_SSPRK3 && c.integrator != ADG_LSERK22 && c.integrator != ADG_LSERK33 &&
+      c.integrator != ADG_SSPRK2)
     return fail(ADG_ERR_INVALID, "unknown integrator");
   if (c.precision != ADG_FP64 && c.precision != ADG_FP32_CONTRACT) return fail(ADG_ERR_INVALID, "unknown precision");
   if (c.check_every < 0) return fail(ADG_ERR_INVALID, "check_every must be >= 0");

@@ -347,13 +347,17 @@ def test_fp32_contraction_within_1e6_of_fp64(oracle_mod, S):
     (3, 2, 2, 2, 1, 2, 3, 0),
     (3, 3, 2, 2, 0, 2, 3, 0),
     (3, 4, 1, 2, 1, 2, 3, 0),
+    (2, 3, 3, 0, 0, 0, 3, 0),   # SSP-RK2
+    (2, 3, 3, 2, 1, 3, 2, 0),
+    (3, 3, 3, 5, 2, 3, 3, 0),
 ])
-def test_lserk_against_oracle(oracle_mod, S, dim, p, integ, ghost, kind, L, levels, precision):
+def test_integrators_against_oracle(oracle_mod, S, dim, p, integ, ghost, kind, L, levels, precision):
     # the two-register schemes move the state through all three registers
     # (the second LSERK(3,3) stage writes its next input over the accumulator
-    # it reads) and end every step in u_n
+    # it reads) and end every step in u_n; SSP-RK2 writes its second stage in
+    # place over u_n
     O = oracle_mod
-    say(f"case: LSERK integrator={integ} dim={dim} p={p} ghost={ghost} kind={kind} L={L} levels={levels} "
+    say(f"case: integrator={integ} dim={dim} p={p} ghost={ghost} kind={kind} L={L} levels={levels} "
         f"precision={precision}, 10 steps")
     if dim == 2:
         cfg = dict(dim=2, cells=(36, 20, 1), parts=(4, 2, 1), hi=(10, 10, 1))

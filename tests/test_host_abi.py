@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(B):
     (dict(gamma=1.0), "gamma"),
     (dict(flux=7), "flux"),
     (dict(precision=3), "precision"),
-    (dict(integrator=3), "integrator"),
+    (dict(integrator=4), "integrator"),
     (dict(integrator=-1), "integrator"),
     (dict(lo=(1, 0, 0), hi=(1, 1, 1)), "hi"),
     (dict(boundary=2), "boundary"),
