@@ -3,6 +3,8 @@ configuration bench.py times.
 
 - 2D vortex 256x256, degree 3, 8x8 subdomains, AT3 with uniform delays in
   {0..3}: the oracle runs the whole mesh, 60 steps; relative L2 <= 1e-11.
+- The paper's vortex in its Dirichlet box, 256x256, degree 2, 16x16
+  subdomains, Alg. caa-at with L = 4, LSERK(3,3): whole mesh, 60 steps.
 - 3D density wave 64^3 (degree 3), 3D density wave 128^3 (degree 2), 2D vortex
   1024^2 (degree 4): one full SSP-RK3 step; the oracle computes the outputs of
   a seeded sample of elements one by one through their dependency cone
@@ -63,6 +65,30 @@ def test_vortex256_p3_at3_uniform_60_steps(oracle_mod):
     o.step(60, dt)
     V = 4
     r = rel_l2_groups(s.download().reshape(-1, V, 16), o.state().reshape(-1, V, 16), V)
+    say("  rel L2", r)
+    assert r <= 1e-11
+
+
+def test_paper_vortex256_p2_caa_at_lserk33_60_steps(oracle_mod):
+    # the paper's own accuracy run at its finest mesh, as bench.py times it:
+    # Dirichlet box, 16x16 subdomains, Alg. caa-at with L = 4, AT3,
+    # LSERK(3,3), CFL 0.05; the oracle runs the whole mesh
+    from paper_2603_28710_amd.solver import Solver
+    O = oracle_mod
+    prm = (5.0, 0.0, 5.0, 1.0, 0.0)
+    cfg = dict(dim=2, cells=(256, 256, 1), parts=(16, 16, 1), lo=(0, -5, 0), hi=(10, 5, 1), ghost=2, delay_kind=2,
+               L=4, levels=3, seed=0, integrator=2)
+    say("case: paper vortex 256^2 p=2 Dirichlet, caa-at L=4, LSERK(3,3), 60 steps, full oracle")
+    o = O.Oracle(p=2, bc=O.DIRICHLET, bc_problem=O.VORTEX, bc_params=prm, **cfg)
+    o.init_problem(O.VORTEX, prm)
+    s = Solver(degree=2, boundary=1, **cfg)
+    s.upload(o.state())
+    s.set_boundary(O.VORTEX, prm)
+    dt = o.stable_dt(0.05)
+    s.step(60, dt)
+    o.step(60, dt)
+    V = 4
+    r = rel_l2_groups(s.download().reshape(-1, V, 9), o.state().reshape(-1, V, 9), V)
     say("  rel L2", r)
     assert r <= 1e-11
 
