@@ -230,8 +230,9 @@ adg_status adg_diff_norm(adg_ctx ctx, const double* host_ref, double out[3]);
 /* Integrals of the V conserved variables over the box (quadrature), FP64. */
 adg_status adg_integrals(adg_ctx ctx, double* out);
 
-/* Checkpoint: state u_n, ring, step counter, time, history origin and
- * predictor weights into a host blob. Call with host_blob == NULL to get the
+/* Checkpoint: state u_n, ring, step counter, time, history origin,
+ * asynchrony settings, boundary problem and predictor weights into a host
+ * blob. Call with host_blob == NULL to get the
  * size in *bytes. adg_load restores a blob saved from the same configuration. */
 adg_status adg_save(adg_ctx ctx, void* host_blob, size_t* bytes);
 adg_status adg_load(adg_ctx ctx, const void* host_blob, size_t bytes);

@@ -694,6 +694,8 @@ struct BlobHeader {
   double t;
   int32_t ghost, delay_kind, L, levels;
   uint64_t seed;
+  int32_t boundary, bc_problem;  // the box and the problem of its boundary data (-1: none set)
+  double bc_prm[5];
 };
 
 adg_status adg_save(adg_ctx c, void* host_blob, size_t* bytes) {
@@ -708,7 +710,7 @@ adg_status adg_save(adg_ctx c, void* host_blob, size_t* bytes) {
   if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
   BlobHeader h{};
   std::memcpy(h.magic, "ADGCKPT", 8);
-  h.version = 1;
+  h.version = 2;
   h.dim = c->D;
   h.degree = c->p;
   h.V = c->V;
@@ -723,6 +725,9 @@ adg_status adg_save(adg_ctx c, void* host_blob, size_t* bytes) {
   h.L = c->as.L;
   h.levels = c->as.levels;
   h.seed = c->as.seed;
+  h.boundary = c->cfg.boundary;
+  h.bc_problem = c->bc_problem;
+  for (int i = 0; i < 5; ++i) h.bc_prm[i] = c->bc_prm.v[i];
   char* b = static_cast<char*>(host_blob);
   std::memcpy(b, &h, sizeof(h));
   b += sizeof(h);
@@ -743,7 +748,8 @@ adg_status adg_load(adg_ctx c, const void* host_blob, size_t bytes) {
   if (bytes < sizeof(h)) return fail(ADG_ERR_INVALID, "blob too small");
   std::memcpy(&h, host_blob, sizeof(h));
   const size_t np = (size_t)mlp_nparams(c->V);
-  if (std::memcmp(h.magic, "ADGCKPT", 8) || h.version != 1 || h.dim != c->D || h.degree != c->p ||
+  if (std::memcmp(h.magic, "ADGCKPT", 8) || h.version != 2 || h.dim != c->D || h.degree != c->p ||
+      h.boundary != c->cfg.boundary ||
       h.ndof != (int64_t)c->ndof || h.ring_bytes != (int64_t)c->ring_bytes || h.nparams != (int64_t)np)
     return fail(ADG_ERR_INVALID, "blob does not match this configuration");
   if (bytes < sizeof(h) + c->ndof * sizeof(double) + c->ring_bytes + np * sizeof(float))
@@ -767,6 +773,10 @@ adg_status adg_load(adg_ctx c, const void* host_blob, size_t bytes) {
   c->n = h.n;
   c->hist_start = h.hist_start;
   c->t = h.t;
+  if (h.bc_problem >= 0) {
+    c->bc_problem = h.bc_problem;
+    for (int i = 0; i < 5; ++i) c->bc_prm.v[i] = h.bc_prm[i];
+  }
   return ADG_OK;
 }
 

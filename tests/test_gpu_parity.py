@@ -266,6 +266,27 @@ def test_checkpoint_resume_bitwise(oracle_mod, S):
     np.testing.assert_array_equal(t.download(), a)
 
 
+def test_checkpoint_resume_dirichlet_box(oracle_mod, S):
+    # the blob carries the boundary problem: the resumed context needs no
+    # adg_set_boundary and continues bitwise
+    O = oracle_mod
+    say("case: Dirichlet box, save after 5 steps, resume in a new context, bitwise")
+    prm = (5.0, 0.0, 5.0, 1.0, 0.0)
+    cfg = dict(dim=2, degree=2, cells=(24, 24, 1), parts=(4, 4, 1), lo=(0, -5, 0), hi=(10, 5, 1), ghost=5,
+               delay_kind=2, L=3, levels=3, seed=1, boundary=1, integrator=2)
+    s = S(**cfg)
+    s.init_problem(O.VORTEX, prm)
+    s.step(5, 0.01)
+    blob = s.save()
+    s.step(8, 0.01)
+    a = s.download()
+    t = S(**cfg)
+    t.load(blob)
+    assert t.time()[0] == 5
+    t.step(8, 0.01)
+    np.testing.assert_array_equal(t.download(), a)
+
+
 @pytest.mark.parametrize("ghost,kind,L", [(0, 0, 0), (1, 1, 3), (2, 1, 3), (2, 2, 2)])
 def test_free_stream_every_mode(oracle_mod, S, ghost, kind, L):
     O = oracle_mod
