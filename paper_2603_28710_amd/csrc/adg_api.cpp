@@ -188,7 +188,6 @@ adg_status check_state(adg_ctx_s* c) {
 
 }  // namespace
 
-// one SSP-RK3 stage: ghost traces (PE faces) then the fused RHS stage
 // ---- event timing --------------------------------------------------------
 constexpr int kProfPairs = 2048;
 
@@ -232,6 +231,9 @@ adg_status adg::prof_end(adg_ctx_s* c) {
     if (_s != ADG_OK) return _s;   \
   } while (0)
 
+// one stage m of the step: the boundary data (Dirichlet box, at m = 0), the
+// learned ghost traces (learned mode or pair collection), then the fused
+// stage kernel
 static adg_status run_stage(adg_ctx_s* c, int m, double dt, bool learned_collect, long long pair_base) {
   // registers per stage. SSP-RK3: inputs u_n, u_a, u_b; outputs u_a, u_b,
   // u_n. SSP-RK2: u_n -> u_a, then u_a -> u_n (in place; each element reads
