@@ -3,12 +3,15 @@
 The paper's accuracy study (Sec. 5.1, the convergence figures of the
 isentropic vortex) shows that delayed neighbour data with the standard flux
 degrade the scheme to first order, while AT extrapolation over past levels
-recovers the synchronous curve and its order p + 1. Two settings:
+recovers the synchronous curve and its order p + 1. Three settings:
 
 * "periodic" (default): the vortex on the periodic box [0,10]^2 with mean
   flow (1,1), 8x8 virtual subdomains, uniform random delays, SSP-RK3, to
   t_end with a time step proportional to h^r (r = (p+1)/3 keeps SSP-RK3's
   time error below the spatial one at degree 3).
+* "wave3d": the density wave on the periodic unit cube (the 3D workloads'
+  stand-in for the paper's cylinder), 4x4x4 subdomains, uniform delays up
+  to L, SSP-RK3 with dt ~ h^((p+1)/3), on the hexahedron kernels.
 * "paper": the paper's own runs: the vortex of mean flow (1,0) in the
   Dirichlet box [0,10] x [-5,5], t_end = 4, 16x16 subdomains (256 PEs), the
   communication-avoiding schedules with L = 4, DG(1) with LSERK(2,2) and AT2
@@ -17,7 +20,7 @@ recovers the synchronous curve and its order p + 1. Two settings:
   run: neighbour traces ("caa_std", "caa_at") and the stored fluxes of the
   algorithms themselves ("flux_caa_std", "flux_caa_at").
 
-    python -m paper_2603_28710_amd.convergence [--setting paper] [--ns 32 64 128 256] [--degree 2]
+    python -m paper_2603_28710_amd.convergence [--setting paper|wave3d] [--ns 32 64 128 256] [--degree 2]
 
 prints one JSON line per (mode, n) and one per mode with its slopes.
 """
@@ -42,11 +45,12 @@ PAPER_MODES = {
 
 
 def _run(n, degree, asy, box, t_end, dt_of, seed=0):
-    """L2 errors (density, momentum, energy) at t_end on the n x n mesh with
+    """L2 errors (density, momentum, energy) at t_end on the n^d mesh with
     the time step dt_of(n), and the number of steps"""
     from paper_2603_28710_amd.solver import Solver
 
-    s = Solver(dim=2, degree=degree, cells=(n, n, 1), seed=seed, **box["cfg"], **asy)
+    dim = box.get("dim", 2)
+    s = Solver(dim=dim, degree=degree, cells=(n, n, n if dim == 3 else 1), seed=seed, **box["cfg"], **asy)
     s.init_problem(box["problem"], box["params"])
     dt = dt_of(n)
     nst = int(math.ceil(t_end / dt))
@@ -59,7 +63,8 @@ def _run(n, degree, asy, box, t_end, dt_of, seed=0):
 def _stable_dt(n, degree, box, cfl):
     from paper_2603_28710_amd.solver import Solver
 
-    s = Solver(dim=2, degree=degree, cells=(n, n, 1), **box["cfg"])
+    dim = box.get("dim", 2)
+    s = Solver(dim=dim, degree=degree, cells=(n, n, n if dim == 3 else 1), **box["cfg"])
     s.init_problem(box["problem"], box["params"])
     dt = s.stable_dt(cfl)
     s.close()
@@ -70,10 +75,14 @@ def slopes(errs):
     return [[math.log2(a / b) for a, b in zip(e0, e1)] for e0, e1 in zip(errs[:-1], errs[1:])]
 
 
-def sweep(modes, ns, degree=3, L=3, parts=8, t_end=1.0, cfl=0.1, r=None, emit=print):
-    """the periodic setting"""
+def sweep(modes, ns, degree=3, L=3, parts=8, t_end=1.0, cfl=0.1, r=None, emit=print, dim=2):
+    """the periodic settings: the 2D vortex, or (dim = 3) the density wave"""
     r = (degree + 1) / 3.0 if r is None else r
-    box = dict(cfg=dict(parts=(parts, parts, 1), lo=(0, 0, 0), hi=(10, 10, 1)), problem=0, params=None)
+    if dim == 3:
+        box = dict(dim=3, cfg=dict(parts=(parts, parts, parts), lo=(0, 0, 0), hi=(1, 1, 1)), problem=1,
+                   params=None)
+    else:
+        box = dict(cfg=dict(parts=(parts, parts, 1), lo=(0, 0, 0), hi=(10, 10, 1)), problem=0, params=None)
     dt_ref = _stable_dt(ns[0], degree, box, cfl)
     out = {}
     for mode in modes:
@@ -84,9 +93,10 @@ def sweep(modes, ns, degree=3, L=3, parts=8, t_end=1.0, cfl=0.1, r=None, emit=pr
         for n in ns:
             err, nst = _run(n, degree, asy, box, t_end, lambda m: dt_ref * (ns[0] / m) ** r)
             errs.append(list(err))
-            emit(json.dumps({"mode": mode, "n": n, "degree": degree, "L": L, "steps": nst, "l2": list(err)}))
+            emit(json.dumps({"dim": dim, "mode": mode, "n": n, "degree": degree, "L": L, "steps": nst,
+                             "l2": list(err)}))
         out[mode] = (errs, slopes(errs))
-        emit(json.dumps({"mode": mode, "slopes": out[mode][1]}))
+        emit(json.dumps({"dim": dim, "mode": mode, "slopes": out[mode][1]}))
     return out
 
 
@@ -115,7 +125,7 @@ def paper_sweep(modes, ns, degree=2, L=4, parts=16, t_end=4.0, emit=print):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--setting", choices=["periodic", "paper"], default="periodic")
+    ap.add_argument("--setting", choices=["periodic", "wave3d", "paper"], default="periodic")
     ap.add_argument("--ns", type=int, nargs="+", default=[32, 64, 128, 256])
     ap.add_argument("--degree", type=int, default=None)
     ap.add_argument("--L", type=int, default=None)
@@ -129,6 +139,9 @@ def main():
     if a.setting == "paper":
         paper_sweep(a.modes or list(PAPER_MODES), a.ns, a.degree or 2, a.L or 4, a.parts or 16, a.t_end or 4.0,
                     emit=emit)
+    elif a.setting == "wave3d":
+        sweep(a.modes or list(MODES), a.ns, a.degree or 2, a.L or 2, a.parts or 4, a.t_end or 0.25, a.cfl, a.r,
+              emit=emit, dim=3)
     else:
         sweep(a.modes or list(MODES), a.ns, a.degree or 3, a.L or 3, a.parts or 8, a.t_end or 1.0, a.cfl, a.r,
               emit=emit)

@@ -54,3 +54,20 @@ def test_paper_setting_caa_at_matches_sync_caa_std_first_order(degree):
     np.testing.assert_allclose(e_at, e_sync, rtol=0.05)
     assert np.all(s_std[-1] < 1.2)                  # first order with the standard flux
     assert np.all(e_std[-1] > 5 * e_sync[-1])
+
+
+def test_wave3d_at_recovers_order_stale_does_not():
+    # the hexahedron kernels: density wave on the unit cube, p = 2, 4^3
+    # subdomains, uniform delays up to L = 2, t = 0.25
+    from paper_2603_28710_amd import convergence as C
+
+    say("case: density wave 3D p=2, n = 8, 16, 32, sync / stale / AT3, uniform L=2")
+    res = C.sweep(["sync", "stale_uniform", "at3_uniform"], [8, 16, 32], degree=2, L=2, parts=4, t_end=0.25,
+                  emit=say, dim=3)
+    e_sync, s_sync = (np.array(x) for x in res["sync"])
+    e_st, s_st = (np.array(x) for x in res["stale_uniform"])
+    e_at, s_at = (np.array(x) for x in res["at3_uniform"])
+    assert np.all(s_sync[-1] > 2.8)
+    assert np.all(s_at[-1] > 2.8)
+    np.testing.assert_allclose(e_at, e_sync, rtol=0.01)
+    assert np.all(s_st[-1] < 1.2)
