@@ -201,12 +201,15 @@ adg_status adg_delay(adg_ctx ctx, int64_t n, int32_t sub, int32_t dir, int32_t* 
  * [-1, 1]. Any pointer may be NULL. */
 adg_status adg_basis(adg_ctx ctx, double* gll_x, double* gll_w, double* gauss_x, double* gauss_w);
 
-/* Kernel timing with HIP events. With enable != 0 the library records a pair
- * of library-owned events on its stream around every launch of the stage
- * kernels; adg_profile_read synchronises the stream and returns, for kernel
- * ADG_KERNEL_RHS (fused right-hand-side stage) or ADG_KERNEL_GHOST (ring
- * publish + ghost traces), the summed elapsed milliseconds and the number of
- * launches since profiling was enabled. enable == 0 stops recording. */
+/* Kernel timing with HIP events. With enable = k > 0 the library records a
+ * pair of library-owned events on its stream around every launch of the
+ * stage kernels in the steps n with n % k == 0 (k = 1: every launch; a
+ * larger k keeps the events' own cost, a few microseconds per pair, out of
+ * most steps); adg_profile_read synchronises the stream and returns, for
+ * kernel ADG_KERNEL_RHS (fused right-hand-side stage) or ADG_KERNEL_GHOST
+ * (learned ghost traces), the summed elapsed milliseconds and the number of
+ * recorded launches since profiling was enabled. enable == 0 stops
+ * recording; enable < 0 is ADG_ERR_INVALID. */
 #define ADG_KERNEL_RHS 0
 #define ADG_KERNEL_GHOST 1
 adg_status adg_profile(adg_ctx ctx, int32_t enable);

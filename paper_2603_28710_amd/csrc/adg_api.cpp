@@ -207,7 +207,7 @@ adg_status adg::prof_fold(adg_ctx_s* c) {
 
 adg_status adg::prof_begin(adg_ctx_s* c, int kind) {
   auto& P = c->prof;
-  if (!P.on) return ADG_OK;
+  if (!P.on || c->n % P.every) return ADG_OK;
   if (P.used == kProfPairs) {
     adg_status s = prof_fold(c);
     if (s != ADG_OK) return s;
@@ -219,7 +219,7 @@ adg_status adg::prof_begin(adg_ctx_s* c, int kind) {
 
 adg_status adg::prof_end(adg_ctx_s* c) {
   auto& P = c->prof;
-  if (!P.on) return ADG_OK;
+  if (!P.on || c->n % P.every) return ADG_OK;
   HIP_TRY(hipEventRecord(P.ev[2 * P.used + 1], c->stream));
   P.used += 1;
   return ADG_OK;
@@ -609,8 +609,10 @@ adg_status adg_basis(adg_ctx c, double* gll_x, double* gll_w, double* gauss_x, d
 
 adg_status adg_profile(adg_ctx c, int32_t enable) {
   if (!c) return fail(ADG_ERR_INVALID, "null context");
+  if (enable < 0) return fail(ADG_ERR_INVALID, "enable must be >= 0");
   auto& P = c->prof;
   if (enable) {
+    P.every = enable;
     if (P.ev.empty()) {
       P.ev.resize(2 * kProfPairs);
       P.kind.resize(kProfPairs);

@@ -51,6 +51,7 @@ struct adg_ctx_s {
   // event timing of the stage kernels (adg_profile)
   struct Prof {
     bool on = false;
+    int every = 1;               // record the launches of steps n with n % every == 0
     std::vector<hipEvent_t> ev;  // pairs (start, end)
     std::vector<int> kind;       // kernel id per recorded pair
     int used = 0;

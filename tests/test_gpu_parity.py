@@ -266,6 +266,24 @@ def test_checkpoint_resume_bitwise(oracle_mod, S):
     np.testing.assert_array_equal(t.download(), a)
 
 
+def test_profile_samples_every_kth_step(oracle_mod, S, B):
+    # events around the stage launches of steps n % k == 0 only
+    O = oracle_mod
+    say("case: event profiling of every 4th step, 20 steps")
+    s = S(dim=2, degree=2, cells=(32, 32, 1), parts=(2, 2, 1), hi=(10, 10, 1), ghost=2, delay_kind=1, L=2,
+          levels=3)
+    s.init_problem(O.VORTEX)
+    B.adg_profile(s.h, 4)
+    s.step(20, 1e-3)
+    ms, n = B.adg_profile_read(s.h, B.ADG_KERNEL_RHS)
+    B.adg_profile(s.h, 1)
+    s.step(2, 1e-3)
+    ms1, n1 = B.adg_profile_read(s.h, B.ADG_KERNEL_RHS)
+    B.adg_profile(s.h, 0)
+    assert n == 5 * 3 and ms > 0
+    assert n1 == 2 * 3 and ms1 > 0
+
+
 def test_checkpoint_resume_dirichlet_box(oracle_mod, S):
     # the blob carries the boundary problem: the resumed context needs no
     # adg_set_boundary and continues bitwise

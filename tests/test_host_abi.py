@@ -79,6 +79,13 @@ def test_dirichlet_box_rejects_learned_ghosts_and_bad_problems(B):
     B.adg_destroy(h2)
 
 
+def test_profile_rejects_negative_sampling(B):
+    h = B.adg_create(B.make_config(), B.make_async())
+    with pytest.raises(B.AdgError):
+        B.adg_profile(h, -1)
+    B.adg_destroy(h)
+
+
 def test_unbound_calls_fail_cleanly(B):
     h = B.adg_create(B.make_config(), B.make_async())
     assert B.adg_step(h, 1, 1e-3) == B.ADG_ERR_UNBOUND
