@@ -143,9 +143,11 @@ def load_traffic(workload):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, target_s=15.0):
+def cpu_baseline(w, target_s=15.0, cells=None):
     """The FP64 CPU oracle, untuned, on a bounded sample of the same workload:
-    the full mesh, a few steps (as many as fit in about target_s seconds)."""
+    the full mesh (or `cells` elements per direction, same subdomain count),
+    a few steps (as many as fit in about target_s seconds). The thread count
+    is OMP_NUM_THREADS, else the usable cores up to 16."""
     from oracle import oracle as O
 
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
@@ -154,7 +156,8 @@ def cpu_baseline(w, target_s=15.0):
         os.environ["OMP_NUM_THREADS"] = str(threads)
     c, a = w["cfg"], w["asy"]
     integ = c.get("integrator", 0)
-    o = O.Oracle(dim=c["dim"], p=c["degree"], cells=c["cells"], parts=c["parts"], lo=c["lo"], hi=c["hi"],
+    mesh = c["cells"] if cells is None else tuple(cells if k < c["dim"] else 1 for k in range(3))
+    o = O.Oracle(dim=c["dim"], p=c["degree"], cells=mesh, parts=c["parts"], lo=c["lo"], hi=c["hi"],
                  ghost=a["ghost"], delay_kind=a["delay_kind"], L=a["L"], levels=a["levels"], seed=a["seed"],
                  integrator=integ, bc=c.get("boundary", 0), bc_problem=w["problem"], bc_params=w.get("params"))
     o.init_problem(w["problem"], w.get("params"))
@@ -169,7 +172,8 @@ def cpu_baseline(w, target_s=15.0):
     return {"value": o.ndof * (2 if integ in (1, 3) else 3) * n / (t3 - t2), "unit": "DOF-updates/s per RK stage",
             "cores": threads,
             "kind": "oracle",
-            "sample": f"full mesh, {n} {['SSP-RK3', 'LSERK(2,2)', 'LSERK(3,3)', 'SSP-RK2'][integ]} steps after 1 warm-up "
+            "sample": f"{'full mesh' if cells is None else 'mesh %d^%d' % (cells, c['dim'])}, {n} "
+                      f"{['SSP-RK3', 'LSERK(2,2)', 'LSERK(3,3)', 'SSP-RK2'][integ]} steps after 1 warm-up "
                       f"step ({t3 - t2:.1f} s)"}
 
 
@@ -215,7 +219,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="print only the cpu_baseline object of the workload (no GPU)")
+    ap.add_argument("--cpu-cells", type=int, default=None,
+                    help="with --cpu-only: elements per direction of a reduced mesh")
     args = ap.parse_args()
+    if args.cpu_only:
+        out = cpu_baseline(WORKLOADS[args.workload], cells=args.cpu_cells)
+        out["workload"] = args.workload
+        print(json.dumps(out), flush=True)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
