@@ -497,3 +497,44 @@ def test_dirichlet_needs_a_boundary_problem(oracle_mod, S, B):
     s.upload(o.state())
     s.step(5, 1e-3)
     np.testing.assert_allclose(s.download(), o.state(), rtol=0, atol=1e-13)
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_zero_steps_leave_the_state(oracle_mod, S):
+    O = oracle_mod
+    s = S(dim=2, degree=3, cells=(8, 8, 1), parts=(2, 2, 1), hi=(10, 10, 1), ghost=2, delay_kind=1, L=2, levels=3)
+    s.init_problem(O.VORTEX)
+    u0 = s.download()
+    s.step(0, 1e-3)
+    assert s.time() == (0, 0.0)
+    np.testing.assert_array_equal(s.download(), u0)
+
+
+@pytest.mark.parametrize("dim,p,cells,parts,ghost,kind,L", [
+    (2, 2, (1, 1, 1), (1, 1, 1), 0, 0, 0),   # one element, its own neighbour on every face
+    (2, 3, (2, 1, 1), (2, 1, 1), 2, 1, 2),   # both x faces PE faces to the same element
+    (2, 3, (3, 2, 1), (3, 2, 1), 2, 1, 2),   # one element per subdomain: every face a PE face
+    (2, 4, (1, 3, 1), (1, 3, 1), 1, 2, 3),
+    (3, 2, (1, 1, 1), (1, 1, 1), 0, 0, 0),
+    (3, 2, (2, 2, 2), (2, 2, 2), 2, 1, 2),
+    (3, 3, (2, 1, 1), (2, 1, 1), 2, 0, 1),   # lane-pair kernel
+    (3, 4, (1, 1, 2), (1, 1, 2), 5, 2, 3),   # LDS kernel, flux history
+])
+def test_degenerate_meshes(oracle_mod, S, dim, p, cells, parts, ghost, kind, L):
+    O = oracle_mod
+    say(f"case: degenerate mesh dim={dim} p={p} cells={cells} parts={parts} ghost={ghost} kind={kind} L={L}")
+    hi = (1, 1, 1)
+    prob = O.DENSITY_WAVE
+    o = O.Oracle(dim=dim, p=p, cells=cells, parts=parts, hi=hi, ghost=ghost, delay_kind=kind, L=L, levels=3,
+                 seed=3)
+    o.init_problem(prob)
+    o.set_state(o.state() + inputs.perturbation(o.ndof, 31, 1e-3))
+    s = S(dim=dim, degree=p, cells=cells, parts=parts, hi=hi, ghost=ghost, delay_kind=kind, L=L, levels=3, seed=3)
+    s.upload(o.state())
+    dt = 0.5 * o.stable_dt(0.1)
+    o.step(12, dt)
+    s.step(12, dt)
+    r = rel_l2(s.download(), o.state(), dim, s=s)
+    say("  rel L2", r)
+    assert r <= TOL

@@ -79,6 +79,17 @@ def test_dirichlet_box_rejects_learned_ghosts_and_bad_problems(B):
     B.adg_destroy(h2)
 
 
+def test_create_rejects_index_overflow(B):
+    # element and face-side indices are 32-bit on the device
+    with pytest.raises(B.AdgError) as ei:
+        B.adg_create(B.make_config(cells=(65536, 65536, 1)), B.make_async())
+    assert "too many elements" in str(ei.value)
+    with pytest.raises(B.AdgError) as ei:
+        B.adg_create(B.make_config(cells=(32768, 32768, 1), parts=(32768, 32768, 1)),
+                     B.make_async(ghost=2, delay_kind=1, L=1))
+    assert "face-sides" in str(ei.value)
+
+
 def test_profile_rejects_negative_sampling(B):
     h = B.adg_create(B.make_config(), B.make_async())
     with pytest.raises(B.AdgError):
