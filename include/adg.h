@@ -124,7 +124,7 @@ typedef struct adg_config {
   int32_t integrator;  /* ADG_SSPRK3, ADG_LSERK22, ADG_LSERK33 or ADG_SSPRK2 */
   int32_t precision;   /* ADG_FP64 or ADG_FP32_CONTRACT */
   int32_t check_every; /* 0: adg_step never checks the state; k>0: every k steps and at the end */
-  int32_t boundary;    /* ADG_BC_PERIODIC or ADG_BC_DIRICHLET (d = 2, not with ADG_GHOST_LEARNED) */
+  int32_t boundary;    /* ADG_BC_PERIODIC or ADG_BC_DIRICHLET (d = 2) */
 } adg_config;
 
 typedef struct adg_async {

@@ -368,7 +368,7 @@ void* orc_create(const orc_cfg* cfg) {
   s->c = *cfg;
   int D = cfg->dim;
   if (D < 2 || D > 3 || cfg->p < 1 || cfg->p > 5 || cfg->integrator < 0 || cfg->integrator > 3 ||
-      cfg->bc < 0 || cfg->bc > 1 || (cfg->bc && (cfg->bc_problem < 0 || cfg->bc_problem > 2 || cfg->ghost == 3))) {
+      cfg->bc < 0 || cfg->bc > 1 || (cfg->bc && (cfg->bc_problem < 0 || cfg->bc_problem > 2))) {
     free(s);
     return NULL;
   }

@@ -97,8 +97,6 @@ double stage_time(int integrator, int m) {
 
 adg_status check_async(const adg_config& c, const adg_async& a) {
   if (a.ghost < 0 || a.ghost > 5) return fail(ADG_ERR_INVALID, "async.ghost must be 0..5");
-  if (a.ghost == ADG_GHOST_LEARNED && c.boundary == ADG_BC_DIRICHLET)
-    return fail(ADG_ERR_INVALID, "the learned ghost predictor needs a periodic box");
   if (a.ghost >= ADG_GHOST_FLUX_STALE && a.delay_kind != ADG_DELAY_CAA)
     return fail(ADG_ERR_INVALID, "the flux-history modes need the CAA delay schedule");
   if (a.delay_kind < 0 || a.delay_kind > 2) return fail(ADG_ERR_INVALID, "async.delay_kind must be 0..2");

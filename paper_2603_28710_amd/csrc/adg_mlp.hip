@@ -168,12 +168,15 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
   if (valid) {
     int cc[3], f;
     face_side_decode(M, fs, cc, &f);
+    // in a Dirichlet box the slot of a boundary face is never read: it is
+    // neither published nor judged and gives no training pair
+    const bool inner = !M.bc || cc[f >> 1] != ((f & 1) ? M.nc[f >> 1] - 1 : 0);
     const long long nb = neighbour(M, cc, f);
     const long long src = nb * V * Pd + face_node_l<D, P>(f ^ 1, j);
-    if (publish)
+    if (publish && inner)
 #pragma unroll
       for (int v = 0; v < V; ++v) ring[A.slot_n * total + (fs * V + v) * Fn + j] = u_n[src + v * Pd];
-    k = delay_of(M, A, subdomain_of(M, cc), f);
+    k = inner ? delay_of(M, A, subdomain_of(M, cc), f) : 0;
 #pragma unroll
     for (int v = 0; v < V; ++v) live[v] = u_in[src + v * Pd];
     if (k >= 1) {

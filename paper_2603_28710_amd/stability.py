@@ -14,8 +14,7 @@ learned mode trains its network first (pairs from the same mesh and
 schedule at CFL 0.1), then runs with an accept bound of LEARNED_TOL.
 Settings: "periodic" (default) is the vortex of mean flow (1,1) on the
 periodic box [0,10]^2 with SSP-RK3; "paper" is the paper's own: mean flow
-(1,0) in the Dirichlet box [0,10] x [-5,5], LSERK(p+1,p+1) (the learned
-predictor needs a periodic box and is skipped there).
+(1,0) in the Dirichlet box [0,10] x [-5,5], LSERK(p+1,p+1).
 """
 import argparse
 import json
@@ -121,8 +120,6 @@ def main():
     sync_lo, sync_hi = max_stable_cfl(maker("at_caa", 0), a.t_end)
     print(json.dumps({"mode": "sync", "L": 0, "stable": sync_lo, "unstable": sync_hi}), flush=True)
     for mode in a.modes:
-        if paper and MODES[mode]["ghost"] == 3:
-            continue
         for L in a.L:
             if L == 0 and mode in ("stale_caa", "flux_stale_caa"):
                 continue

@@ -219,3 +219,31 @@ def test_train_on_solver_traces_beats_at(oracle_mod, kind, cfl, max_resid):
     d_le = np.linalg.norm(runs["learned"] - runs["sync"])
     say("  ||AT - sync||", d_at, " ||learned - sync||", d_le)
     assert d_le < d_at
+
+
+def test_learned_mode_in_a_dirichlet_box(oracle_mod):
+    # boundary faces take the exact data; the predictor judges only the PE
+    # faces, as the oracle does
+    O = oracle_mod
+    say("case: learned ghosts, fixed weights, paper vortex Dirichlet box 32x32 p=2 parts 4x4, 14 steps")
+    prm = (5.0, 0.0, 5.0, 1.0, 0.0)
+    cfg = dict(dim=2, cells=(32, 32, 1), parts=(4, 4, 1), lo=(0, -5, 0), hi=(10, 5, 1), ghost=3, delay_kind=2, L=3,
+               levels=3, seed=2, learned_tol=1e-4)
+    o = O.Oracle(p=2, bc=O.DIRICHLET, bc_problem=O.VORTEX, bc_params=prm, **cfg)
+    o.init_problem(O.VORTEX, prm)
+    s = _solver(degree=2, boundary=1, **cfg)
+    w = inputs.mlp_weights(s.predictor_nparams(), 7, 0.2).astype(np.float32)
+    s.predictor_set(w)
+    o.set_predictor(w)
+    s.upload(o.state())
+    s.set_boundary(O.VORTEX, prm)
+    dt = o.stable_dt(0.1)
+    o.step(14, dt)
+    s.step(14, dt)
+    a, b = s.download(), o.state()
+    r = np.linalg.norm(a - b) / np.linalg.norm(b)
+    acc_o, rej_o = o.learned_stats()
+    rate, judged = s.predictor_stats()
+    say("  rel L2", r, "gpu accept", rate, judged, "oracle", acc_o, rej_o)
+    assert r <= 1e-11
+    assert judged == acc_o + rej_o and judged > 0 and abs(rate * judged - acc_o) <= max(1, 1e-3 * judged)

@@ -651,18 +651,18 @@ def test_dirichlet_zero_delay_is_bitwise_synchronous(oracle_mod):
     ref.init_problem(O.VORTEX, PAPER_VORTEX)
     dt = ref.stable_dt(0.1)
     ref.step(10, dt)
-    for ghost, kind, L in ((O.STALE, O.FIXED, 0), (O.AT, O.FIXED, 0), (O.FLUX_STALE, O.CAA, 1),
-                           (O.FLUX_AT, O.CAA, 0)):
+    for ghost, kind, L in ((O.STALE, O.FIXED, 0), (O.AT, O.FIXED, 0), (O.LEARNED, O.FIXED, 0),
+                           (O.FLUX_STALE, O.CAA, 1), (O.FLUX_AT, O.CAA, 0)):
         o = O.Oracle(ghost=ghost, delay_kind=kind, L=L, levels=3, **base)
         o.init_problem(O.VORTEX, PAPER_VORTEX)
         o.step(10, dt)
         np.testing.assert_array_equal(o.state(), ref.state())
 
 
-def test_dirichlet_rejects_learned_ghosts(oracle_mod):
+def test_dirichlet_rejects_unknown_boundary_problem(oracle_mod):
     O = oracle_mod
     with pytest.raises(ValueError):
-        O.Oracle(dim=2, p=2, cells=(8, 8, 1), parts=(2, 2, 1), ghost=O.LEARNED, bc=O.DIRICHLET)
+        O.Oracle(dim=2, p=2, cells=(8, 8, 1), parts=(2, 2, 1), bc=O.DIRICHLET, bc_problem=3)
 
 
 # ---------------------------------------------------------- SSP-RK2 (Heun)
