@@ -17,9 +17,10 @@
  *   - AT extrapolation over past levels with the stage-fractional delay of the
  *     naive RK coupling: Sec. 3.2, eq. at-flux, at-flux-constraints,
  *     Table at-flux-coeffs; applied here to neighbour traces.
- *   - Time integration: explicit SSP-RK3 in Shu-Osher form (default), or the
- *     paper's two-register LSERK(2,2) / LSERK(3,3) of Sec. 2.3 (eq. lserk-dg,
- *     Table lserk-scheme; stage times from the scheme's own a and b).
+ *   - Time integration: explicit SSP-RK3 in Shu-Osher form (default),
+ *     SSP-RK2, or the paper's two-register LSERK(2,2) / LSERK(3,3) of
+ *     Sec. 2.3 (eq. lserk-dg, Table lserk-scheme; stage times from the
+ *     scheme's own a and b).
  *   - Boundaries: a periodic box (default), or, for d = 2, the Dirichlet box of
  *     the paper's vortex test (Sec. 5.1), whose boundary data come from the
  *     exact solution.
@@ -153,7 +154,7 @@ adg_status adg_create(const adg_config* cfg, const adg_async* async, void* hip_s
  * reductions. */
 adg_status adg_sizes(adg_ctx ctx, size_t* n_dof, size_t* state_bytes, size_t* ring_bytes, size_t* scratch_bytes);
 
-/* Bind caller-owned device buffers: the three SSP-RK3 registers (u_n holds
+/* Bind caller-owned device buffers: the three state registers (u_n holds
  * the solution between steps; u_a is also used as staging by adg_diff_norm),
  * the ring (may be NULL if ring_bytes == 0) and the scratch area, all at least
  * the sizes of adg_sizes, 256-byte aligned. The first bind allocates and
@@ -182,10 +183,11 @@ adg_status adg_set_boundary(adg_ctx ctx, int32_t problem, const double* params);
  * the warm-up clamp counts from the current step. */
 adg_status adg_set_async(adg_ctx ctx, const adg_async* async);
 
-/* Advance n_steps SSP-RK3 steps of fixed size dt (> 0). Asynchronous on the
- * stream unless check_every > 0, in which case the state is checked (finite,
- * rho > 0, p > 0) every check_every steps and at the end of the call, with a
- * blocking read of one flag: ADG_ERR_NONFINITE / ADG_ERR_NONPHYSICAL. */
+/* Advance n_steps steps of the configured integrator, of fixed size dt (> 0;
+ * n_steps == 0 does nothing). Asynchronous on the stream unless
+ * check_every > 0, in which case the state is checked (finite, rho > 0,
+ * p > 0) every check_every steps and at the end of the call, with a blocking
+ * read of one flag: ADG_ERR_NONFINITE / ADG_ERR_NONPHYSICAL. */
 adg_status adg_step(adg_ctx ctx, int64_t n_steps, double dt);
 
 /* Delay k (in steps) that the receiving subdomain `sub` uses at step n for
