@@ -18,7 +18,8 @@ recovers the synchronous curve and its order p + 1. Three settings:
   or DG(2) with LSERK(3,3) and AT3, CFL 0.05 for the synchronous and AT
   schemes and 0.03 for the standard flux. Both readings of what is delayed
   run: neighbour traces ("caa_std", "caa_at") and the stored fluxes of the
-  algorithms themselves ("flux_caa_std", "flux_caa_at").
+  algorithms themselves ("flux_caa_std", "flux_caa_at"); "learned_caa" adds
+  the learned predictor over AT, trained on each mesh first.
 
     python -m paper_2603_28710_amd.convergence [--setting paper|wave3d] [--ns 32 64 128 256] [--degree 2]
 
@@ -41,17 +42,27 @@ PAPER_MODES = {
     "caa_at": dict(ghost=2, delay_kind=2, cfl=0.05),
     "flux_caa_std": dict(ghost=4, delay_kind=2, cfl=0.03),
     "flux_caa_at": dict(ghost=5, delay_kind=2, cfl=0.05),
+    # the learned predictor over AT (caa-at schedule), its network trained on
+    # the same mesh first (stability.train_predictor), accept bound 1e-4
+    "learned_caa": dict(ghost=3, delay_kind=2, cfl=0.05, learned_tol=1e-4),
 }
 
 
-def _run(n, degree, asy, box, t_end, dt_of, seed=0):
-    """L2 errors (density, momentum, energy) at t_end on the n^d mesh with
-    the time step dt_of(n), and the number of steps"""
+def _make(n, degree, asy, box, seed=0, weights=None):
     from paper_2603_28710_amd.solver import Solver
 
     dim = box.get("dim", 2)
     s = Solver(dim=dim, degree=degree, cells=(n, n, n if dim == 3 else 1), seed=seed, **box["cfg"], **asy)
+    if weights is not None:
+        s.predictor_set(weights)
     s.init_problem(box["problem"], box["params"])
+    return s
+
+
+def _run(n, degree, asy, box, t_end, dt_of, seed=0, weights=None):
+    """L2 errors (density, momentum, energy) at t_end on the n^d mesh with
+    the time step dt_of(n), and the number of steps"""
+    s = _make(n, degree, asy, box, seed, weights)
     dt = dt_of(n)
     nst = int(math.ceil(t_end / dt))
     s.step(nst, t_end / nst)
@@ -114,7 +125,12 @@ def paper_sweep(modes, ns, degree=2, L=4, parts=16, t_end=4.0, emit=print):
         m["levels"] = 1 if m["ghost"] in (1, 4) else degree + 1
         errs = []
         for n in ns:
-            err, nst = _run(n, degree, m, box, t_end, lambda k: _stable_dt(k, degree, box, cfl))
+            w = None
+            if m["ghost"] == 3:
+                from paper_2603_28710_amd.stability import train_predictor
+
+                w = train_predictor(lambda: _make(n, degree, m, box), cfl)
+            err, nst = _run(n, degree, m, box, t_end, lambda k: _stable_dt(k, degree, box, cfl), weights=w)
             errs.append(list(err))
             emit(json.dumps({"setting": "paper", "mode": mode, "n": n, "degree": degree, "L": m["L"], "cfl": cfl,
                              "steps": nst, "l2": list(err)}))
