@@ -195,9 +195,17 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
   const long long ring_level = M.nfs * V * (flux_mode ? Q : P);  // values per ring level
   const bool publish = src == kSrcRing && A.stage == 0;
 
+  // u^n for the combine (SSP stages 2 and 3), loaded at the start of the
+  // last face pass so that its latency hides behind the y faces (FP64,
+  // degree <= 3: elsewhere the registers would cost occupancy)
+  constexpr bool kEarlyUn = sizeof(T) == 8 && P <= 4;
+  double un[Pd];
+  const bool need_un = kEarlyUn && valid && !S.lserk && S.a != 0.0;
+
   // ---- faces, one axis per pass
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
+    if (a == 1 && need_un) load_col<P>(u_n + col, un);
     __syncthreads();  // sX is rewritten
     // own and neighbour traces of variable v at the Gauss points of both faces
 #pragma unroll
@@ -385,8 +393,7 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
 #pragma unroll
       for (int i = 0; i < Pd; ++i) o[i] = S.b * (u[i] + S.dt * (double)k[i]);
     } else {
-      double un[Pd];
-      load_col<P>(u_n + col, un);
+      if (!kEarlyUn) load_col<P>(u_n + col, un);
 #pragma unroll
       for (int i = 0; i < Pd; ++i) o[i] = S.a * un[i] + S.b * (u[i] + S.dt * (double)k[i]);
     }
