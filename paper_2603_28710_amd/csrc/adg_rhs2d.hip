@@ -195,12 +195,14 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
   const long long ring_level = M.nfs * V * (flux_mode ? Q : P);  // values per ring level
   const bool publish = src == kSrcRing && A.stage == 0;
 
-  // u^n for the combine (SSP stages 2 and 3), loaded at the start of the
-  // last face pass so that its latency hides behind the y faces (FP64,
-  // degree <= 3: elsewhere the registers would cost occupancy)
+  // u^n for the combine (SSP stages 2 and 3; the accumulator w of the LSERK
+  // stages after the first), loaded at the start of the last face pass so
+  // that its latency hides behind the y faces (FP64, degree <= 3: elsewhere
+  // the registers would cost occupancy). Only this element reads its column
+  // of u_n, and it writes it only in the combine.
   constexpr bool kEarlyUn = sizeof(T) == 8 && P <= 4;
   double un[Pd];
-  const bool need_un = kEarlyUn && valid && !S.lserk && S.a != 0.0;
+  const bool need_un = kEarlyUn && valid && (S.lserk ? u_n != u_in : S.a != 0.0);
 
   // ---- faces, one axis per pass
 #pragma unroll
@@ -376,6 +378,9 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
     if (u_n == u_in) {
 #pragma unroll
       for (int i = 0; i < Pd; ++i) wv[i] = u[i];
+    } else if (kEarlyUn) {
+#pragma unroll
+      for (int i = 0; i < Pd; ++i) wv[i] = un[i];
     } else {
       load_col<P>(u_n + col, wv);
     }
