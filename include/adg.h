@@ -135,6 +135,9 @@ typedef struct adg_async {
   int32_t levels;     /* AT levels (order), 1..4 */
   uint64_t seed;      /* seed of the uniform delay draws */
   double learned_tol; /* accept bound on the learned correction (physical units), e.g. 1e-6 */
+  int32_t learned_judge; /* 0: a face's correction is accepted iff max|d| <= learned_tol;
+                            1: also iff max|d| <= max|AT over 4 levels - AT over 3 levels| on
+                            the face, the extrapolation's own error estimate */
 } adg_async;
 
 typedef struct adg_ctx_s* adg_ctx;

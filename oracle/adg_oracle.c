@@ -793,13 +793,19 @@ static void ghost_face(orc_solver* s, const double* uin, int64_t e, int f, int s
   int Fn = s->Fn;
   double gn[64 * MAXV], dn[64 * MAXV];
   double T[8 * MAXV];
-  double maxd = 0.0;
+  double maxd = 0.0, est = 0.0;
+  double c3[MAXN], c4[MAXN];
+  orc_at_weights(3, tau, c3);
+  orc_at_weights(4, tau, c4);
   for (int j = 0; j < Fn; ++j) {
     for (int l = 0; l < K_MLP; ++l) trace_node(s, level_state(s, s->n - k - l), nb, fn, j, T + l * V);
     for (int v = 0; v < V; ++v) {
-      double a = 0.0;
+      double a = 0.0, a3 = 0.0, a4 = 0.0;
       for (int l = 0; l < lev; ++l) a += c[l] * T[l * V + v];
+      for (int l = 0; l < 3; ++l) a3 += c3[l] * T[l * V + v];
+      for (int l = 0; l < 4; ++l) a4 += c4[l] * T[l * V + v];
       gn[j * V + v] = a;
+      if (fabs(a4 - a3) > est) est = fabs(a4 - a3);
     }
     double x[32], y[MAXV], S3;
     orc_learned_features(s, T, tau, stage_time(s, stage), x, &S3);
@@ -813,7 +819,7 @@ static void ghost_face(orc_solver* s, const double* uin, int64_t e, int f, int s
       if (fabs(dn[j * V + v]) > maxd || dn[j * V + v] != dn[j * V + v]) maxd = fabs(dn[j * V + v]);
     }
   }
-  int accept = s->has_mlp && maxd <= s->c.learned_tol;
+  int accept = s->has_mlp && maxd <= s->c.learned_tol && (!s->c.learned_judge || maxd <= est);
 #pragma omp atomic
   s->acc += accept;
 #pragma omp atomic

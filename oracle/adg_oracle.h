@@ -49,6 +49,9 @@ typedef struct orc_cfg {
   int32_t bc_problem;   /* ORC_* problem that supplies the boundary data */
   int32_t bc_prm_set;   /* 0: the problem's default parameters; 1: bc_prm */
   double bc_prm[5];     /* parameters, as for orc_init_problem */
+  int32_t learned_judge; /* 0: accept a face's correction iff max|d| <= learned_tol; 1: also
+                            iff max|d| <= max|AT over 4 levels - AT over 3 levels| on the
+                            face, the extrapolation's own error estimate (reading) */
 } orc_cfg;
 
 enum { ORC_VORTEX = 0, ORC_DENSITY_WAVE = 1, ORC_CONSTANT = 2 };

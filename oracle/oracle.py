@@ -27,7 +27,7 @@ class OrcCfg(C.Structure):
         ("delay_kind", C.c_int32), ("L", C.c_int32), ("levels", C.c_int32),
         ("seed", C.c_uint64), ("learned_tol", C.c_double), ("integrator", C.c_int32),
         ("bc", C.c_int32), ("bc_problem", C.c_int32), ("bc_prm_set", C.c_int32),
-        ("bc_prm", C.c_double * 5),
+        ("bc_prm", C.c_double * 5), ("learned_judge", C.c_int32),
     ]
 
 
@@ -128,7 +128,7 @@ class Oracle:
 
     def __init__(self, dim=2, p=2, nq=0, cells=(16, 16, 1), parts=(1, 1, 1), lo=(0, 0, 0),
                  hi=(10, 10, 1), gamma=1.4, flux=LLF, ghost=SYNC, delay_kind=FIXED, L=0, levels=3,
-                 seed=0, learned_tol=1e-6, integrator=0, bc=0, bc_problem=0, bc_params=None):
+                 seed=0, learned_tol=1e-6, integrator=0, bc=0, bc_problem=0, bc_params=None, learned_judge=0):
         c = OrcCfg()
         c.dim, c.p, c.nq = dim, p, nq
         for k in range(3):
@@ -143,6 +143,7 @@ class Oracle:
         # the exact solution of bc_problem (bc_params, or its defaults)
         c.bc, c.bc_problem = bc, bc_problem
         c.bc_prm_set = 0 if bc_params is None else 1
+        c.learned_judge = learned_judge
         if bc_params is not None:
             for i in range(5):
                 c.bc_prm[i] = float(bc_params[i])

@@ -34,7 +34,8 @@ class adg_config(C.Structure):
 
 class adg_async(C.Structure):
     _fields_ = [("ghost", C.c_int32), ("delay_kind", C.c_int32), ("L", C.c_int32),
-                ("levels", C.c_int32), ("seed", C.c_uint64), ("learned_tol", C.c_double)]
+                ("levels", C.c_int32), ("seed", C.c_uint64), ("learned_tol", C.c_double),
+                ("learned_judge", C.c_int32)]
 
 
 class AdgError(RuntimeError):
@@ -296,7 +297,9 @@ def make_config(dim=2, degree=2, cells=(16, 16, 1), parts=(1, 1, 1), lo=(0, 0, 0
     return c
 
 
-def make_async(ghost=ADG_GHOST_SYNC, delay_kind=ADG_DELAY_FIXED, L=0, levels=3, seed=0, learned_tol=1e-6):
+def make_async(ghost=ADG_GHOST_SYNC, delay_kind=ADG_DELAY_FIXED, L=0, levels=3, seed=0, learned_tol=1e-6,
+               learned_judge=0):
     a = adg_async()
     a.ghost, a.delay_kind, a.L, a.levels, a.seed, a.learned_tol = ghost, delay_kind, L, levels, seed, learned_tol
+    a.learned_judge = learned_judge
     return a

@@ -105,6 +105,7 @@ adg_status check_async(const adg_config& c, const adg_async& a) {
   if ((a.ghost == 1 || a.ghost == 4) && a.delay_kind == 2 && a.L < 1)
     return fail(ADG_ERR_INVALID, "CAA with a stale trace or flux needs L >= 1");
   if (!(a.learned_tol >= 0.0)) return fail(ADG_ERR_INVALID, "async.learned_tol must be >= 0");
+  if (a.learned_judge != 0 && a.learned_judge != 1) return fail(ADG_ERR_INVALID, "async.learned_judge must be 0 or 1");
   return ADG_OK;
 }
 
@@ -143,6 +144,7 @@ Async make_async(const adg_ctx_s* c, int stage) {
   A.stage = stage;
   A.c_m = stage_time(c->cfg.integrator, stage);
   A.tol = c->as.learned_tol;
+  A.judge = c->as.learned_judge;
   A.slot_n = c->R > 0 ? (int)(c->n % c->R) : 0;
   unsigned mod = 1;
   if (A.delay_kind == 1) mod = A.L + 1;

@@ -119,6 +119,7 @@ struct Async {
   int stage;
   double c_m;        // stage time fraction
   double tol;        // learned accept bound
+  int judge;         // 1: the correction must also stay within |AT4 - AT3| on the face
   int slot_n;        // ring slot of level n (n mod R), 0 without a ring
   FastMod64 kmod;    // the delay schedule's modulus: L+1 uniform, L caa-std, L+Qh caa-at
 };

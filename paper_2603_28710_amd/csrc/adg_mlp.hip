@@ -152,6 +152,7 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
   constexpr int NFW = 64 / Fn;  // face-sides per wavefront
   __shared__ float s_io[4][64][17];  // per wavefront and node: features, then outputs
   __shared__ double s_max[4][64];
+  __shared__ double s_est[4][64];  // |AT4 - AT3| per node (the second judge)
   __shared__ int s_acc[4][64];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const long long fs = ((long long)blockIdx.x * 4 + w) * NFW + lane / Fn;
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
   const bool valid = lane < NFW * Fn && fs < M.nfs;
   const long long total = M.nfs * V * Fn;
   int k = 0;
-  double at[V], live[V], S3 = 0.0;
+  double at[V], live[V], S3 = 0.0, est = 0.0;
   float x[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) x[i] = 0.0f;
@@ -193,6 +194,20 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
 #pragma unroll
           for (int v = 0; v < V; ++v) at[v] += wl * T[lv][v];
         }
+      }
+      if (A.judge) {
+        // AT over 4 levels minus AT over 3: the extrapolation's error estimate
+        double d[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) d[v] = 0.0;
+#pragma unroll
+        for (int lv = 0; lv < kMlpK; ++lv) {
+          const double w4 = at_weight(lv, 4, tau), w3 = lv < 3 ? at_weight(lv, 3, tau) : 0.0;
+#pragma unroll
+          for (int v = 0; v < V; ++v) d[v] += (w4 - w3) * T[lv][v];
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) est = fabs(d[v]) > est ? fabs(d[v]) : est;
       }
       // second and third backward differences (no contraction: the features
       // are bit-reproducible), both scaled by S = max|second| + max|third|
@@ -242,17 +257,19 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
     if (!(fabs(dl[v]) <= mx)) mx = fabs(dl[v]);
   }
   s_max[w][lane] = (valid && k >= 1) ? mx : 0.0;
+  s_est[w][lane] = est;
   __syncthreads();
   // per face-side judge (its first node's lane), counted per wavefront
   int acc = 0, judged = 0;
   if (valid && j == 0) {
-    double mm = 0.0;
+    double mm = 0.0, me = 0.0;
 #pragma unroll
     for (int q = 0; q < Fn; ++q) {
       const double v = s_max[w][lane + q];
       if (!(v <= mm)) mm = v;
+      me = s_est[w][lane + q] > me ? s_est[w][lane + q] : me;
     }
-    acc = use_net && (mm <= A.tol);
+    acc = use_net && (mm <= A.tol) && (!A.judge || mm <= me);
     judged = k >= 1 && use_net;
     s_acc[w][lane] = acc;
   }

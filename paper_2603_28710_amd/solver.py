@@ -19,7 +19,7 @@ def _aligned_empty(nbytes, device):
 
 class Solver:
     def __init__(self, device="cuda:0", stream=None, **cfg):
-        asy = {k: cfg.pop(k) for k in ("ghost", "delay_kind", "L", "levels", "seed", "learned_tol")
+        asy = {k: cfg.pop(k) for k in ("ghost", "delay_kind", "L", "levels", "seed", "learned_tol", "learned_judge")
                if k in cfg}
         self.cfg = B.make_config(**cfg)
         self.asy = B.make_async(**asy)

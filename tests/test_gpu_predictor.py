@@ -109,8 +109,9 @@ def test_learned_mode_parity_with_oracle(oracle_mod):
     assert judged == acc_o + rej_o and abs(rate * judged - acc_o) <= max(1, 1e-3 * judged)
 
 
-@pytest.mark.parametrize("bias,tol,expect", [(1e20, 1e-6, "reject"), (1.0, 1e-6, "mixed")])
-def test_learned_judge_matches_oracle(oracle_mod, bias, tol, expect):
+@pytest.mark.parametrize("bias,tol,expect,judge", [(1e20, 1e-6, "reject", 0), (1.0, 1e-6, "mixed", 0),
+                                                   (1.0, 1e-6, "mixed", 1)])
+def test_learned_judge_matches_oracle(oracle_mod, bias, tol, expect, judge):
     # W2 = 0 and a constant output bias b make every correction exactly S * b
     # on both sides, so accept (max |S b| <= tol per face) is decided on the
     # same numbers up to the state's round-off. b = 1e20 rejects every face of
@@ -120,7 +121,7 @@ def test_learned_judge_matches_oracle(oracle_mod, bias, tol, expect):
     O = oracle_mod
     say(f"case: learned judge, constant correction bias={bias} tol={tol}")
     cfg = dict(dim=2, cells=(32, 32, 1), parts=(4, 4, 1), hi=(1, 1, 1), delay_kind=1, L=3, levels=3, seed=3,
-               ghost=3, learned_tol=tol)
+               ghost=3, learned_tol=tol, learned_judge=judge)
     s = _solver(degree=3, **cfg)
     w = np.zeros(s.predictor_nparams(), dtype=np.float32)
     w[-4:] = bias

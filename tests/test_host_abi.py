@@ -54,7 +54,7 @@ def test_create_rejects_bad_config(B, kw, msg):
 @pytest.mark.parametrize("kw", [dict(ghost=6), dict(delay_kind=4), dict(L=17), dict(levels=0),
                                 dict(levels=5), dict(ghost=1, delay_kind=2, L=0),
                                 dict(ghost=4, delay_kind=0, L=2), dict(ghost=5, delay_kind=1, L=2),
-                                dict(ghost=4, delay_kind=2, L=0)])
+                                dict(ghost=4, delay_kind=2, L=0), dict(ghost=3, learned_judge=2)])
 def test_create_rejects_bad_async(B, kw):
     with pytest.raises(B.AdgError):
         B.adg_create(B.make_config(), B.make_async(**kw))

@@ -712,3 +712,33 @@ def test_ssprk2_at_recovers_sync_stale_does_not(oracle_mod):
     d_at = np.linalg.norm(runs["at"] - runs["sync"])
     d_st = np.linalg.norm(runs["stale"] - runs["sync"])
     assert d_at < 0.05 * d_st
+
+
+def test_learned_judge_with_at_error_estimate_accepts_a_subset(oracle_mod):
+    # with learned_judge = 1 a face's correction must also stay within
+    # |AT4 - AT3| on the face: the accepted faces are a subset, the judged
+    # ones the same; a constant output bias makes every correction S * b
+    O = oracle_mod
+    cfg = dict(dim=2, p=3, cells=(32, 32, 1), parts=(4, 4, 1), hi=(1, 1, 1), ghost=O.LEARNED, delay_kind=O.UNIFORM,
+               L=3, levels=3, seed=3, learned_tol=1e-6)
+    counts = {}
+    for judge in (0, 1):
+        o = O.Oracle(learned_judge=judge, **cfg)
+        o.init_problem(O.DENSITY_WAVE)
+        o.set_predictor(_bias_net(_nparams(O), 1.0))
+        dt = o.stable_dt(0.1)
+        o.step(12, dt)
+        counts[judge] = o.learned_stats()
+    (a0, r0), (a1, r1) = counts[0], counts[1]
+    assert a0 + r0 == a1 + r1 > 0
+    assert 0 <= a1 <= a0 and a0 > 0
+
+
+def _nparams(O):
+    return O.lib().orc_mlp_nparams(10, 64, 4)
+
+
+def _bias_net(n, b):
+    w = np.zeros(n, dtype=np.float32)
+    w[-4:] = b
+    return w
