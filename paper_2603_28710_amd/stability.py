@@ -29,6 +29,9 @@ MODES = {
     # the learned predictor over AT, trained first on the same mesh and
     # schedule (see train_predictor); its accept bound is LEARNED_TOL
     "learned_caa": dict(ghost=3, delay_kind=2),
+    # the same with the second judge: corrections within AT's own error
+    # estimate only
+    "learned_judged_caa": dict(ghost=3, delay_kind=2, learned_judge=1),
 }
 LEARNED_TOL = 1e-4
 PAPER_VORTEX = (5.0, 0.0, 5.0, 1.0, 0.0)
