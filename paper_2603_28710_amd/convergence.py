@@ -45,6 +45,8 @@ PAPER_MODES = {
     # the learned predictor over AT (caa-at schedule), its network trained on
     # the same mesh first (stability.train_predictor), accept bound 1e-4
     "learned_caa": dict(ghost=3, delay_kind=2, cfl=0.05, learned_tol=1e-4),
+    # the same with the second judge (corrections within AT's own error estimate)
+    "learned_judged_caa": dict(ghost=3, delay_kind=2, cfl=0.05, learned_tol=1e-4, learned_judge=1),
 }
 
 
