@@ -274,6 +274,9 @@ typedef struct {
   int has_mlp, nin, nh, nout;
   float* mlp;
   int64_t acc, rej;
+  /* test hook: training pairs of the learned mode as the run produces them */
+  double* rec;
+  int64_t rec_cap, rec_n;
 } orc_solver;
 
 static const int K_MLP = 4;   /* past levels the learned predictor reads */
@@ -620,6 +623,12 @@ static void num_flux(const orc_solver* s, const double* wm, const double* wp, in
   for (int v = 0; v < V; ++v) out[v] = 0.5 * (Fm[v] + Fp[v]) * sigma + 0.5 * lam * (wm[v] - wp[v]);
 }
 
+/* the numerical flux of the solver's configuration (gamma, flux kind) for
+ * two states, as every face of a run evaluates it */
+void orc_numerical_flux(void* vs, const double* wm, const double* wp, int a, double sigma, double* out) {
+  num_flux((const orc_solver*)vs, wm, wp, a, sigma, out);
+}
+
 /* ------------------------------------------------------------------------ */
 /* delays (reading: per step n, receiving subdomain, face direction)        */
 /* ------------------------------------------------------------------------ */
@@ -809,6 +818,26 @@ static void ghost_face(orc_solver* s, const double* uin, int64_t e, int f, int s
     }
     double x[32], y[MAXV], S3;
     orc_learned_features(s, T, tau, stage_time(s, stage), x, &S3);
+    if (s->rec) {
+      /* test hook: the pair this node gives, (features, (live - AT) / S) */
+      double live[MAXV];
+      trace_node(s, uin, nb, fn, j, live);
+      int64_t slot;
+#pragma omp atomic capture
+      slot = s->rec_n++;
+      if (slot < s->rec_cap) {
+        const int nr = 6 + s->nin + V;
+        double* r = s->rec + slot * nr;
+        r[0] = (double)s->n;
+        r[1] = stage;
+        r[2] = (double)e;
+        r[3] = f;
+        r[4] = j;
+        r[5] = k;
+        for (int i = 0; i < s->nin; ++i) r[6 + i] = x[i];
+        for (int v = 0; v < V; ++v) r[6 + s->nin + v] = (live[v] - gn[j * V + v]) / S3;
+      }
+    }
     if (s->has_mlp) {
       mlp_bf16_forward(s, x, y);
     } else {
@@ -1370,6 +1399,20 @@ void orc_set_predictor(void* vs, const float* w) {
     s->has_mlp = 0;
   }
 }
+
+/* test hook: while buf is set, every node of a learned-mode ghost face with
+ * delay k >= 1 appends one record of 6 + (2V+2) + V doubles to buf (up to
+ * cap records): step, stage, receiving element, face, face node, k, the
+ * features, and the training target (live neighbour trace - AT) / S. The
+ * order follows the threads; buf == NULL stops recording. */
+void orc_record_pairs(void* vs, double* buf, int64_t cap) {
+  orc_solver* s = (orc_solver*)vs;
+  s->rec = buf;
+  s->rec_cap = buf ? cap : 0;
+  s->rec_n = 0;
+}
+
+int64_t orc_recorded_pairs(void* vs) { return ((orc_solver*)vs)->rec_n; }
 
 void orc_learned_stats(void* vs, int64_t* accepted, int64_t* rejected) {
   orc_solver* s = (orc_solver*)vs;

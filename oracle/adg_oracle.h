@@ -83,6 +83,9 @@ void orc_integrals(void* s, double* out);
 int orc_delay(void* s, int64_t n, int64_t sub, int dir);
 int64_t orc_subdomain(void* s, int64_t e);
 double orc_stable_dt(void* s, double cfl);
+/* n.F^ of the configured flux for n = sigma e_a, seen from the side holding wm
+ * (Sec. 2.2, eq. lfflux, lfflux-lambda) */
+void orc_numerical_flux(void* s, const double* wm, const double* wp, int a, double sigma, double* out);
 
 /* learned ghost predictor (FP64 reference forward/backward) */
 int orc_mlp_nparams(int nin, int nh, int nout);
@@ -95,6 +98,9 @@ void orc_adam(double* w, double* m, double* v, const double* g, int np, double l
 void orc_set_predictor(void* s, const float* w);
 void orc_learned_stats(void* s, int64_t* accepted, int64_t* rejected);
 void orc_learned_features(void* s, const double* T, double tau, double cm, double* x, double* S2);
+/* test hook: record the learned mode's training pairs (see adg_oracle.c) */
+void orc_record_pairs(void* s, double* buf, int64_t cap);
+int64_t orc_recorded_pairs(void* s);
 
 #ifdef __cplusplus
 }

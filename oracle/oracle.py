@@ -79,6 +79,10 @@ def lib():
         L.orc_set_predictor.argtypes = [vp, C.POINTER(C.c_float)]
         L.orc_learned_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.orc_learned_features.argtypes = [vp, dp, C.c_double, C.c_double, dp, dp]
+        L.orc_numerical_flux.argtypes = [vp, dp, dp, C.c_int, C.c_double, dp]
+        L.orc_record_pairs.argtypes = [vp, dp, C.c_int64]
+        L.orc_recorded_pairs.argtypes = [vp]
+        L.orc_recorded_pairs.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -236,6 +240,29 @@ class Oracle:
         a = C.c_int64(); r = C.c_int64()
         lib().orc_learned_stats(self.ptr, C.byref(a), C.byref(r))
         return a.value, r.value
+
+    def numerical_flux(self, wm, wp, a, sigma):
+        """n.F^ for n = sigma e_a seen from the side holding wm, with this
+        solver's gamma and flux kind"""
+        wm = np.ascontiguousarray(wm, dtype=np.float64)
+        wp = np.ascontiguousarray(wp, dtype=np.float64)
+        assert wm.size == self.V and wp.size == self.V
+        out = np.zeros(self.V)
+        lib().orc_numerical_flux(self.ptr, _dp(wm), _dp(wp), int(a), float(sigma), _dp(out))
+        return out
+
+    def record_pairs(self, cap):
+        """start recording the learned mode's training pairs (cap records)"""
+        self._rec = np.zeros((cap, 6 + 2 * self.V + 2 + self.V))
+        lib().orc_record_pairs(self.ptr, _dp(self._rec), int(cap))
+
+    def recorded_pairs(self):
+        """stop recording; rows (step, stage, element, face, node, k,
+        features..., (live - AT) / S ...) in thread order"""
+        n = min(lib().orc_recorded_pairs(self.ptr), len(self._rec))
+        lib().orc_record_pairs(self.ptr, None, 0)
+        out, self._rec = self._rec[:n].copy(), None
+        return out
 
     def learned_features(self, T, tau, cm):
         T = np.ascontiguousarray(T, dtype=np.float64)

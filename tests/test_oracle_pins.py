@@ -742,3 +742,155 @@ def _bias_net(n, b):
     w = np.zeros(n, dtype=np.float32)
     w[-4:] = b
     return w
+
+
+# ------------------------------------------- numerical flux, hand-evaluated
+
+def _frac(t):
+    from fractions import Fraction
+    return float(Fraction(t))
+
+
+def _flux_cases():
+    out = []
+    with open(os.path.join(GOLDEN, "llf_flux.txt")) as f:
+        for ln in f:
+            ln = ln.strip()
+            if not ln or ln.startswith("#"):
+                continue
+            head, wm, wp, exp = [p.split() for p in ln.split("|")]
+            out.append((int(head[0]), head[1], int(head[2]), float(head[3]), [_frac(t) for t in wm],
+                        [_frac(t) for t in wp], [_frac(t) for t in exp]))
+    return out
+
+
+@pytest.mark.parametrize("dim,kind,a,sigma,wm,wp,expect", _flux_cases())
+def test_numerical_flux_hand_evaluated(oracle_mod, dim, kind, a, sigma, wm, wp, expect):
+    """eq. lfflux with lambda of eq. lfflux-lambda (the factor 1/2 included)
+    and the Rusanov option, against exact values at states where
+    sqrt(|u|^2 + c^2) is an integer (tests/golden/llf_flux.txt). Dropping the
+    1/2 of eq. lfflux-lambda doubles the dissipation term and moves every
+    value by (lambda/2) |w- - w+|."""
+    O = oracle_mod
+    o = O.Oracle(dim=dim, p=1, cells=(2, 2, 2 if dim == 3 else 1), parts=(1, 1, 1), gamma=1.4,
+                 flux=O.LLF if kind == "llf" else O.RUSANOV)
+    got = o.numerical_flux(wm, wp, a, sigma)
+    scale = max(1.0, np.abs(expect).max())
+    np.testing.assert_allclose(got, expect, rtol=0, atol=2e-14 * scale)
+
+
+def test_numerical_flux_golden_separates_the_readings(oracle_mod):
+    """the fixture distinguishes the printed lambda from the same formula
+    without its 1/2 (the plausible slip) and from the Rusanov speed"""
+    O = oracle_mod
+    for dim, kind, a, sigma, wm, wp, expect in _flux_cases():
+        if kind != "llf":
+            continue
+        wm, wp = np.array(wm), np.array(wp)
+        o = O.Oracle(dim=dim, p=1, cells=(2, 2, 2 if dim == 3 else 1), flux=O.LLF)
+        central = o.numerical_flux(wm, wm, a, sigma) + o.numerical_flux(wp, wp, a, sigma)
+        diss = np.array(expect) - 0.5 * central        # (lambda/2)(w- - w+)
+        lam = 2.0 * diss[0] / (wm[0] - wp[0])
+        # lambda from the fixture is half the largest sqrt(|u|^2 + c^2)
+        def speed(w):
+            u = w[1:dim + 1] / w[0]
+            p = 0.4 * (w[-1] - 0.5 * w[0] * u @ u)
+            return math.sqrt(u @ u + 1.4 * p / w[0])
+        assert abs(lam - 0.5 * max(speed(wm), speed(wp))) < 1e-12
+        # the dissipation term, which a missing 1/2 would double, is far
+        # above the tolerance of the fixture test in every case
+        assert np.abs(diss).max() > 0.1
+
+
+def test_numerical_flux_consistent_and_antisymmetric(oracle_mod):
+    """F^(w, w; n) = F(w).n and F^(a, b; n) = -F^(b, a; -n) (Sec. 2.2)"""
+    O = oracle_mod
+    rng = np.random.default_rng(11)
+    for dim in (2, 3):
+        o = O.Oracle(dim=dim, p=1, cells=(2, 2, 2 if dim == 3 else 1), flux=O.LLF)
+        for _ in range(5):
+            rho = rng.uniform(0.5, 2.0, 2)
+            u = rng.uniform(-1, 1, (2, dim))
+            p = rng.uniform(0.5, 2.0, 2)
+            w = [np.concatenate([[rho[i]], rho[i] * u[i], [p[i] / 0.4 + 0.5 * rho[i] * u[i] @ u[i]]])
+                 for i in range(2)]
+            for a in range(dim):
+                f_self = o.numerical_flux(w[0], w[0], a, 1.0)
+                fx = np.concatenate([[w[0][1 + a]], w[0][1:dim + 1] * u[0][a], [(w[0][-1] + p[0]) * u[0][a]]])
+                fx[1 + a] += p[0]
+                np.testing.assert_allclose(f_self, fx, rtol=1e-14, atol=1e-14)
+                np.testing.assert_allclose(o.numerical_flux(w[0], w[1], a, 1.0),
+                                           -o.numerical_flux(w[1], w[0], a, -1.0), rtol=1e-14, atol=1e-14)
+
+
+# ------------------------------------- the stage path of the full-size tests
+
+@pytest.mark.parametrize("case", ["periodic2d", "periodic3d", "dirichlet2d"])
+def test_stage_elements_compose_to_one_step(oracle_mod, case):
+    """orc_stage_elements, the per-element SSP-RK3 stage used as reference by
+    the full-size GPU tests, composed over the whole mesh through stages
+    0 -> 1 -> 2 equals one synchronous orc_step (its own face loop, each
+    interior face evaluated once); in a Dirichlet box too."""
+    O = oracle_mod
+    if case == "periodic3d":
+        kw = dict(dim=3, p=2, cells=(4, 3, 5), parts=(1, 1, 1), hi=(1, 1, 1))
+        prob, prm = O.DENSITY_WAVE, None
+    elif case == "periodic2d":
+        kw = dict(dim=2, p=3, cells=(6, 5, 1), parts=(1, 1, 1), hi=(10, 10, 1))
+        prob, prm = O.VORTEX, None
+    else:
+        prm = (5.0, 0.0, 5.0, 1.0, 0.0)
+        kw = dict(dim=2, p=2, cells=(8, 6, 1), parts=(1, 1, 1), lo=(0, -5, 0), hi=(10, 5, 1), bc=O.DIRICHLET,
+                  bc_problem=O.VORTEX, bc_params=prm)
+        prob = O.VORTEX
+    o = O.Oracle(**kw)
+    o.init_problem(prob, prm)
+    u0 = o.state() + inputs.perturbation(o.ndof, 5, 1e-4)
+    o.set_state(u0)
+    dt = o.stable_dt(0.1)
+    allel = np.arange(o.E, dtype=np.int64)
+    r = O.Oracle(**kw)
+    r.set_state(u0)
+    ua = r.stage_elements(0, dt, u0, u0, allel)
+    ub = r.stage_elements(1, dt, ua, u0, allel)
+    un = r.stage_elements(2, dt, ub, u0, allel)
+    o.step(1, dt)
+    ref = o.state()
+    err = np.abs(un - ref).max() / np.abs(ref).max()
+    assert err <= 1e-15, err
+
+
+def test_stage_elements_subset_equals_whole_mesh(oracle_mod):
+    """a sampled subset of elements gives the same outputs as the whole-mesh
+    call (each element's stage depends only on its own and its face
+    neighbours' data)"""
+    O = oracle_mod
+    o = O.Oracle(dim=3, p=2, cells=(5, 4, 3), parts=(1, 1, 1), hi=(1, 1, 1))
+    o.init_problem(O.DENSITY_WAVE)
+    u0 = o.state() + inputs.perturbation(o.ndof, 6, 1e-4)
+    dt = o.stable_dt(0.1)
+    full = o.stage_elements(1, dt, u0, u0, np.arange(o.E, dtype=np.int64)).reshape(o.E, -1)
+    pick = np.array([0, 7, 13, 41, 59], dtype=np.int64)
+    part = o.stage_elements(1, dt, u0, u0, pick).reshape(len(pick), -1)
+    assert np.array_equal(part, full[pick])
+
+
+# ------------------------------------------------ learned inference in bf16
+
+def test_mlp_forward_bf16_close_to_fp64(oracle_mod):
+    """the oracle's forward in the kernel's precision (bf16 operands, binary32
+    accumulation) stays within 1e-2 of the FP64 forward, relative to the
+    output scale, and is not the FP64 forward itself"""
+    O = oracle_mod
+    V = 5
+    nin, nh = 2 * V + 2, 64
+    w = inputs.mlp_weights(O.mlp_nparams(nin, nh, V), 21, 0.3)
+    x, _ = inputs.mlp_batch(2000, nin, V, 22)
+    yf = O.mlp_forward(w, nin, nh, V, x)
+    yb = O.mlp_forward_bf16(w.astype(np.float32), nin, nh, V, x)
+    rel = np.abs(yb - yf).max() / np.abs(yf).max()
+    assert rel <= 1e-2, rel
+    assert np.abs(yb - yf).max() > 0
+    # a bf16 rounding of ~2^-9 per operand: the typical deviation is far
+    # below the bound, the worst case within it
+    assert np.median(np.abs(yb - yf)) <= 2e-3 * np.abs(yf).max()
