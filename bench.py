@@ -22,10 +22,11 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
-# Workloads (synthetic, analytic initial states). The default is the 2D
-# isentropic vortex on the periodic [0,10]^2 box, 256x256 quads, degree 3,
-# 8x8 virtual subdomains, AT extrapolation over 3 past levels, delays drawn
-# uniformly in {0..3} per step, subdomain and face direction.
+# Workloads (synthetic, analytic initial states). The default is the 3D
+# density wave rho = 1 + 0.2 sin(2 pi (x+y+z-3t)) on the periodic unit cube,
+# 128^3 hexahedra of degree 2 (283 M DoFs), 8x8x8 virtual subdomains, AT
+# extrapolation over 3 past levels, delays drawn uniformly in {0..4} per
+# step, subdomain and face direction.
 WORKLOADS = {
     "vortex256_p3_at3_uniformL3": dict(
         cfg=dict(dim=2, degree=3, cells=(256, 256, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
@@ -43,25 +44,28 @@ WORKLOADS = {
         asy=dict(ghost=0, delay_kind=0, L=0, levels=3, seed=0), problem=0, precision=0),
     "wave64_p3_at3_fixedL2": dict(
         cfg=dict(dim=3, degree=3, cells=(64, 64, 64), parts=(4, 4, 4), lo=(0, 0, 0), hi=(1, 1, 1)),
-        asy=dict(ghost=2, delay_kind=0, L=2, levels=3, seed=0), problem=1, precision=0),
+        asy=dict(ghost=2, delay_kind=0, L=2, levels=3, seed=0), problem=1, precision=0, cpu_cells=16),
     "vortex1024_p4_at3_uniformL3_fp32": dict(
         cfg=dict(dim=2, degree=4, cells=(1024, 1024, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
-        asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=1,
-        reference="vortex1024_p4_at3_uniformL3_fp64"),
+        asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=1, cpu_cells=128),
     "vortex1024_p4_at3_uniformL3_fp64": dict(
         cfg=dict(dim=2, degree=4, cells=(1024, 1024, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1)),
-        asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=0),
+        asy=dict(ghost=2, delay_kind=1, L=3, levels=3, seed=0), problem=0, precision=0, cpu_cells=128),
     # uniform delays up to 4 need CFL 0.05 to stay stable over long runs
     "wave128_p2_at3_uniformL4": dict(
         cfg=dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1)),
-        asy=dict(ghost=2, delay_kind=1, L=4, levels=3, seed=0), problem=1, precision=0, cfl=0.05),
-    # the learned ghost predictor (untrained, Glorot-initialised network from
-    # a fixed seed: inference and the per-face judge cost the same whatever
-    # the weights; a face whose correction exceeds the bound keeps AT)
+        asy=dict(ghost=2, delay_kind=1, L=4, levels=3, seed=0), problem=1, precision=0, cfl=0.05, cpu_cells=32),
+    "wave128_p2_sync": dict(
+        cfg=dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1)),
+        asy=dict(ghost=0, delay_kind=0, L=0, levels=3, seed=0), problem=1, precision=0, cfl=0.05, cpu_cells=32),
+    # the learned ghost predictor, its network trained first on pairs this
+    # mesh's own run gives (AT ghosts), then judged per face with the bound
+    # 1e-6 and AT's own error estimate; a rejected face keeps AT
     "wave128_p2_learned_uniformL4": dict(
         cfg=dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1)),
-        asy=dict(ghost=3, delay_kind=1, L=4, levels=3, seed=0, learned_tol=1e-6), problem=1, precision=0,
-        cfl=0.05, net_seed=1, reference="wave128_p2_at3_uniformL4"),
+        asy=dict(ghost=3, delay_kind=1, L=4, levels=3, seed=0, learned_tol=1e-6, learned_judge=1), problem=1,
+        precision=0, cfl=0.05, cpu_cells=32,
+        train=dict(warm_steps=24, collect_steps=1, epochs=2, batch=4096, lr=1e-3, seed=1)),
     # the paper's low-storage LSERK(3,3) instead of SSP-RK3 (same stage kernel)
     "vortex256_p3_at3_uniformL3_lserk33": dict(
         cfg=dict(dim=2, degree=3, cells=(256, 256, 1), parts=(8, 8, 1), lo=(0, 0, 0), hi=(10, 10, 1),
@@ -80,7 +84,13 @@ WORKLOADS = {
         asy=dict(ghost=2, delay_kind=2, L=4, levels=3, seed=0), problem=0, params=(5.0, 0.0, 5.0, 1.0, 0.0),
         precision=0, cfl=0.05),
 }
-DEFAULT = "vortex256_p3_at3_uniformL3"
+DEFAULT = "wave128_p2_at3_uniformL4"
+# the variants the metric compares at matched L2 error, reported with the
+# default workload: (variant, its FP64 reference, synchronous run or None)
+COMPARISONS = [
+    ("wave128_p2_learned_uniformL4", "wave128_p2_at3_uniformL4", "wave128_p2_sync"),
+    ("vortex1024_p4_at3_uniformL3_fp32", "vortex1024_p4_at3_uniformL3_fp64", None),
+]
 PROFILE_EVERY = 8
 
 
@@ -105,29 +115,51 @@ def algorithmic_bytes_per_launch(ndof, nfs_nodes_vars, ghost, levels, integrator
     return ndof * per_dof + ring + 8.0 * bnd_values
 
 
+def interp_fmas(dim, P, Q):
+    """I_d = sum_{i=1..d} Q^i P^(d-i+1): FMAs of one variable's sum-factorised
+    interpolation from the P^d nodes to the Q^d Gauss points"""
+    return sum(Q ** i * P ** (dim - i + 1) for i in range(1, dim + 1))
+
+
+# flops of the pointwise Euler flux tensor at one point (1/rho, u, |m.u|,
+# p, and the d columns of F) and of the LLF flux at one face point (both
+# normal fluxes, both speeds sqrt(|u|^2 + c^2), the maximum and the V
+# central-plus-dissipation combinations); division and square root count 1
+def flux_point_flops(dim):
+    return dim * dim + 6 * dim + 3
+
+
+def llf_point_flops(dim):
+    return 2 * (3 * dim + 8) + 13 + 5 * (dim + 2)
+
+
 def algorithmic_flops_per_element(dim, P, Q):
-    """Flops of one element-stage of the sum-factorised operator (FMA = 2):
-    d interpolation sweeps nodes->Gauss points, the Euler flux at every Gauss
-    point, d collocation-derivative sweeps, d transposed interpolation sweeps,
-    the face fluxes on 2d faces (trace interpolation of both sides, LLF flux,
-    lift) and d inverse-mass sweeps, plus the RK combine."""
+    """Flops of one element-stage of the method, sum-factorised (FMA = 2):
+    V interpolations of I_d FMAs; the Euler flux at the Q^d Gauss points;
+    the test with the gradients, V (d Q^(d+1) + I_d) FMAs (collocation
+    derivative and transposed interpolation); d faces per element, each with
+    two trace interpolations and two lifts, 4 I_(d-1) V FMAs, and the LLF flux
+    at Q^(d-1) points; the inverse mass, d P^(d+1) V FMAs; the RK combine,
+    4 flops per DoF. Each interior face is counted once (it is shared by
+    two elements)."""
     V = dim + 2
-    if dim == 2:
-        interp = V * (P * P * Q + Q * P * Q)
-        Fq, Fn = Q, P
-    else:
-        interp = V * (P * P * P * Q + Q * P * P * Q + Q * Q * P * Q)
-        Fq, Fn = Q * Q, P * P
-    Qd, Pd, nf = Q ** dim, P ** dim, 2 * dim
-    deriv = dim * V * Qd * Q                 # FMAs
-    test = interp                            # FMAs (transposed sweeps)
-    traces = 2 * nf * Fq * V * Fn            # FMAs, both sides at each face Gauss point
-    lift = nf * V * Fn * Fq                  # FMAs
-    minv = dim * V * Pd * P                  # FMAs
-    flux_qp = 12 + dim * (2 * V + 3)         # pressure, 1/rho, d scaled flux columns
-    llf = 60 + 2 * V                         # two normal fluxes, wave speeds, scaling
-    combine = 4 * V * Pd
-    return 2 * (interp + deriv + test + traces + lift + minv) + Qd * flux_qp + nf * Fq * llf + combine
+    I_d, I_f = interp_fmas(dim, P, Q), interp_fmas(dim - 1, P, Q)
+    fmas = V * I_d + V * (dim * Q ** (dim + 1) + I_d) + dim * 4 * I_f * V + dim * P ** (dim + 1) * V
+    return (2 * fmas + Q ** dim * flux_point_flops(dim) + dim * Q ** (dim - 1) * llf_point_flops(dim)
+            + 4 * V * P ** dim)
+
+
+def cpu_model():
+    """model name of the host CPU (Linux /proc/cpuinfo), or the platform's"""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
 
 
 def load_traffic(workload):
@@ -145,9 +177,10 @@ def load_traffic(workload):
 
 def cpu_baseline(w, target_s=15.0, cells=None):
     """The FP64 CPU oracle, untuned, on a bounded sample of the same workload:
-    the full mesh (or `cells` elements per direction, same subdomain count),
-    a few steps (as many as fit in about target_s seconds). The thread count
-    is OMP_NUM_THREADS, else the usable cores up to 16."""
+    the full mesh, or `cells` elements per direction with the same degree,
+    subdomain count and asynchrony, for as many steps as fit in about
+    target_s seconds. The thread count is OMP_NUM_THREADS, else the usable
+    cores up to 16."""
     from oracle import oracle as O
 
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
@@ -169,29 +202,68 @@ def cpu_baseline(w, target_s=15.0, cells=None):
     t2 = time.perf_counter()
     o.step(n, dt)
     t3 = time.perf_counter()
+    where = "full mesh" if cells is None else "mesh " + "x".join(str(x) for x in mesh[: c["dim"]]) + \
+        f" (same degree, subdomain count and asynchrony; {o.ndof} DoFs)"
     return {"value": o.ndof * (2 if integ in (1, 3) else 3) * n / (t3 - t2), "unit": "DOF-updates/s per RK stage",
-            "cores": threads,
+            "cores": threads, "cpu_model": cpu_model(),
             "kind": "oracle",
-            "sample": f"{'full mesh' if cells is None else 'mesh %d^%d' % (cells, c['dim'])}, {n} "
-                      f"{['SSP-RK3', 'LSERK(2,2)', 'LSERK(3,3)', 'SSP-RK2'][integ]} steps after 1 warm-up "
-                      f"step ({t3 - t2:.1f} s)"}
+            "sample": f"{where}, {n} {['SSP-RK3', 'LSERK(2,2)', 'LSERK(3,3)', 'SSP-RK2'][integ]} steps after 1 "
+                      f"warm-up step ({t3 - t2:.1f} s)"}
 
 
-def run_steps(w, steps, warmup):
+def make_solver(w):
+    from paper_2603_28710_amd.solver import Solver
+    return Solver(device="cuda:0", precision=w["precision"], **w["cfg"], **w["asy"])
+
+
+def train_predictor(w):
+    """FP32 weights of the predictor trained on the GPU on pairs this
+    workload's own run gives: a solver in the learned mode without a network
+    (AT ghosts) is stepped train["warm_steps"] steps from t = 0, then
+    collects train["collect_steps"] steps of pairs (every PE face node and
+    stage); Adam epochs on them. Returns (weights, info)."""
+    import torch
+
+    tr = w["train"]
+    s = make_solver(w)
+    s.init_problem(w["problem"], w.get("params"))
+    dt = s.stable_dt(w.get("cfl", 0.1))
+    s.step(tr["warm_steps"], dt)
+    nfs = s.n_face_sides()
+    Fn = (w["cfg"]["degree"] + 1) ** (w["cfg"]["dim"] - 1)
+    stages = 2 if w["cfg"].get("integrator", 0) in (1, 3) else 3
+    s.predictor_bind(nfs * Fn * stages * tr["collect_steps"])
+    t0 = time.perf_counter()
+    n = s.predictor_collect(tr["collect_steps"], dt)
+    loss = s.predictor_train(epochs=tr["epochs"], batch=tr["batch"], lr=tr["lr"], seed=tr["seed"])
+    torch.cuda.synchronize()
+    wts = s.predictor_get()
+    info = dict(tr, pairs=int(n), final_loss=float(loss), seconds=time.perf_counter() - t0)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return wts, info
+
+
+def run_steps(w, steps, warmup, weights=None, profile=False):
     """a solver of workload w stepped warmup + steps times at the workload's
-    CFL; returns (solver, dt, wall seconds of the timed steps)"""
+    CFL from its initial state; returns (solver, dt, wall seconds of the timed
+    steps, (stage-kernel ms, launches) from the library's events or None)"""
     import torch
 
     from paper_2603_28710_amd import binding as B
-    from paper_2603_28710_amd.solver import Solver
 
-    c, a = w["cfg"], w["asy"]
-    s = Solver(device="cuda:0", precision=w["precision"], **c, **a)
+    s = make_solver(w)
     s.init_problem(w["problem"], w.get("params"))
-    if a["ghost"] == B.ADG_GHOST_LEARNED:
-        s.predictor_init(w["net_seed"])
+    if weights is not None:
+        s.predictor_set(weights)
     dt = s.stable_dt(w.get("cfl", 0.1))
     s.step(warmup, dt)
+    torch.cuda.synchronize()
+    if profile:
+        # HIP events around the stage launches of every PROFILE_EVERY-th
+        # step, recorded by the library on its own stream
+        B.adg_profile(s.h, PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = s.step_status(steps, dt)
@@ -199,33 +271,87 @@ def run_steps(w, steps, warmup):
     t1 = time.perf_counter()
     if st != 0:
         raise RuntimeError(B.adg_last_error())
-    return s, dt, t1 - t0
+    ev = None
+    if profile:
+        ev = (B.adg_profile_read(s.h, B.ADG_KERNEL_RHS), B.adg_profile_read(s.h, B.ADG_KERNEL_GHOST))
+        B.adg_profile(s.h, 0)
+    return s, dt, t1 - t0, ev
 
 
-def matched_error(s, sec, ref_name, steps, warmup):
-    """the workload's FP64 reference (same mesh, initial state, dt and step
-    count) run after the timed region: relative L2 difference of the states
-    (density, momentum, energy) and the reference's time over this one's"""
-    r, _, rsec = run_steps(WORKLOADS[ref_name], steps, warmup)
-    diff = s.diff_norm(r.download())
-    r.close()
-    return {"reference": ref_name, "rel_l2_vs_reference": list(diff), "speedup_vs_reference": rsec / sec}
+def stages_of(w):
+    return 2 if w["cfg"].get("integrator", 0) in (1, 3) else 3
+
+
+def comparison(variant, reference, sync, steps, warmup, ref_run=None):
+    """a variant the metric compares against its FP64 reference at matched L2
+    error: both run warmup + steps from the same initial state with the same
+    dt; reported are both throughputs, the speedup, the relative L2
+    difference of the final states (density, momentum, energy), both L2
+    errors against the exact solution and, with a synchronous run, the
+    distance of each from it. ref_run = (state, seconds, l2 vs exact) reuses
+    an already timed reference."""
+    import numpy as np
+    import torch
+
+    wv, wr = WORKLOADS[variant], WORKLOADS[reference]
+    out = {"variant": variant, "reference": reference, "steps": steps, "warmup": warmup}
+    weights = None
+    if "train" in wv:
+        weights, out["training"] = train_predictor(wv)
+    if ref_run is None:
+        r, _, rsec, _ = run_steps(wr, steps, warmup)
+        ref_run = (r.download(), rsec, list(r.error_norms(wr["problem"], wr.get("params"))))
+        r.close()
+        del r
+        torch.cuda.empty_cache()
+    ref_state, rsec, ref_err = ref_run
+    s, dt, sec, _ = run_steps(wv, steps, warmup, weights=weights)
+    ndof, st = s.ndof, stages_of(wv) * steps
+    out.update({"dt": dt, "value": ndof * st / sec, "reference_value": ndof * st / rsec,
+                "speedup_vs_reference": rsec / sec,
+                "rel_l2_vs_reference": list(s.diff_norm(ref_state)),
+                "l2_error_vs_exact": {"variant": list(s.error_norms(wv["problem"], wv.get("params"))),
+                                      "reference": ref_err}})
+    out["within_1e-6"] = bool(max(out["rel_l2_vs_reference"]) <= 1e-6)
+    if wv["asy"]["ghost"] == 3:
+        rate, judged, te, ta = s.predictor_stats(trace_errors=True)
+        out["learned"] = {"accept_rate": rate, "faces_judged": judged, "mean_trace_err_used": te,
+                          "mean_trace_err_at": ta, "judge": wv["asy"].get("learned_judge", 0),
+                          "accept_bound": wv["asy"]["learned_tol"]}
+    if sync is not None:
+        mine = s.download()
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        y, _, _, _ = run_steps(WORKLOADS[sync], steps, warmup)
+        y_state = y.download()
+        out["rel_l2_vs_sync"] = {"variant": list(y.diff_norm(mine)), "reference": list(y.diff_norm(ref_state))}
+        y.close()
+        del y
+    else:
+        s.close()
+        del s
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the matched-error comparisons of the FP32 and learned variants")
     ap.add_argument("--cpu-only", action="store_true",
                     help="print only the cpu_baseline object of the workload (no GPU)")
     ap.add_argument("--cpu-cells", type=int, default=None,
                     help="with --cpu-only: elements per direction of a reduced mesh")
     args = ap.parse_args()
     if args.cpu_only:
-        out = cpu_baseline(WORKLOADS[args.workload], cells=args.cpu_cells)
+        w = WORKLOADS[args.workload]
+        out = cpu_baseline(w, cells=args.cpu_cells if args.cpu_cells else w.get("cpu_cells"))
         out["workload"] = args.workload
         print(json.dumps(out), flush=True)
         return
@@ -238,38 +364,17 @@ def main():
     import torch
 
     from paper_2603_28710_amd import binding as B
-    from paper_2603_28710_amd.solver import Solver
 
     w = WORKLOADS[args.workload]
     c, a = w["cfg"], w["asy"]
-    s = Solver(device="cuda:0", precision=w["precision"], **c, **a)
-    s.init_problem(w["problem"], w.get("params"))
-    if a["ghost"] == B.ADG_GHOST_LEARNED:
-        s.predictor_init(w["net_seed"])
-    cfl = w.get("cfl", 0.1)
-    dt = s.stable_dt(cfl)
-    s.step(args.warmup, dt)
-    torch.cuda.synchronize()
-
-    # HIP events around the stage launches of every PROFILE_EVERY-th step:
-    # the average launch duration of the roofline, without putting the
-    # events' own cost (a few microseconds per pair) into every step
-    B.adg_profile(s.h, PROFILE_EVERY)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = s.step_status(args.steps, dt)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if st != 0:
-        raise RuntimeError(B.adg_last_error())
-    rhs_ms, rhs_n = B.adg_profile_read(s.h, B.ADG_KERNEL_RHS)
-    gh_ms, gh_n = B.adg_profile_read(s.h, B.ADG_KERNEL_GHOST)
-    B.adg_profile(s.h, 0)
-
-    sec = t1 - t0
-    stages = (2 if c.get("integrator", 0) in (B.ADG_LSERK22, B.ADG_SSPRK2) else 3) * args.steps
+    weights = None
+    if "train" in w:
+        weights, _ = train_predictor(w)
+    s, dt, sec, ev = run_steps(w, args.steps, args.warmup, weights=weights, profile=True)
+    (rhs_ms, rhs_n), (gh_ms, gh_n) = ev
+    stages = stages_of(w) * args.steps
     value = s.ndof * stages / sec
-    nfs = B.adg_delay(s.h, s.time()[0], 0, 0)[1]
+    nfs = s.n_face_sides()
     Fn = (c["degree"] + 1) ** (c["dim"] - 1)
     # in a Dirichlet box (2D) the boundary faces keep unused slots in the
     # face-side enumeration: count only the PE face-sides, 2 (parts_a - 1)
@@ -281,12 +386,35 @@ def main():
     bytes_launch = algorithmic_bytes_per_launch(s.ndof, nfs * s.V * Fn, a["ghost"], a["levels"],
                                                 c.get("integrator", 0), bnd_values)
     avg_s = rhs_ms / max(rhs_n, 1) / 1e3
-    achieved = bytes_launch / avg_s / 1e9
     P, Q = c["degree"] + 1, c["degree"] + 2
     flops_launch = algorithmic_flops_per_element(c["dim"], P, Q) * s.E
     fpeak = FP32_PEAK_TFLOPS if w["precision"] else FP64_PEAK_TFLOPS
+    gbs = bytes_launch / avg_s / 1e9
+    tfs = flops_launch / avg_s / 1e12
+    # the binding roof: the larger of the two lower bounds on the launch time
+    t_hbm, t_alu = bytes_launch / (HBM_PEAK_GBS * 1e9), flops_launch / (fpeak * 1e12)
     traffic = load_traffic(args.workload)
     err = s.error_norms(w["problem"], w.get("params")) if w["problem"] in (0, 1) else None
+    kname = "rhs_stage{}d<{},{}>".format(c["dim"], "f32" if w["precision"] else "f64", P)
+    launches_per_step = stages_of(w)
+    ms_step = sec * 1e3 / args.steps
+    if t_alu >= t_hbm:
+        roof = {"bound": "alu", "achieved": tfs, "peak": fpeak, "unit": "TFLOP/s", "frac": tfs / fpeak}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    roof.update({
+        "traffic": traffic,
+        "kernel": kname, "avg_launch_us": avg_s * 1e6, "launches": rhs_n,
+        "event_sampling": f"stage launches of every {PROFILE_EVERY}th step",
+        # the sampled launches and a step's other work must fit in the step
+        "events_fit_step": bool(launches_per_step * avg_s * 1e3 + gh_ms / max(gh_n, 1) * launches_per_step
+                                <= ms_step * 1.02),
+        "algorithmic_bytes_per_launch": bytes_launch, "algorithmic_flops_per_launch": flops_launch,
+        "hbm_frac": gbs / HBM_PEAK_GBS, "alu_frac": tfs / fpeak,
+        "alu_peak_tflops": fpeak,
+        "binding_time_us": {"hbm": t_hbm * 1e6, "alu": t_alu * 1e6}})
+    if traffic:
+        roof["traffic_over_algorithmic"] = traffic / bytes_launch
 
     out = {
         "metric": "DOF-updates/s per RK stage",
@@ -295,7 +423,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sec * 1e3 / args.steps,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -306,26 +434,27 @@ def main():
                    "ghost": ["sync", "stale", "at", "learned", "flux_stale", "flux_at"][a["ghost"]],
                    "levels": a["levels"],
                    "delay": ["fixed", "uniform", "caa"][a["delay_kind"]], "L": a["L"], "seed": a["seed"],
-                   "dofs": s.ndof, "elements": s.E, "dt": dt, "cfl": cfl,
+                   "dofs": s.ndof, "elements": s.E, "dt": dt, "cfl": w.get("cfl", 0.1),
                    "integrator": ["ssprk3", "lserk22", "lserk33", "ssprk2"][c.get("integrator", 0)],
                    "boundary": ["periodic", "dirichlet"][c.get("boundary", 0)]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "rhs_stage", "avg_launch_us": avg_s * 1e6, "launches": rhs_n,
-                     "event_sampling": f"stage launches of every {PROFILE_EVERY}th step",
-                     "algorithmic_bytes_per_launch": bytes_launch},
-        "alu": {"achieved_tflops": flops_launch / avg_s / 1e12, "peak_tflops": fpeak,
-                "frac": flops_launch / avg_s / 1e12 / fpeak, "flops_per_launch": flops_launch},
+        "roofline": roof,
         "ghost_kernel": {"avg_launch_us": gh_ms / max(gh_n, 1) * 1e3, "launches": gh_n},
         "l2_error_vs_exact": err,
     }
     if a["ghost"] == B.ADG_GHOST_LEARNED:
-        rate, judged = s.predictor_stats()
-        out["ghost_kernel"].update({"faces_judged": judged, "accept_rate": rate})
-    if "reference" in w:
-        out["matched_error"] = matched_error(s, sec, w["reference"], args.steps, args.warmup)
+        rate, judged, te, ta = s.predictor_stats(trace_errors=True)
+        out["ghost_kernel"].update({"faces_judged": judged, "accept_rate": rate, "mean_trace_err_used": te,
+                                    "mean_trace_err_at": ta})
+    main_run = (s.download(), sec, list(err) if err is not None else None)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_compare:
+        out["matched_error"] = [comparison(v, r, y, args.steps, args.warmup,
+                                           ref_run=main_run if r == args.workload else None)
+                                for v, r, y in COMPARISONS if args.workload in (r, DEFAULT)]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, cells=w.get("cpu_cells"))
     print(json.dumps(out), flush=True)
 
 

@@ -274,9 +274,17 @@ adg_status adg_predictor_grad(adg_ctx ctx, int64_t first, int64_t count, float* 
 adg_status adg_predictor_infer(adg_ctx ctx, int64_t first, int64_t count, float* y);
 adg_status adg_predictor_get(adg_ctx ctx, float* w);
 adg_status adg_predictor_set(adg_ctx ctx, const float* w);
-/* faces judged (learned mode, delay >= 1) since the last reset and the
- * fraction whose correction was accepted */
-adg_status adg_predictor_stats(adg_ctx ctx, double* accept_rate, int64_t* faces_judged);
+/* Statistics of the learned ghost traces since the last reset (adg_upload,
+ * adg_init_problem, adg_set_async): the faces judged (learned mode with a
+ * network, delay >= 1) and the fraction whose correction was accepted (1 -
+ * the AT fallback rate); and, over every PE face node with delay >= 1 that the
+ * learned ghost kernel built (learned mode or pair collection), the mean of
+ * max_v |w+ used - w+ live| (mean_trace_err) and of max_v |w+ AT - w+ live|
+ * (mean_at_err), where w+ live is the neighbour's current stage value, the
+ * trace a synchronous scheme would use. Any pointer may be NULL. Blocks on
+ * the stream. */
+adg_status adg_predictor_stats(adg_ctx ctx, double* accept_rate, int64_t* faces_judged, double* mean_trace_err,
+                               double* mean_at_err);
 
 adg_status adg_destroy(adg_ctx ctx);
 const char* adg_last_error(void);

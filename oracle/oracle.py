@@ -132,7 +132,7 @@ class Oracle:
 
     def __init__(self, dim=2, p=2, nq=0, cells=(16, 16, 1), parts=(1, 1, 1), lo=(0, 0, 0),
                  hi=(10, 10, 1), gamma=1.4, flux=LLF, ghost=SYNC, delay_kind=FIXED, L=0, levels=3,
-                 seed=0, learned_tol=1e-6, integrator=0, bc=0, bc_problem=0, bc_params=None, learned_judge=0):
+                 seed=0, learned_tol=1e-6, integrator=0, bc=0, bc_problem=0, bc_params=None, learned_judge=1):
         c = OrcCfg()
         c.dim, c.p, c.nq = dim, p, nq
         for k in range(3):

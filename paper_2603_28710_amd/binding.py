@@ -83,7 +83,7 @@ _SIGS = {
     "adg_predictor_train": [_vp, C.c_int32, C.c_int32, C.c_float, C.c_uint64, _fp],
     "adg_predictor_get": [_vp, _fp],
     "adg_predictor_set": [_vp, _fp],
-    "adg_predictor_stats": [_vp, _dp, C.POINTER(C.c_int64)],
+    "adg_predictor_stats": [_vp, _dp, C.POINTER(C.c_int64), _dp, _dp],
     "adg_destroy": [_vp],
 }
 for _name, _args in _SIGS.items():
@@ -268,9 +268,13 @@ def adg_predictor_set(h, w_ptr):
     _call("adg_predictor_set", h, C.cast(w_ptr, _fp))
 
 
-def adg_predictor_stats(h):
-    r, n = C.c_double(), C.c_int64()
-    _call("adg_predictor_stats", h, C.byref(r), C.byref(n))
+def adg_predictor_stats(h, trace_errors=False):
+    """(accept rate, faces judged), and with trace_errors=True also the mean
+    trace error of the ghosts used and of AT against the live values"""
+    r, n, te, ta = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+    _call("adg_predictor_stats", h, C.byref(r), C.byref(n), C.byref(te), C.byref(ta))
+    if trace_errors:
+        return r.value, n.value, te.value, ta.value
     return r.value, n.value
 
 
@@ -298,7 +302,10 @@ def make_config(dim=2, degree=2, cells=(16, 16, 1), parts=(1, 1, 1), lo=(0, 0, 0
 
 
 def make_async(ghost=ADG_GHOST_SYNC, delay_kind=ADG_DELAY_FIXED, L=0, levels=3, seed=0, learned_tol=1e-6,
-               learned_judge=0):
+               learned_judge=1):
+    """asynchrony settings; the learned judge defaults to 1: a face's
+    correction must stay within the accept bound and within AT's own error
+    estimate on the face"""
     a = adg_async()
     a.ghost, a.delay_kind, a.L, a.levels, a.seed, a.learned_tol = ghost, delay_kind, L, levels, seed, learned_tol
     a.learned_judge = learned_judge

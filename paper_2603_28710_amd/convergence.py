@@ -44,7 +44,7 @@ PAPER_MODES = {
     "flux_caa_at": dict(ghost=5, delay_kind=2, cfl=0.05),
     # the learned predictor over AT (caa-at schedule), its network trained on
     # the same mesh first (stability.train_predictor), accept bound 1e-4
-    "learned_caa": dict(ghost=3, delay_kind=2, cfl=0.05, learned_tol=1e-4),
+    "learned_caa": dict(ghost=3, delay_kind=2, cfl=0.05, learned_tol=1e-4, learned_judge=0),
     # the same with the second judge (corrections within AT's own error estimate)
     "learned_judged_caa": dict(ghost=3, delay_kind=2, cfl=0.05, learned_tol=1e-4, learned_judge=1),
 }

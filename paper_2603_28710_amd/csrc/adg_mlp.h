@@ -45,6 +45,9 @@ struct MlpDev {
   float* lpart;               // [kTrainBlocks][2] partial loss and weight sums
   uint16_t* pack;             // BF16 operand tiles and FP32 biases (kPackBytes)
   unsigned long long* stats;  // [kStatSlots][2]: accepted faces, judged faces
+  // [kStatSlots][3]: over PE face nodes with delay >= 1, the sums of
+  // max_v |ghost used - live| and max_v |AT - live|, and the node count
+  double* terr;
   float* gout;                // reduced gradient (nparams)
   float* yout;                // inference outputs (kMaxBatch * V)
   float* loss;                // last loss

@@ -38,6 +38,7 @@ size_t mlp_scratch_bytes(int V) {
   s = al256(s + (size_t)kTrainBlocks * 2 * 4);   // lpart
   s = al256(s + kPackBytes);                     // pack
   s = al256(s + 2 * kStatSlots * sizeof(unsigned long long));  // stats
+  s = al256(s + 3 * kStatSlots * sizeof(double));              // terr
   s = al256(s + np * 4);                         // gout
   s = al256(s + (size_t)kMaxBatch * V * 4);      // yout
   s = al256(s + 4 * 4);                          // loss
@@ -61,6 +62,7 @@ MlpDev mlp_dev(const MlpState& s) {
   d.lpart = reinterpret_cast<float*>(take((size_t)kTrainBlocks * 2 * 4));
   d.pack = reinterpret_cast<uint16_t*>(take(kPackBytes));
   d.stats = reinterpret_cast<unsigned long long*>(take(2 * kStatSlots * sizeof(unsigned long long)));
+  d.terr = reinterpret_cast<double*>(take(3 * kStatSlots * sizeof(double)));
   d.gout = reinterpret_cast<float*>(take(np * 4));
   d.yout = reinterpret_cast<float*>(take((size_t)kMaxBatch * s.V * 4));
   d.loss = reinterpret_cast<float*>(take(16));
@@ -146,6 +148,7 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
                                                             double* __restrict__ ring, double* __restrict__ ghost,
                                                             int publish, const uint16_t* __restrict__ pk,
                                                             int use_net, unsigned long long* __restrict__ stats,
+                                                            double* __restrict__ terr,
                                                             float* __restrict__ pairs, long long pair_base,
                                                             int collect) {
   constexpr int V = D + 2, Fn = D == 2 ? P : P * P, Pd = Fn * P, NIN = 2 * V + 2;
@@ -280,10 +283,37 @@ __global__ __launch_bounds__(256) void ghost_learned_kernel(Mesh M, Async A, con
     if (ma) atomicAdd(&slot[0], (unsigned long long)__popcll(ma));
   }
   __syncthreads();
+  // trace errors against the live stage value (what a synchronous scheme
+  // would use) at the nodes with delay >= 1: of the ghost used and of AT
+  double e_used = 0.0, e_at = 0.0;
+  const bool delayed = valid && k >= 1;
   if (valid) {
     const int fa = s_acc[w][lane - j];
 #pragma unroll
-    for (int v = 0; v < V; ++v) ghost[(fs * V + v) * Fn + j] = k == 0 ? live[v] : at[v] + (fa ? dl[v] : 0.0);
+    for (int v = 0; v < V; ++v) {
+      const double gv = k == 0 ? live[v] : at[v] + (fa ? dl[v] : 0.0);
+      ghost[(fs * V + v) * Fn + j] = gv;
+      if (delayed) {
+        e_used = fmax(e_used, fabs(gv - live[v]));
+        e_at = fmax(e_at, fabs(at[v] - live[v]));
+      }
+    }
+  }
+  {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      e_used += __shfl_xor(e_used, o);
+      e_at += __shfl_xor(e_at, o);
+    }
+    const unsigned long long md = __ballot(delayed);
+    if (lane == 0 && md) {
+      double* slot = terr + 3 * ((blockIdx.x * 4 + w) % kStatSlots);
+      atomicAdd(&slot[0], e_used);
+      atomicAdd(&slot[1], e_at);
+      atomicAdd(&slot[2], (double)__popcll(md));
+    }
+  }
+  if (valid) {
     if (collect) {
       // target: live stage value minus AT, in units of S. Targets beyond
       // kTargetClip (well above the largest extrapolation coefficient the
@@ -318,7 +348,7 @@ hipError_t launch_ghost_learned(int dim, int degree, const Mesh& M, const Async&
 #define ADG_GL_CASE(dd, p)                                                                                       \
   if (dim == dd && degree == p) {                                                                                \
     hipLaunchKernelGGL((ghost_learned_kernel<dd, p + 1>), dim3(nblk), dim3(256), 0, st, M, A, u_in, u_n, ring,   \
-                       ghost, publish, d.pack, use_net, d.stats, s.pairs, pair_base, collect ? 1 : 0);           \
+                       ghost, publish, d.pack, use_net, d.stats, d.terr, s.pairs, pair_base, collect ? 1 : 0);   \
     return hipGetLastError();                                                                                    \
   }
   ADG_GL_CASE(2, 1) ADG_GL_CASE(2, 2) ADG_GL_CASE(2, 3) ADG_GL_CASE(2, 4)
@@ -488,6 +518,9 @@ void mlp_reset_stats(adg_ctx_s* c) {
   const MlpDev d = mlp_dev(c->mlp);
   hipLaunchKernelGGL(mlp_zero_kernel, dim3((2 * kStatSlots + 63) / 64), dim3(64), 0, c->stream, d.stats,
                      2 * kStatSlots);
+  // the all-zero bit pattern is 0.0
+  hipLaunchKernelGGL(mlp_zero_kernel, dim3((3 * kStatSlots + 63) / 64), dim3(64), 0, c->stream,
+                     reinterpret_cast<unsigned long long*>(d.terr), 3 * kStatSlots);
 }
 
 // upload host_w as the master weights, repack, zero Adam state
@@ -697,21 +730,28 @@ adg_status adg_predictor_set(adg_ctx c, const float* w) {
   return mlp_set_host(c, w);
 }
 
-adg_status adg_predictor_stats(adg_ctx c, double* accept_rate, int64_t* faces_judged) {
+adg_status adg_predictor_stats(adg_ctx c, double* accept_rate, int64_t* faces_judged, double* mean_trace_err,
+                               double* mean_at_err) {
   if (!c) return fail(ADG_ERR_INVALID, "null context");
   unsigned long long h[2] = {0, 0};
+  double te[3] = {0.0, 0.0, 0.0};
   if (c->bound) {
     const MlpDev d = mlp_dev(c->mlp);
     unsigned long long slots[2 * kStatSlots];
+    double ts[3 * kStatSlots];
     HIP_TRY(hipMemcpyAsync(slots, d.stats, sizeof(slots), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(ts, d.terr, sizeof(ts), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     for (int i = 0; i < kStatSlots; ++i) {
       h[0] += slots[2 * i];
       h[1] += slots[2 * i + 1];
+      for (int q = 0; q < 3; ++q) te[q] += ts[3 * i + q];
     }
   }
   if (accept_rate) *accept_rate = h[1] ? (double)h[0] / (double)h[1] : 0.0;
   if (faces_judged) *faces_judged = (int64_t)h[1];
+  if (mean_trace_err) *mean_trace_err = te[2] > 0 ? te[0] / te[2] : 0.0;
+  if (mean_at_err) *mean_at_err = te[2] > 0 ? te[1] / te[2] : 0.0;
   return ADG_OK;
 }
 

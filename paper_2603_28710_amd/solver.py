@@ -89,6 +89,10 @@ class Solver:
     def time(self):
         return B.adg_time(self.h)
 
+    def n_face_sides(self):
+        """PE-boundary face-sides of the partition (host-only query)"""
+        return B.adg_delay(self.h, self.time()[0], 0, 0)[1]
+
     def stable_dt(self, cfl):
         return B.adg_stable_dt(self.h, cfl)
 
@@ -121,6 +125,7 @@ class Solver:
 
     def predictor_bind(self, max_pairs):
         pb = B.adg_predictor_pair_bytes(self.h)
+        self.pairs = None  # release the previous buffer first
         self.pairs, ptr = _aligned_empty(pb * max_pairs, self.device)
         B.adg_predictor_bind(self.h, ptr, max_pairs)
 
@@ -156,5 +161,5 @@ class Solver:
         w = np.ascontiguousarray(w, dtype=np.float32)
         B.adg_predictor_set(self.h, w.ctypes.data)
 
-    def predictor_stats(self):
-        return B.adg_predictor_stats(self.h)
+    def predictor_stats(self, trace_errors=False):
+        return B.adg_predictor_stats(self.h, trace_errors)

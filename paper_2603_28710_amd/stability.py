@@ -28,7 +28,7 @@ MODES = {
     "at_uniform": dict(ghost=2, delay_kind=1),
     # the learned predictor over AT, trained first on the same mesh and
     # schedule (see train_predictor); its accept bound is LEARNED_TOL
-    "learned_caa": dict(ghost=3, delay_kind=2),
+    "learned_caa": dict(ghost=3, delay_kind=2, learned_judge=0),
     # the same with the second judge: corrections within AT's own error
     # estimate only
     "learned_judged_caa": dict(ghost=3, delay_kind=2, learned_judge=1),

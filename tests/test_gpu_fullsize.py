@@ -10,6 +10,13 @@ configuration bench.py times.
   a seeded sample of elements one by one through their dependency cone
   (face-distance 2, 1, 0 for the three stages). At step 0 the warm-up makes
   every delay zero, so the asynchronous run equals the synchronous scheme.
+- The same three workloads through the asynchronous path: the oracle runs the
+  whole mesh step by step past the warm-up until the largest delay L has been
+  used (levels + L + 1 steps or more), relative L2 <= 1e-11; the delays of
+  the run are read back through the C ABI and must include every value 1..L.
+- The FP32-contraction variant at 1024^2, degree 4, against the FP64 path of
+  the same configuration (itself oracle-pinned above): relative L2 <= 1e-6
+  after 100 and after 200 steps.
 """
 import sys
 
@@ -136,3 +143,69 @@ def test_full_size_one_step_sampled(oracle_mod, name, cfg, problem, precision):
     r = rel_l2_groups(mine, ref, V)
     say("  rel L2 on samples", r)
     assert r <= 1e-11
+
+
+ASYNC_FULL = [
+    # name, config, problem, steps, cfl
+    ("vortex1024_p4_at3_uniformL3", dict(dim=2, p=4, cells=(1024, 1024, 1), parts=(8, 8, 1), hi=(10, 10, 1),
+                                         ghost=2, delay_kind=1, L=3, levels=3, seed=0), 0, 9, 0.1),
+    ("wave64_p3_at3_fixedL2", dict(dim=3, p=3, cells=(64, 64, 64), parts=(4, 4, 4), hi=(1, 1, 1), ghost=2,
+                                   delay_kind=0, L=2, levels=3, seed=0), 1, 6, 0.1),
+    ("wave128_p2_at3_uniformL4", dict(dim=3, p=2, cells=(128, 128, 128), parts=(8, 8, 8), hi=(1, 1, 1), ghost=2,
+                                      delay_kind=1, L=4, levels=3, seed=0), 1, 9, 0.05),
+]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,cfg,problem,steps,cfl", ASYNC_FULL)
+def test_full_size_async_whole_mesh(oracle_mod, name, cfg, problem, steps, cfl):
+    from paper_2603_28710_amd import binding as B
+    from paper_2603_28710_amd.solver import Solver
+    O = oracle_mod
+    say(f"case: {name}, {steps} steps through the asynchronous path, whole-mesh oracle")
+    dim, p = cfg["dim"], cfg["p"]
+    o = O.Oracle(**cfg)
+    o.init_problem(problem)
+    gcfg = dict(cfg)
+    gcfg["degree"] = gcfg.pop("p")
+    s = Solver(**gcfg)
+    s.upload(o.state())
+    dt = o.stable_dt(cfl)
+    delays = set()
+    nsub = int(np.prod(cfg["parts"][:dim]))
+    for n in range(steps):
+        for sub in range(nsub):
+            for d in range(2 * dim):
+                delays.add(B.adg_delay(s.h, n, sub, d)[0])
+        s.step(1, dt)
+        o.step(1, dt)
+        say(f"  step {n + 1} of {steps}")
+    V, Pd = dim + 2, (p + 1) ** dim
+    r = rel_l2_groups(s.download().reshape(-1, V, Pd), o.state().reshape(-1, V, Pd), V)
+    say("  delays used", sorted(delays), " rel L2", r)
+    assert set(range(cfg["L"] + 1)) <= delays
+    assert r <= 1e-11
+
+
+def test_fp32_contractions_full_size_vs_fp64():
+    """the FP32-contraction variant of the 1024^2, degree-4 vortex (AT3,
+    uniform delays up to 3) stays within 1e-6 (relative L2 per group) of the
+    FP64 path every 100 steps"""
+    from paper_2603_28710_amd.solver import Solver
+    say("case: vortex 1024^2 p=4 AT3 uniform L=3, FP32 contractions vs FP64, 200 steps")
+    cfg = dict(dim=2, degree=4, cells=(1024, 1024, 1), parts=(8, 8, 1), hi=(10, 10, 1), ghost=2, delay_kind=1, L=3,
+               levels=3, seed=0)
+    a = Solver(precision=0, **cfg)
+    b = Solver(precision=1, **cfg)
+    a.init_problem(0)
+    b.init_problem(0)
+    dt = a.stable_dt(0.1)
+    assert dt == b.stable_dt(0.1)
+    worst = 0.0
+    for k in range(2):
+        a.step(100, dt)
+        b.step(100, dt)
+        d = max(b.diff_norm(a.download()))
+        worst = max(worst, d)
+        say(f"  after {100 * (k + 1)} steps: rel L2 FP32 vs FP64 {d:.3e}")
+    assert 0 < worst <= 1e-6

@@ -2,6 +2,9 @@
 
 - FP32 training gradients against the oracle's FP64 backward on seeded pairs
   (relative <= 1e-4 of the largest component).
+- Two Adam steps of adg_predictor_train against the oracle's Adam on the
+  oracle's gradients; the pairs adg_predictor_collect records against the
+  pairs the oracle's own run gives (features and live-minus-AT targets).
 - BF16 matrix-core inference against the oracle's forward in the kernel's
   precision (bf16 operands) and against the exact FP64 forward.
 - The LEARNED ghost mode with fixed weights against the oracle running the
@@ -61,6 +64,136 @@ def test_gradient_matches_oracle(oracle_mod, dim):
     assert np.abs(g - go).max() <= 1e-4 * np.abs(go).max()
 
 
+def test_adam_steps_match_oracle(oracle_mod):
+    """adg_predictor_train with one full-batch minibatch per epoch: two Adam
+    steps (0.9, 0.999, 1e-8, bias-corrected) on the weighted MSE, against
+    orc_adam applied to the oracle's FP64 gradient at each step"""
+    O = oracle_mod
+    V = 5
+    nin, nh, n, lr = 2 * V + 2, 64, 4000, 1e-3
+    say("case: two Adam steps vs oracle, 3D predictor, 4000 pairs")
+    s = _solver(dim=3, degree=2, cells=(4, 4, 4), parts=(2, 2, 2), hi=(1, 1, 1), ghost=3, delay_kind=1, L=2)
+    w0 = inputs.mlp_weights(s.predictor_nparams(), 31, 0.2).astype(np.float32)
+    s.predictor_set(w0)
+    s.predictor_bind(n)
+    rec = _pairs(n, V, 32)
+    s.predictor_load_pairs(rec)
+    s.predictor_train(epochs=2, batch=n, lr=lr, seed=5)
+    got = s.predictor_get().astype(np.float64)
+    x = rec[:, :nin].astype(np.float64)
+    y = rec[:, nin:nin + V].astype(np.float64)
+    w = w0.astype(np.float64)
+    m, v = np.zeros_like(w), np.zeros_like(w)
+    gmin = np.full_like(w, np.inf)
+    for t in (1, 2):
+        _, g = O.mlp_loss_grad(w, nin, nh, V, x, y)
+        gmin = np.minimum(gmin, np.abs(g) / np.abs(g).max())
+        O.adam(w, m, v, g, lr, t)
+    d = np.abs(got - w)
+    firm = gmin > 1e-4  # components whose sign and size fp32 resolves
+    say("  max |dw| (resolved components)", d[firm].max(), " all", d.max(), " step size", lr,
+        " resolved", firm.mean())
+    assert firm.mean() > 0.9
+    assert d[firm].max() <= 2e-3 * lr + 2e-7
+    assert d.max() <= 4 * lr
+    assert np.abs(got - w0).max() > 0.5 * lr  # the weights did move
+
+
+def _fs_table(cells, parts, dim):
+    """(element, face) of every PE face-side index, in the enumeration the
+    header documents: by receiving subdomain, then face direction, then the
+    subdomain-local position over the other axes (lowest axis fastest)"""
+    nc = [cells[k] if k < dim else 1 for k in range(3)]
+    pp = [parts[k] if k < dim else 1 for k in range(3)]
+    m = [nc[k] // pp[k] for k in range(3)]
+    offs, off = {}, 0
+    for f in range(2 * dim):
+        a = f // 2
+        if pp[a] < 2:
+            continue
+        offs[f] = off
+        area = 1
+        for k in range(dim):
+            if k != a:
+                area *= m[k]
+        off += area
+    fs_sub = off
+    out = []
+    for sub in range(pp[0] * pp[1] * pp[2]):
+        sc = [sub % pp[0], (sub // pp[0]) % pp[1], sub // (pp[0] * pp[1])]
+        for f, o in offs.items():
+            a = f // 2
+            others = [k for k in range(3) if k != a]
+            cnt = 1
+            for k in range(dim):
+                if k != a:
+                    cnt *= m[k]
+            for li in range(cnt):
+                l = [0, 0, 0]
+                l[others[0]] = li % m[others[0]]
+                if dim == 3:
+                    l[others[1]] = li // m[others[0]]
+                l[a] = m[a] - 1 if f & 1 else 0
+                c = [sc[k] * m[k] + l[k] for k in range(3)]
+                out.append((c[0] + nc[0] * (c[1] + nc[1] * c[2]), f))
+    assert len(out) == fs_sub * pp[0] * pp[1] * pp[2]
+    return out
+
+
+def test_collected_pairs_match_oracle(oracle_mod):
+    """adg_predictor_collect against the pairs the oracle's own learned run
+    (no network: every face keeps AT) gives at the same steps: one record
+    per PE face node and stage, features and target (live stage value of
+    the neighbour minus AT) / S, weight 1 exactly where the delay is >= 1"""
+    O = oracle_mod
+    say("case: collected training pairs vs oracle, 3D p=2 8^3 parts 2^3, uniform L=3, 3 steps after 6")
+    cfg = dict(dim=3, cells=(8, 8, 8), parts=(2, 2, 2), hi=(1, 1, 1), ghost=3, delay_kind=1, L=3, levels=3, seed=4)
+    o = O.Oracle(p=2, **cfg)
+    o.init_problem(O.DENSITY_WAVE)
+    u0 = o.state() + inputs.perturbation(o.ndof, 33, 1e-4)
+    o.set_state(u0)
+    s = _solver(degree=2, **cfg)
+    s.upload(u0)
+    dt = o.stable_dt(0.1)
+    o.step(6, dt)
+    s.step(6, dt)
+    V, nin, Fn = 5, 12, 9
+    table = _fs_table(cfg["cells"], cfg["parts"], 3)
+    nfs = len(table)
+    per = nfs * Fn
+    s.predictor_bind(3 * 3 * per)
+    n = s.predictor_collect(3, dt)
+    assert n == 3 * 3 * per
+    o.record_pairs(3 * 3 * per)
+    o.step(3, dt)
+    rows = o.recorded_pairs()
+    nrec = nin + V + 1
+    off = (-s.pairs.data_ptr()) % 256
+    raw = s.pairs.cpu().numpy().tobytes()[off:off + n * nrec * 4]
+    rec = np.frombuffer(raw, dtype=np.float32).reshape(n, nrec)
+    index = {ef: i for i, ef in enumerate(table)}
+    seen = np.zeros(n, dtype=bool)
+    dx = dt_ = 0.0
+    tscale = np.abs(rows[:, 6 + nin:]).max()
+    for r in rows:
+        st, stage, e, f, j = int(r[0]) - 6, int(r[1]), int(r[2]), int(r[3]), int(r[4])
+        i = (st * 3 + stage) * per + index[(e, f)] * Fn + j
+        tgt = r[6 + nin:]
+        if np.abs(tgt).max() > 64:
+            assert rec[i, nin + V] == 0.0
+            continue
+        assert rec[i, nin + V] == 1.0
+        seen[i] = True
+        dx = max(dx, np.abs(rec[i, :nin] - r[6:6 + nin]).max())
+        dt_ = max(dt_, np.abs(rec[i, nin:nin + V] - tgt).max())
+    say("  oracle pairs", len(rows), " gpu weighted", int(rec[:, nin + V].sum()), " max |dx|", dx,
+        " max |dtarget|", dt_, " target scale", tscale)
+    assert len(rows) > 1000
+    assert int(rec[:, nin + V].sum()) == int(seen.sum())
+    assert dx <= 2e-6
+    assert dt_ <= 1e-5 * max(1.0, tscale)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_bf16_inference_matches_oracle(oracle_mod, dim):
     O = oracle_mod
@@ -89,7 +222,7 @@ def test_learned_mode_parity_with_oracle(oracle_mod):
     O = oracle_mod
     say("case: learned ghosts with fixed weights vs oracle, 3D p=2 8^3 parts 2^3, 14 steps")
     cfg = dict(dim=3, cells=(8, 8, 8), parts=(2, 2, 2), hi=(1, 1, 1), ghost=3, delay_kind=1, L=3, levels=3, seed=2,
-               learned_tol=1e-6)
+               learned_tol=1e-6, learned_judge=0)
     o = O.Oracle(p=2, **cfg)
     o.init_problem(O.DENSITY_WAVE)
     s = _solver(degree=2, **cfg)
@@ -148,7 +281,7 @@ def test_learned_judge_matches_oracle(oracle_mod, bias, tol, expect, judge):
     assert r <= 1e-11
 
 
-@pytest.mark.parametrize("kind,cfl,max_resid", [(2, 0.1, 0.4), (1, 0.05, 1.0)])
+@pytest.mark.parametrize("kind,cfl,max_resid", [(2, 0.1, 0.4), (1, 0.05, 0.85)])
 def test_train_on_solver_traces_beats_at(oracle_mod, kind, cfl, max_resid):
     """Collect (features, live-minus-AT) pairs from the solver, train on the
     GPU, then measure on fresh pairs how much of AT's trace error remains,
@@ -208,7 +341,7 @@ def test_train_on_solver_traces_beats_at(oracle_mod, kind, cfl, max_resid):
     # belongs to the 128^3 workload, whose corrections are ~1e-7).
     runs = {}
     for name in ("sync", "at", "learned"):
-        r = _solver(ghost=0 if name == "sync" else 3, learned_tol=1e-4, **cfg)
+        r = _solver(ghost=0 if name == "sync" else 3, learned_tol=1e-4, learned_judge=0, **cfg)
         if name == "learned":
             r.predictor_set(w)
         r.init_problem(O.DENSITY_WAVE)
@@ -229,7 +362,7 @@ def test_learned_mode_in_a_dirichlet_box(oracle_mod):
     say("case: learned ghosts, fixed weights, paper vortex Dirichlet box 32x32 p=2 parts 4x4, 14 steps")
     prm = (5.0, 0.0, 5.0, 1.0, 0.0)
     cfg = dict(dim=2, cells=(32, 32, 1), parts=(4, 4, 1), lo=(0, -5, 0), hi=(10, 5, 1), ghost=3, delay_kind=2, L=3,
-               levels=3, seed=2, learned_tol=1e-4)
+               levels=3, seed=2, learned_tol=1e-4, learned_judge=0)
     o = O.Oracle(p=2, bc=O.DIRICHLET, bc_problem=O.VORTEX, bc_params=prm, **cfg)
     o.init_problem(O.VORTEX, prm)
     s = _solver(degree=2, boundary=1, **cfg)
@@ -248,3 +381,51 @@ def test_learned_mode_in_a_dirichlet_box(oracle_mod):
     say("  rel L2", r, "gpu accept", rate, judged, "oracle", acc_o, rej_o)
     assert r <= 1e-11
     assert judged == acc_o + rej_o and judged > 0 and abs(rate * judged - acc_o) <= max(1, 1e-3 * judged)
+
+
+def test_trained_predictor_at_the_configured_workload(oracle_mod):
+    """The learned mode of the 128^3 density-wave workload (degree 2, 8^3
+    subdomains, uniform delays up to 4, CFL 0.05) as configured: accept bound
+    1e-6 and the default judge (a correction must stay within the bound and
+    within AT's own error estimate |AT4 - AT3| on the face). The network is
+    trained on the GPU on one step of pairs this mesh's own run gives after
+    24 steps (2 epochs of Adam), as the benchmark does. Against the live
+    stage values the ghosts it uses are closer than AT's, and after 100
+    steps the state is closer to the synchronous run than the AT run's."""
+    O = oracle_mod
+    say("case: trained predictor, bound 1e-6, default judge, density wave 128^3 p=2, parts 8^3, uniform L=4")
+    cfg = dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), hi=(1, 1, 1), delay_kind=1, L=4, levels=3,
+               seed=0)
+    c = _solver(ghost=3, **cfg)
+    c.init_problem(O.DENSITY_WAVE)
+    dt = c.stable_dt(0.05)
+    c.step(24, dt)
+    c.predictor_bind(c.n_face_sides() * 9 * 3)
+    n = c.predictor_collect(1, dt)
+    loss = c.predictor_train(epochs=2, batch=4096, lr=1e-3, seed=1)
+    w = c.predictor_get()
+    say("  pairs", n, " final loss", loss)
+    c.close()
+    del c
+    runs, stats = {}, {}
+    for name in ("sync", "at", "learned"):
+        r = _solver(ghost=0 if name == "sync" else 3, learned_tol=1e-6, **cfg)
+        if name == "learned":
+            r.predictor_set(w)
+        r.init_problem(O.DENSITY_WAVE)
+        r.step(100, dt)
+        runs[name] = r.download()
+        if name != "sync":
+            stats[name] = r.predictor_stats(trace_errors=True)
+            say(f"  {name}: accept rate, faces judged, mean trace error used / AT", stats[name])
+        r.close()
+        del r
+    d_at = np.linalg.norm(runs["at"] - runs["sync"]) / np.linalg.norm(runs["sync"])
+    d_le = np.linalg.norm(runs["learned"] - runs["sync"]) / np.linalg.norm(runs["sync"])
+    say("  rel ||AT - sync||", d_at, " rel ||learned - sync||", d_le)
+    rate, judged, te, ta = stats["learned"]
+    assert judged > 0 and rate > 0
+    # the AT run uses AT everywhere: its used error is AT's
+    assert stats["at"][2] == pytest.approx(stats["at"][3], rel=1e-12)
+    assert te < ta
+    assert d_le < d_at
