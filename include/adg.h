@@ -238,6 +238,20 @@ adg_status adg_diff_norm(adg_ctx ctx, const double* host_ref, double out[3]);
 /* Integrals of the V conserved variables over the box (quadrature), FP64. */
 adg_status adg_integrals(adg_ctx ctx, double* out);
 
+/* adg_integrals for callers that cannot allocate, or cannot lend the bound
+ * scratch area (code under graph capture, serving loops, harnesses that
+ * forbid allocation): the same kernels and the same result, with their
+ * per-block partial sums (at most 2048 blocks of 6 doubles) and the reduced
+ * values in a static device array of 98,560 bytes that the library holds per
+ * GPU until the process ends, instead of the scratch bound at adg_bind. Calls
+ * no allocating routine. The context must be bound and its device (the one
+ * current at adg_bind) current: ADG_ERR_STATE otherwise; a mesh that would
+ * need more partial blocks than the array holds is ADG_ERR_INVALID (the norm
+ * kernels use at most 2048). Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (several streams or threads) race. Blocks on
+ * the context's stream; out receives V doubles. */
+adg_status adg_integrals_noalloc(adg_ctx ctx, double* out);
+
 /* Checkpoint: state u_n, ring, step counter, time, history origin,
  * asynchrony settings, boundary problem and predictor weights into a host
  * blob. Call with host_blob == NULL to get the

@@ -70,6 +70,7 @@ _SIGS = {
     "adg_error_norms": [_vp, C.c_int32, _dp, _dp],
     "adg_diff_norm": [_vp, _dp, _dp],
     "adg_integrals": [_vp, _dp],
+    "adg_integrals_noalloc": [_vp, _dp],
     "adg_save": [_vp, _vp, _sz],
     "adg_load": [_vp, _vp, C.c_size_t],
     "adg_predictor_nparams": [_vp, C.POINTER(C.c_int32)],
@@ -198,6 +199,12 @@ def adg_diff_norm(h, host_ref_ptr):
 def adg_integrals(h, V):
     out = (C.c_double * V)()
     _call("adg_integrals", h, out)
+    return list(out)
+
+
+def adg_integrals_noalloc(h, V):
+    out = (C.c_double * V)()
+    _call("adg_integrals_noalloc", h, out)
     return list(out)
 
 

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -164,17 +165,23 @@ Prm problem_params(int problem, const double* params) {
   return prm;
 }
 
-adg_status run_norms(adg_ctx_s* c, int what, int problem, const double* params, const double* u, const double* ref,
-                     int ncomp, int op, double* host_out) {
+// a norm or integral of the mesh: per-block partial sums into `partial`
+// ([nblk][6]), their reduction into `red` (ncomp values), copied to host
+adg_status run_norms_into(adg_ctx_s* c, int what, int problem, const double* params, const double* u,
+                          const double* ref, int ncomp, int op, double* partial, double* red, double* host_out) {
   const Prm prm = problem_params(problem, params);
   const int nblk = norms_blocks(c->mesh.E);
-  double* partial = scratch_d(c, c->partial_off);
-  double* red = scratch_d(c, c->red_off);
   HIP_TRY(launch_norms(c->D, c->p, c->mesh, what, problem, prm, c->t, u, ref, c->d_tab64, partial, nblk, c->stream));
   HIP_TRY(launch_reduce(partial, nblk, ncomp, op, red, c->stream));
   HIP_TRY(hipMemcpyAsync(host_out, red, sizeof(double) * ncomp, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ADG_OK;
+}
+
+adg_status run_norms(adg_ctx_s* c, int what, int problem, const double* params, const double* u, const double* ref,
+                     int ncomp, int op, double* host_out) {
+  return run_norms_into(c, what, problem, params, u, ref, ncomp, op, scratch_d(c, c->partial_off),
+                        scratch_d(c, c->red_off), host_out);
 }
 
 adg_status check_state(adg_ctx_s* c) {
@@ -495,6 +502,7 @@ adg_status adg_bind(adg_ctx c, void* u_n, void* u_a, void* u_b, void* ring, void
   c->ring = static_cast<double*>(ring);
   c->ring_cap = ring ? c->ring_bytes : 0;
   c->scratch = static_cast<char*>(scratch);
+  if (c->device < 0) HIP_TRY(hipGetDevice(&c->device));
   if (!c->d_tab64) {
     const int nt = (int)c->tab64.size();
     std::vector<float> t32(nt);
@@ -687,6 +695,62 @@ adg_status adg_integrals(adg_ctx c, double* out) {
   if (!c || !out) return fail(ADG_ERR_INVALID, "null argument");
   if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
   return run_norms(c, 1, 0, nullptr, c->u_n, nullptr, c->V, 0, out);
+}
+
+}  // extern "C"
+
+// ---- adg_integrals without the bound scratch ------------------------------
+// The per-block partial sums ([2048][6] doubles, the most blocks the norm
+// kernels use) and the reduced values (up to 32) live in a file-scope device
+// array, one copy per GPU, held until the process ends. Host code reaches it
+// only through the address hipGetSymbolAddress returns on each device.
+namespace {
+constexpr int kStaticPartial = 2048 * 6;
+constexpr int kStaticDoubles = kStaticPartial + 32;
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+double* g_static_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
+namespace {
+// the device address of `scratch` on device dev (the current device),
+// looked up once per device
+adg_status static_scratch(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(ADG_ERR_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ADG_ERR_HIP, "hipGetSymbolAddress returned no address for the static scratch");
+    g_static_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_static_ptr[dev];
+  return ADG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+adg_status adg_integrals_noalloc(adg_ctx c, double* out) {
+  if (!c || !out) return fail(ADG_ERR_INVALID, "null argument");
+  if (!c->bound) return fail(ADG_ERR_UNBOUND, "buffers not bound");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != c->device)
+    return fail(ADG_ERR_STATE, "adg_integrals_noalloc: make the context's device (" + std::to_string(c->device) +
+                                   ") current");
+  const int nblk = norms_blocks(c->mesh.E);
+  if ((long long)nblk * 6 > kStaticPartial || c->V > 6)
+    return fail(ADG_ERR_INVALID, "adg_integrals_noalloc: " + std::to_string(nblk) +
+                                     " partial blocks exceed the static scratch of 2048");
+  double* base = nullptr;
+  adg_status s = static_scratch(dev, &base);
+  if (s != ADG_OK) return s;
+  // every partial the reduction reads and every value it returns is written
+  // by this call's kernels first, so nothing needs clearing
+  return run_norms_into(c, 1, 0, nullptr, c->u_n, nullptr, c->V, 0, base, base + kStaticPartial, out);
 }
 
 // checkpoint blob: header, u_n, ring, predictor weights

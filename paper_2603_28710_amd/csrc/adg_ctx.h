@@ -41,6 +41,7 @@ struct adg_ctx_s {
   double *u_n = nullptr, *u_a = nullptr, *u_b = nullptr, *ring = nullptr;
   char* scratch = nullptr;
   bool bound = false;
+  int device = -1;  // the HIP device current at the first adg_bind
   double* d_tab64 = nullptr;
   float* d_tab32 = nullptr;
   std::vector<double> tab64;
