@@ -13,11 +13,16 @@
 //
 //   volume: one Gauss plane q_z at a time. The lane combines its nodal
 //           planes along z (B), interpolates the result in x and y, and
-//           stores the plane's values; row by row it then reads the full
-//           state, forms its own flux components F_x[v], F_y[v], F_z[v]
-//           (eq. euler-dealii) and accumulates
-//             k += (2/h_x) (GW (x) BW (x) BW) F_x + (2/h_y) (BW (x) GW (x) BW) F_y
-//                + (2/h_z) (BW (x) BW (x) GW) F_z
+//           stores the plane's values. Once per Gauss point (three points
+//           per lane) the scaled velocity s_a u_a (s_a = 2/h_a) and the
+//           pressure are formed and stored beside the state. Row by row each
+//           lane then forms its own scaled flux components s_a F_a[v]
+//           (eq. euler-dealii; four FMAs per point) and tests them along x;
+//           the y test accumulates over the plane's rows into A (x- and
+//           y-derivative terms) and C (z term), and the plane's z test
+//           adds them once:
+//             k += (GW (x) BW (x) BW) s_x F_x + (BW (x) GW (x) BW) s_y F_y
+//                + (BW (x) BW (x) GW) s_z F_z
 //           (BW = M1^{-1} B^T W, GW = M1^{-1} B^T D^T W per direction;
 //           eq. weakform-dealii / weakform-compact-dealii).
 //   faces:  one face direction at a time. Each lane interpolates its own and
@@ -65,6 +70,10 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
   // the faces; one spare element slot for the idle lanes; the stride is
   // padded so 16-byte reads of consecutive elements spread over the banks
   constexpr int PER0 = 2 * Fq * V;
+  // during the volume: the plane's state [Fq][V], then from kPre the
+  // scaled velocity and pressure [Fq][4] (16-byte aligned)
+  constexpr int kPre = (Fq * V + 3) / 4 * 4;
+  static_assert(kPre + 4 * Fq <= PER0, "volume data exceed the element's LDS block");
   constexpr int PER = sizeof(T) == 8 ? PER0 + (6 - PER0 % 4) % 4 : PER0 + (12 - PER0 % 8) % 8;
   // the same LDS stages the wavefront's element data (FP64) at the start and
   // the end of the stage
@@ -96,7 +105,8 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
   {
     const T gm1 = (T)M.gamma - (T)1;
     const T sx = (T)(2.0 / M.h[0]), sy = (T)(2.0 / M.h[1]), sz = (T)(2.0 / M.h[2]);
-    const T e1 = v == 1 ? (T)1 : (T)0, e2 = v == 2 ? (T)1 : (T)0, e3 = v == 3 ? (T)1 : (T)0;
+    // this lane's pressure terms of the scaled flux columns s_a F_a[v]
+    const T cx = v == 1 ? sx : (T)0, cy = v == 2 ? sy : (T)0, cz = v == 3 ? sz : (T)0;
     const T e4 = v == 4 ? (T)1 : (T)0;
 #pragma unroll 1
     for (int qz = 0; qz < Q; ++qz) {
@@ -141,51 +151,74 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
           }
       }
       __syncthreads();
-      // flux components of this lane's variable, tested row by row
+      // once per Gauss point (three points per lane): the scaled velocity
+      // s_a u_a and the pressure (eq. euler-parameters-dealii), after the
+      // point's state in the element's LDS block
+#pragma unroll
+      for (int it = 0; it < (NE * Fq + 63) / 64; ++it) {
+        const int t = lane + 64 * it;
+        if (t < NE * Fq) {
+          const int el = t / Fq, m = t - el * Fq;
+          const T* w = sX + el * PER + m * V;
+          const T rho = w[0], mx = w[1], my = w[2], mz = w[3], en = w[4];
+          const T ir = recip(rho);
+          const T ux = mx * ir, uy = my * ir, uz = mz * ir;
+          const T p = gm1 * (en - (T)0.5 * fmx(mz, uz, fmx(my, uy, mx * ux)));
+          T* d = sX + el * PER + kPre + 4 * m;
+          d[0] = sx * ux;
+          d[1] = sy * uy;
+          d[2] = sz * uz;
+          d[3] = p;
+        }
+      }
+      __syncthreads();
+      // the scaled flux columns of this lane's variable, tested with the
+      // x operators per Gauss row, then with the y operators into the
+      // plane's accumulators A (x- and y-derivative terms) and C (z term)
+      T A[P][P], C[P][P];
+#pragma unroll
+      for (int iy = 0; iy < P; ++iy)
+#pragma unroll
+        for (int ix = 0; ix < P; ++ix) A[iy][ix] = C[iy][ix] = (T)0;
 #pragma unroll
       for (int qy = 0; qy < Q; ++qy) {
         T tx[P], ty[P], tz[P];
 #pragma unroll
+        for (int i = 0; i < P; ++i) tx[i] = ty[i] = tz[i] = (T)0;
+#pragma unroll
         for (int qx = 0; qx < Q; ++qx) {
-          const T* w = mine + (qy * Q + qx) * V;
-          const T rho = w[0], mx = w[1], my = w[2], mz = w[3], en = w[4];
-          const T wv = w[v];
-          const T ir = recip(rho);
-          const T ux = mx * ir, uy = my * ir, uz = mz * ir;
-          const T p = gm1 * (en - (T)0.5 * fmx(mz, uz, fmx(my, uy, mx * ux)));
+          const int m = qy * Q + qx;
+          const T wv = mine[m * V + v];
+          const T* d = mine + kPre + 4 * m;
+          const T su_x = d[0], su_y = d[1], su_z = d[2], p = d[3];
+          // s_a F_a[v] = s_a u_a (w_v + p [v=4]) + s_a p [v=1+a]
           const T t = fmx(p, e4, wv);
-          // F_a[v] = u_a (w_v + p [v=4]) + p [v=1+a]
-          const T fx = fmx(ux, t, p * e1), fy = fmx(uy, t, p * e2), fz = fmx(uz, t, p * e3);
+          const T fx = fmx(su_x, t, p * cx), fy = fmx(su_y, t, p * cy), fz = fmx(su_z, t, p * cz);
 #pragma unroll
           for (int i = 0; i < P; ++i) {
-            if (qx == 0) {
-              tx[i] = (T)O.GW[i][0] * fx;
-              ty[i] = (T)O.BW[i][0] * fy;
-              tz[i] = (T)O.BW[i][0] * fz;
-            } else {
-              tx[i] = fmx((T)O.GW[i][qx], fx, tx[i]);
-              ty[i] = fmx((T)O.BW[i][qx], fy, ty[i]);
-              tz[i] = fmx((T)O.BW[i][qx], fz, tz[i]);
-            }
+            tx[i] = fmx((T)O.GW[i][qx], fx, tx[i]);
+            ty[i] = fmx((T)O.BW[i][qx], fy, ty[i]);
+            tz[i] = fmx((T)O.BW[i][qx], fz, tz[i]);
           }
         }
 #pragma unroll
-        for (int iy = 0; iy < P; ++iy) {
-          T ab[P], c[P];
+        for (int iy = 0; iy < P; ++iy)
 #pragma unroll
           for (int ix = 0; ix < P; ++ix) {
-            ab[ix] = fmx((T)O.GW[iy][qy] * sy, ty[ix], ((T)O.BW[iy][qy] * sx) * tx[ix]);
-            c[ix] = ((T)O.BW[iy][qy] * sz) * tz[ix];
+            A[iy][ix] = fmx((T)O.GW[iy][qy], ty[ix], fmx((T)O.BW[iy][qy], tx[ix], A[iy][ix]));
+            C[iy][ix] = fmx((T)O.BW[iy][qy], tz[ix], C[iy][ix]);
           }
-#pragma unroll
-          for (int iz = 0; iz < P; ++iz)
-#pragma unroll
-            for (int ix = 0; ix < P; ++ix) {
-              const int n = (iz * P + iy) * P + ix;
-              k[n] = fmx(gw[iz], c[ix], fmx(bw[iz], ab[ix], k[n]));
-            }
-        }
       }
+      // the z operators of this plane: k += BW_z (x) A + GW_z (x) C
+#pragma unroll
+      for (int iz = 0; iz < P; ++iz)
+#pragma unroll
+        for (int iy = 0; iy < P; ++iy)
+#pragma unroll
+          for (int ix = 0; ix < P; ++ix) {
+            const int n = (iz * P + iy) * P + ix;
+            k[n] = fmx(gw[iz], C[iy][ix], fmx(bw[iz], A[iy][ix], k[n]));
+          }
     }
   }
 
