@@ -283,35 +283,47 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
       sFsF[le] = fs;
       sKdF[le] = kd;
     }
-    // own and neighbour traces at the Gauss points (q0 + Q q1) of the face
+    // own trace at the Gauss points first (its work covers the neighbour
+    // loads), then the neighbour's
     {
-      T Xo[P][Q], Xn[P][Q];
+      T Xo[P][Q];
 #pragma unroll
       for (int j1 = 0; j1 < P; ++j1)
 #pragma unroll
         for (int q0 = 0; q0 < Q; ++q0) {
           T o = (T)O.B[q0][0] * (T)u[node3<P>(a, ia, 0, j1)];
-          T n = (T)O.B[q0][0] * (T)g[P * j1];
 #pragma unroll
-          for (int j0 = 1; j0 < P; ++j0) {
-            o = fmx((T)O.B[q0][j0], (T)u[node3<P>(a, ia, j0, j1)], o);
-            n = fmx((T)O.B[q0][j0], (T)g[j0 + P * j1], n);
-          }
+          for (int j0 = 1; j0 < P; ++j0) o = fmx((T)O.B[q0][j0], (T)u[node3<P>(a, ia, j0, j1)], o);
           Xo[j1][q0] = o;
-          Xn[j1][q0] = n;
         }
 #pragma unroll
       for (int q1 = 0; q1 < Q; ++q1)
 #pragma unroll
         for (int q0 = 0; q0 < Q; ++q0) {
           T o = (T)O.B[q1][0] * Xo[0][q0];
+#pragma unroll
+          for (int j1 = 1; j1 < P; ++j1) o = fmx((T)O.B[q1][j1], Xo[j1][q0], o);
+          mine[(q1 * Q + q0) * V + v] = o;
+        }
+    }
+    {
+      T Xn[P][Q];
+#pragma unroll
+      for (int j1 = 0; j1 < P; ++j1)
+#pragma unroll
+        for (int q0 = 0; q0 < Q; ++q0) {
+          T n = (T)O.B[q0][0] * (T)g[P * j1];
+#pragma unroll
+          for (int j0 = 1; j0 < P; ++j0) n = fmx((T)O.B[q0][j0], (T)g[j0 + P * j1], n);
+          Xn[j1][q0] = n;
+        }
+#pragma unroll
+      for (int q1 = 0; q1 < Q; ++q1)
+#pragma unroll
+        for (int q0 = 0; q0 < Q; ++q0) {
           T n = (T)O.B[q1][0] * Xn[0][q0];
 #pragma unroll
-          for (int j1 = 1; j1 < P; ++j1) {
-            o = fmx((T)O.B[q1][j1], Xo[j1][q0], o);
-            n = fmx((T)O.B[q1][j1], Xn[j1][q0], n);
-          }
-          mine[(q1 * Q + q0) * V + v] = o;
+          for (int j1 = 1; j1 < P; ++j1) n = fmx((T)O.B[q1][j1], Xn[j1][q0], n);
           mine[(Fq + q1 * Q + q0) * V + v] = n;
         }
     }
