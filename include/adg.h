@@ -170,8 +170,11 @@ adg_status adg_upload(adg_ctx ctx, const double* host, size_t n);
 adg_status adg_download(adg_ctx ctx, double* host, size_t n);
 
 /* L2 projection of an analytic problem (ADG_VORTEX, ...) at t = 0 into u_n,
- * computed on the GPU. params may be NULL for the defaults (vortex
- * 5,5,5,1,1; density wave 0.2,1,1,1,1; constant 1,0.3,-0.2,0.1,1). Resets
+ * computed on the GPU: u = M_e^{-1} (phi, w_exact)_e with the element mass
+ * matrix of Sec. 2.1 (eq. weakform-compact-dealii) and the Gauss rule of
+ * p + 2 points per direction; the vortex is the test problem of Sec. 5.1.
+ * params may be NULL for the defaults (vortex 5,5,5,1,1; density wave
+ * 0.2,1,1,1,1; constant 1,0.3,-0.2,0.1,1). Resets
  * n, t and the history, and makes the problem the boundary problem. */
 adg_status adg_init_problem(adg_ctx ctx, int32_t problem, const double* params);
 
@@ -187,7 +190,15 @@ adg_status adg_set_boundary(adg_ctx ctx, int32_t problem, const double* params);
 adg_status adg_set_async(adg_ctx ctx, const adg_async* async);
 
 /* Advance n_steps steps of the configured integrator, of fixed size dt (> 0;
- * n_steps == 0 does nothing). Asynchronous on the stream unless
+ * n_steps == 0 does nothing). Each stage evaluates the right-hand side
+ * M^{-1} R(w) of Sec. 2.1 (eq. weakform-dealii, weakform-compact-dealii) with
+ * the numerical flux of Sec. 2.2 on every face; at PE-boundary faces the
+ * neighbour trace follows the asynchrony settings (Sec. 3: the delayed trace
+ * of eq. delayed-flux, the AT extrapolation of eq. at-flux with the naive
+ * stage coupling tau = k + c_m of Sec. 3.2, the stored fluxes of Alg.
+ * caa-std / caa-at); the stages combine as the integrator prescribes (SSP-RK3
+ * Shu-Osher form; eq. lserk-dg for LSERK). The time step dt stays fixed, as
+ * the AT weights assume uniform steps (Sec. 3.2). Asynchronous on the stream unless
  * check_every > 0, in which case the state is checked (finite, rho > 0,
  * p > 0) every check_every steps and at the end of the call, with a blocking
  * read of one flag: ADG_ERR_NONFINITE / ADG_ERR_NONPHYSICAL. */
@@ -227,7 +238,8 @@ adg_status adg_time(adg_ctx ctx, int64_t* n, double* t);
 adg_status adg_stable_dt(adg_ctx ctx, double cfl, double* dt);
 
 /* Quadrature (n_q Gauss points) L2 norms of u_n minus the exact solution at
- * the current time: out = {rho, |rho u| (vector), E}. */
+ * the current time: out = {rho, |rho u| (vector), E}; the error measure of
+ * the convergence study (Sec. 5.3). */
 adg_status adg_error_norms(adg_ctx ctx, int32_t problem, const double* params, double out[3]);
 
 /* Relative L2 difference of u_n against a host state of the public layout,
@@ -235,7 +247,11 @@ adg_status adg_error_norms(adg_ctx ctx, int32_t problem, const double* params, d
  * ||u - ref|| / ||ref||. */
 adg_status adg_diff_norm(adg_ctx ctx, const double* host_ref, double out[3]);
 
-/* Integrals of the V conserved variables over the box (quadrature), FP64. */
+/* Integrals of the V conserved variables over the box (quadrature), FP64:
+ * the conservation check of the scheme (Sec. 3.3 states that the CAA-AT
+ * algorithm keeps local conservation: its stored fluxes are one value per
+ * face; the trace modes, where each side of a PE face builds its own flux,
+ * do not conserve under asynchrony). out receives V doubles. */
 adg_status adg_integrals(adg_ctx ctx, double* out);
 
 /* adg_integrals for callers that cannot allocate, or cannot lend the bound

@@ -1,6 +1,6 @@
 """Convergence of the asynchronous schemes on the GPU solver.
 
-The paper's accuracy study (Sec. 5.1, the convergence figures of the
+The paper's accuracy study (Sec. 5.3, the convergence figures of the
 isentropic vortex) shows that delayed neighbour data with the standard flux
 degrade the scheme to first order, while AT extrapolation over past levels
 recovers the synchronous curve and its order p + 1. Three settings:

@@ -3,7 +3,7 @@
 settings (8x8 virtual subdomains, degree 3, uniform random delays up to L=3):
 delayed traces with the standard flux lose the order of accuracy, AT
 extrapolation over three past levels recovers the synchronous errors and
-order p + 1 (Sec. 5.1, the convergence figures). Errors are against the
+order p + 1 (Sec. 5.3, the convergence figures). Errors are against the
 exact vortex; the time step scales as h^(4/3) so that SSP-RK3's time error
 stays below the spatial one at degree 3.
 """
@@ -38,7 +38,7 @@ def test_at_recovers_order_p_plus_1_stale_does_not():
 
 @pytest.mark.parametrize("degree", [1, 2])
 def test_paper_setting_caa_at_matches_sync_caa_std_first_order(degree):
-    # the paper's own runs (the convergence figures of Sec. 5.1): vortex with
+    # the paper's own runs (the convergence figures of Sec. 5.3): vortex with
     # mean flow (1,0) in the Dirichlet box [0,10] x [-5,5] to t = 4, 16x16
     # subdomains, CAA schedules with L = 4, LSERK(p+1,p+1), AT over p+1
     # levels; CFL 0.05 (sync, AT) and 0.03 (standard flux)
