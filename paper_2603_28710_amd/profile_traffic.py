@@ -48,7 +48,8 @@ def run(workload, steps):
     s = Solver(device="cuda:0", precision=w["precision"], **w["cfg"], **w["asy"])
     s.init_problem(w["problem"], w.get("params"))
     if w["asy"]["ghost"] == 3:
-        s.predictor_init(w["net_seed"])
+        # the ghost kernel's traffic and work do not depend on the weights
+        s.predictor_init(w.get("train", {}).get("seed", 1))
     dt = s.stable_dt(w.get("cfl", 0.1))
     s.step(steps, dt)
     torch.cuda.synchronize()
