@@ -25,14 +25,20 @@
 //                + (BW (x) BW (x) GW) s_z F_z
 //           (BW = M1^{-1} B^T W, GW = M1^{-1} B^T D^T W per direction;
 //           eq. weakform-dealii / weakform-compact-dealii).
-//   faces:  one face direction at a time. Each lane interpolates its own and
-//           the neighbour's face traces (live values; the delayed / AT /
-//           learned trace at a PE-boundary face; or, in the flux-history
-//           modes, the stored flux) to the face's Gauss points; one lane per
-//           (element, point) evaluates the LLF flux (eq. lfflux /
-//           lfflux-lambda) in canonical (left, right) order; each lane lifts
-//           its variable with BW along the two tangential axes and adds the
-//           column of M1^{-1} at that face.
+//   faces:  the x faces in one pass: the wavefront's elements are
+//           consecutive in x, so each lane interpolates its own traces on both
+//           x faces, and a face between two of its elements (same row, not a
+//           PE face of an asynchronous run) gets its LLF flux once for both
+//           sides; only the other x face-sides (the wavefront's two ends, a
+//           row break, PE faces; at most four, else the per-face passes
+//           below) take a neighbour trace. Then one pass per y and z face:
+//           each lane interpolates its own and the neighbour's face traces
+//           (live values; the delayed / AT / learned trace at a PE-boundary
+//           face; or, in the flux-history modes, the stored flux) to the
+//           face's Gauss points; one lane per (element, point) evaluates the
+//           LLF flux (eq. lfflux / lfflux-lambda) in canonical (left, right)
+//           order; each lane lifts its variable with BW along the two
+//           tangential axes and adds the column of M1^{-1} at that face.
 //   stage:  out = a u_n + b (u_in + dt k) in FP64, u_n and out through LDS.
 //
 // The ring publish (stage 0, stale and AT modes), the delay schedule, the AT
@@ -77,12 +83,15 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
   constexpr int PER = sizeof(T) == 8 ? PER0 + (6 - PER0 % 4) % 4 : PER0 + (12 - PER0 % 8) % 8;
   // the same LDS stages the wavefront's element data (FP64) at the start and
   // the end of the stage
-  constexpr int kXB = (NE + 1) * PER * (int)sizeof(T), kDB = NE * V * Pd * 8;
+  // the x pass adds kExtX outside traces [Fq][V] after the element slots
+  constexpr int kExtX = 4;
+  constexpr int kXB = ((NE + 1) * PER + kExtX * Fq * V) * (int)sizeof(T), kDB = NE * V * Pd * 8;
   __shared__ __align__(16) unsigned char sRaw[kXB > kDB ? kXB : kDB];
   T* sX = reinterpret_cast<T*>(sRaw);
   double* sD = reinterpret_cast<double*>(sRaw);
   __shared__ long long sFsF[NE + 1];  // flux-history modes: face-side of the current face, or -1
   __shared__ int sKdF[NE + 1];        // and its delay
+  __shared__ int sItem[2 * NE + 1];   // x pass: the flux items 2 l + side, then their count
 
   const int lane = threadIdx.x, le = lane / V, v = lane - le * V;  // le == NE: idle lane
   const long long e0 = (long long)xcd_block() * NE, e = e0 + le;
@@ -228,18 +237,17 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
   const bool flux_mode = src == kSrcFlux;
   const long long ring_level = M.nfs * V * (flux_mode ? Fq : Fn);  // values per ring level
   const bool publish = src == kSrcRing && A.stage == 0;
-  // one pass per face, with the face index a compile-time constant so that
-  // every register index below is fixed
-  auto face_pass = [&](auto fc) {
+  // the neighbour trace of variable v at the face nodes (j0 + P j1) of face
+  // f: live values, the delayed / AT / learned trace at a PE-boundary face
+  // (whose own trace is published at stage 0), nothing in a flux-history
+  // silent step; fs and kd receive the face-side and its delay
+  auto gather = [&](auto fc, double* g, long long& fs, int& kd) {
     constexpr int f = decltype(fc)::value;
     constexpr int a = f >> 1, s = f & 1, ia = s ? P - 1 : 0;
-    __syncthreads();  // sX is rewritten
-    // neighbour trace of variable v at the face nodes (j0 + P j1)
-    double g[Fn];
 #pragma unroll
     for (int j = 0; j < Fn; ++j) g[j] = 0.0;
-    long long fs = -1;
-    int kd = 0;
+    fs = -1;
+    kd = 0;
     if (valid) {
       fs = async_on ? face_side_at(M, pos, f) : -1;
       if (fs >= 0 && (src == kSrcRing || flux_mode)) kd = delay_of(M, A, sub_at(M, pos.sc), f);
@@ -279,54 +287,81 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
         }
       }
     }
+  };
+  // face-node values x[j0 + P j1] of variable v interpolated to the Gauss
+  // points (q0 + Q q1) of the face, stored at dst[(q0 + Q q1) V]
+  auto interp_face = [&](const auto& x, T* dst) {
+    T X[P][Q];
+#pragma unroll
+    for (int j1 = 0; j1 < P; ++j1)
+#pragma unroll
+      for (int q0 = 0; q0 < Q; ++q0) {
+        T o = (T)O.B[q0][0] * (T)x(0, j1);
+#pragma unroll
+        for (int j0 = 1; j0 < P; ++j0) o = fmx((T)O.B[q0][j0], (T)x(j0, j1), o);
+        X[j1][q0] = o;
+      }
+#pragma unroll
+    for (int q1 = 0; q1 < Q; ++q1)
+#pragma unroll
+      for (int q0 = 0; q0 < Q; ++q0) {
+        T o = (T)O.B[q1][0] * X[0][q0];
+#pragma unroll
+        for (int j1 = 1; j1 < P; ++j1) o = fmx((T)O.B[q1][j1], X[j1][q0], o);
+        dst[(q1 * Q + q0) * V] = o;
+      }
+  };
+  // lift of the scaled fluxes src[(q0 + Q q1) V] of face f with BW along both
+  // tangential axes, then k(i_a, j0, j1) += MC_s[i_a] * lifted(j0, j1)
+  auto lift_face = [&](auto fc, const T* src) {
+    constexpr int f = decltype(fc)::value;
+    constexpr int a = f >> 1, s = f & 1;
+    T L0[Q][P];
+#pragma unroll
+    for (int q1 = 0; q1 < Q; ++q1) {
+      T G[Q];
+#pragma unroll
+      for (int q0 = 0; q0 < Q; ++q0) G[q0] = src[(q1 * Q + q0) * V];
+#pragma unroll
+      for (int j0 = 0; j0 < P; ++j0) {
+        T acc = (T)O.BW[j0][0] * G[0];
+#pragma unroll
+        for (int q0 = 1; q0 < Q; ++q0) acc = fmx((T)O.BW[j0][q0], G[q0], acc);
+        L0[q1][j0] = acc;
+      }
+    }
+#pragma unroll
+    for (int j1 = 0; j1 < P; ++j1)
+#pragma unroll
+      for (int j0 = 0; j0 < P; ++j0) {
+        T lf = (T)O.BW[j1][0] * L0[0][j0];
+#pragma unroll
+        for (int q1 = 1; q1 < Q; ++q1) lf = fmx((T)O.BW[j1][q1], L0[q1][j0], lf);
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          const int n = node3<P>(a, i, j0, j1);
+          k[n] = fmx((T)O.MC[s][i], lf, k[n]);
+        }
+      }
+  };
+  // one pass per face, with the face index a compile-time constant so that
+  // every register index below is fixed
+  auto face_pass = [&](auto fc) {
+    constexpr int f = decltype(fc)::value;
+    constexpr int a = f >> 1, s = f & 1, ia = s ? P - 1 : 0;
+    __syncthreads();  // sX is rewritten
+    double g[Fn];
+    long long fs;
+    int kd;
+    gather(fc, g, fs, kd);
     if (flux_mode && v == 0) {
       sFsF[le] = fs;
       sKdF[le] = kd;
     }
     // own trace at the Gauss points first (its work covers the neighbour
     // loads), then the neighbour's
-    {
-      T Xo[P][Q];
-#pragma unroll
-      for (int j1 = 0; j1 < P; ++j1)
-#pragma unroll
-        for (int q0 = 0; q0 < Q; ++q0) {
-          T o = (T)O.B[q0][0] * (T)u[node3<P>(a, ia, 0, j1)];
-#pragma unroll
-          for (int j0 = 1; j0 < P; ++j0) o = fmx((T)O.B[q0][j0], (T)u[node3<P>(a, ia, j0, j1)], o);
-          Xo[j1][q0] = o;
-        }
-#pragma unroll
-      for (int q1 = 0; q1 < Q; ++q1)
-#pragma unroll
-        for (int q0 = 0; q0 < Q; ++q0) {
-          T o = (T)O.B[q1][0] * Xo[0][q0];
-#pragma unroll
-          for (int j1 = 1; j1 < P; ++j1) o = fmx((T)O.B[q1][j1], Xo[j1][q0], o);
-          mine[(q1 * Q + q0) * V + v] = o;
-        }
-    }
-    {
-      T Xn[P][Q];
-#pragma unroll
-      for (int j1 = 0; j1 < P; ++j1)
-#pragma unroll
-        for (int q0 = 0; q0 < Q; ++q0) {
-          T n = (T)O.B[q0][0] * (T)g[P * j1];
-#pragma unroll
-          for (int j0 = 1; j0 < P; ++j0) n = fmx((T)O.B[q0][j0], (T)g[j0 + P * j1], n);
-          Xn[j1][q0] = n;
-        }
-#pragma unroll
-      for (int q1 = 0; q1 < Q; ++q1)
-#pragma unroll
-        for (int q0 = 0; q0 < Q; ++q0) {
-          T n = (T)O.B[q1][0] * Xn[0][q0];
-#pragma unroll
-          for (int j1 = 1; j1 < P; ++j1) n = fmx((T)O.B[q1][j1], Xn[j1][q0], n);
-          mine[(Fq + q1 * Q + q0) * V + v] = n;
-        }
-    }
+    interp_face([&](int j0, int j1) { return u[node3<P>(a, ia, j0, j1)]; }, mine + v);
+    interp_face([&](int j0, int j1) { return g[j0 + P * j1]; }, mine + Fq * V + v);
     __syncthreads();
     // numerical flux, one lane per (element, face point), in place of the
     // own trace, scaled by -(n.e_a) 2/h_a
@@ -386,40 +421,102 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
       }
     }
     __syncthreads();
-    // lift with BW along both tangential axes, then k(i_a, j0, j1) +=
-    // MC_s[i_a] * lifted(j0, j1)
-    {
-      T L0[Q][P];
+    lift_face(fc, mine + v);
+  };
+  // the x faces of the wavefront's consecutive elements in one pass: each
+  // lane interpolates its own traces on both x faces, a face between two
+  // elements of the wavefront (same row, not a PE face of an asynchronous
+  // run) takes its flux once for both sides, and only the other face-sides
+  // (the wavefront's ends, a row break, PE faces) take a neighbour trace,
+  // from up to kExtX outside slots; otherwise the two per-face passes
+  bool x_shared = false;
+  if (!flux_mode) {
+    // bit l: the +x face of element l is shared with element l + 1
+    const bool pr = valid && le + 1 < ne && pos.c[0] + 1 < M.nc[0] && !(async_on && face_side_at(M, pos, 1) >= 0);
+    const unsigned long long bal = __ballot(v == 0 && pr);
+    unsigned pair = 0;
 #pragma unroll
-      for (int q1 = 0; q1 < Q; ++q1) {
-        T G[Q];
-#pragma unroll
-        for (int q0 = 0; q0 < Q; ++q0) G[q0] = mine[(q1 * Q + q0) * V + v];
-#pragma unroll
-        for (int j0 = 0; j0 < P; ++j0) {
-          T acc = (T)O.BW[j0][0] * G[0];
-#pragma unroll
-          for (int q0 = 1; q0 < Q; ++q0) acc = fmx((T)O.BW[j0][q0], G[q0], acc);
-          L0[q1][j0] = acc;
+    for (int l = 0; l < NE; ++l) pair |= (unsigned)((bal >> (V * l)) & 1ull) << l;
+    // bit 2l + s: face-side (l, s) takes an outside trace
+    unsigned ext = 0;
+    for (int l = 0; l < ne; ++l) {
+      if (l == 0 || !((pair >> (l - 1)) & 1u)) ext |= 1u << (2 * l);
+      if (!((pair >> l) & 1u)) ext |= 1u << (2 * l + 1);
+    }
+    if (__popc(ext) <= kExtX) {
+      x_shared = true;
+      __syncthreads();  // sX is rewritten
+      // flux items in order: (l, -x) if it takes an outside trace, (l, +x)
+      if (lane == 0) {
+        int n = 0;
+        for (int l = 0; l < ne; ++l) {
+          if ((ext >> (2 * l)) & 1u) sItem[n++] = l * 2;
+          sItem[n++] = l * 2 + 1;
         }
+        sItem[2 * NE] = n;
       }
+      T* outside = sX + (NE + 1) * PER;  // kExtX traces [Fq][V]
+      interp_face([&](int j0, int j1) { return u[node3<P>(0, 0, j0, j1)]; }, mine + v);
+      interp_face([&](int j0, int j1) { return u[node3<P>(0, P - 1, j0, j1)]; }, mine + Fq * V + v);
+      // the outside traces of the face-sides that take one, -x then +x (the
+      // gather publishes the own trace of a PE face at stage 0)
+      const unsigned below = le < NE ? (1u << (2 * le)) - 1u : 0u;
+      if (valid && ((ext >> (2 * le)) & 1u)) {
+        double g[Fn];
+        long long fs;
+        int kd;
+        gather(std::integral_constant<int, 0>{}, g, fs, kd);
+        interp_face([&](int j0, int j1) { return g[j0 + P * j1]; }, outside + __popc(ext & below) * Fq * V + v);
+      }
+      if (valid && ((ext >> (2 * le + 1)) & 1u)) {
+        double g[Fn];
+        long long fs;
+        int kd;
+        gather(std::integral_constant<int, 1>{}, g, fs, kd);
+        interp_face([&](int j0, int j1) { return g[j0 + P * j1]; },
+                    outside + __popc(ext & (below | (1u << (2 * le)))) * Fq * V + v);
+      }
+      __syncthreads();
+      // numerical flux, one lane per (item, face point): a shared face writes
+      // -s G to its left element's +x slot and +s G to its right element's -x
+      // slot; an outside face-side writes to its own slot only
+      {
+        const T gamma = (T)M.gamma;
+        const T sc = (T)(2.0 / M.h[0]);
+        const int nt = sItem[2 * NE] * Fq;
+#pragma unroll 1
+        for (int t = lane; t < nt; t += 64) {
+          const int it = sItem[t / Fq], m = t - (t / Fq) * Fq;
+          const int l = it >> 1, sd = it & 1;
+          T* own = sX + l * PER + (sd ? Fq * V : 0) + m * V;
+          const bool shared = sd && ((pair >> l) & 1u);
+          T* other = shared ? sX + (l + 1) * PER + m * V
+                            : outside + __popc(ext & ((1u << it) - 1u)) * Fq * V + m * V;
+          T wl[V], wr[V], G[V];
 #pragma unroll
-      for (int j1 = 0; j1 < P; ++j1)
+          for (int vv = 0; vv < V; ++vv) {
+            wl[vv] = sd ? own[vv] : other[vv];  // canonical order: left element first
+            wr[vv] = sd ? other[vv] : own[vv];
+          }
+          num_flux<T, 3>(wl, wr, 0, gamma, M.flux, G);
+          const T sg = sd ? -sc : sc;
 #pragma unroll
-        for (int j0 = 0; j0 < P; ++j0) {
-          T lf = (T)O.BW[j1][0] * L0[0][j0];
+          for (int vv = 0; vv < V; ++vv) own[vv] = sg * G[vv];
+          if (shared) {
 #pragma unroll
-          for (int q1 = 1; q1 < Q; ++q1) lf = fmx((T)O.BW[j1][q1], L0[q1][j0], lf);
-#pragma unroll
-          for (int i = 0; i < P; ++i) {
-            const int n = node3<P>(a, i, j0, j1);
-            k[n] = fmx((T)O.MC[s][i], lf, k[n]);
+            for (int vv = 0; vv < V; ++vv) other[vv] = sc * G[vv];
           }
         }
+      }
+      __syncthreads();
+      lift_face(std::integral_constant<int, 0>{}, mine + v);
+      lift_face(std::integral_constant<int, 1>{}, mine + Fq * V + v);
     }
-  };
-  face_pass(std::integral_constant<int, 0>{});
-  face_pass(std::integral_constant<int, 1>{});
+  }
+  if (!x_shared) {
+    face_pass(std::integral_constant<int, 0>{});
+    face_pass(std::integral_constant<int, 1>{});
+  }
   face_pass(std::integral_constant<int, 2>{});
   face_pass(std::integral_constant<int, 3>{});
   face_pass(std::integral_constant<int, 4>{});

@@ -242,6 +242,35 @@ def test_learned_mode_parity_with_oracle(oracle_mod):
     assert judged == acc_o + rej_o and abs(rate * judged - acc_o) <= max(1, 1e-3 * judged)
 
 
+@pytest.mark.parametrize("judge", [0, 1])
+def test_learned_mode_parity_larger_mesh(oracle_mod, judge):
+    """the learned mode with fixed weights on a 24^3 mesh of degree 2 in 4^3
+    subdomains (6^3 elements each), uniform delays up to 4 as the 128^3
+    workload has them, 12 steps past the warm-up, against the oracle running
+    the same weights; both judges"""
+    O = oracle_mod
+    say(f"case: learned ghosts, fixed weights, 3D p=2 24^3 parts 4^3, uniform L=4, judge {judge}, 12 steps")
+    cfg = dict(dim=3, cells=(24, 24, 24), parts=(4, 4, 4), hi=(1, 1, 1), ghost=3, delay_kind=1, L=4, levels=3,
+               seed=5, learned_tol=1e-6, learned_judge=judge)
+    o = O.Oracle(p=2, **cfg)
+    o.init_problem(O.DENSITY_WAVE)
+    s = _solver(degree=2, **cfg)
+    w = inputs.mlp_weights(s.predictor_nparams(), 8, 0.05).astype(np.float32)
+    s.predictor_set(w)
+    o.set_predictor(w)
+    s.upload(o.state())
+    dt = o.stable_dt(0.05)
+    o.step(12, dt)
+    s.step(12, dt)
+    a, b = s.download(), o.state()
+    r = np.linalg.norm(a - b) / np.linalg.norm(b)
+    acc_o, rej_o = o.learned_stats()
+    rate, judged = s.predictor_stats()
+    say("  rel L2", r, "gpu accept", rate, judged, "oracle", acc_o, rej_o)
+    assert r <= 1e-11
+    assert judged == acc_o + rej_o and judged > 0 and abs(rate * judged - acc_o) <= max(1, 1e-3 * judged)
+
+
 @pytest.mark.parametrize("bias,tol,expect,judge", [(1e20, 1e-6, "reject", 0), (1.0, 1e-6, "mixed", 0),
                                                    (1.0, 1e-6, "mixed", 1)])
 def test_learned_judge_matches_oracle(oracle_mod, bias, tol, expect, judge):
