@@ -66,34 +66,55 @@ __device__ __forceinline__ void num_flux(const T* wl, const T* wr, int a, T gamm
 // wavefront in 16-byte pieces (both addresses 16-byte aligned), four loads in
 // flight per lane before their stores: a wavefront's elements are one
 // contiguous range, so staging them through LDS turns per-lane strided
-// accesses into coalesced ones
-template <int NMAX>
+// accesses into coalesced ones. NT_LD / NT_ST mark the global loads / stores
+// non-temporal (streamed past L2 with low retention), for data no other
+// wavefront reads in this launch, so that L2 keeps the stage input the
+// neighbouring wavefronts read their face traces from.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ dvec2 ld2(const dvec2* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st2(dvec2* p, dvec2 x) {
+  if constexpr (NT) __builtin_nontemporal_store(x, p);
+  else *p = x;
+}
+template <int NMAX, bool NT_LD, bool NT_ST>
 __device__ __forceinline__ void wave_copy(double* dst, const double* src, int n) {
   constexpr int IT = (NMAX / 2 + 63) / 64;
   const int lane = threadIdx.x, n2 = n >> 1;
-  const double2* s2 = reinterpret_cast<const double2*>(src);
-  double2* d2 = reinterpret_cast<double2*>(dst);
+  const dvec2* s2 = reinterpret_cast<const dvec2*>(src);
+  dvec2* d2 = reinterpret_cast<dvec2*>(dst);
   // past the end a lane copies piece 0 again (the same value to the same
   // place), which keeps the loop free of branches
 #pragma unroll 1
   for (int k0 = 0; k0 < IT; k0 += 4) {
     const int i0 = lane + 64 * k0, i1 = i0 + 64, i2 = i0 + 128, i3 = i0 + 192;
     const int j0 = i0 < n2 ? i0 : 0, j1 = i1 < n2 ? i1 : 0, j2 = i2 < n2 ? i2 : 0, j3 = i3 < n2 ? i3 : 0;
-    const double2 a0 = s2[j0], a1 = s2[j1], a2 = s2[j2], a3 = s2[j3];
-    d2[j0] = a0;
-    d2[j1] = a1;
-    d2[j2] = a2;
-    d2[j3] = a3;
+    const dvec2 a0 = ld2<NT_LD>(s2 + j0), a1 = ld2<NT_LD>(s2 + j1), a2 = ld2<NT_LD>(s2 + j2),
+                a3 = ld2<NT_LD>(s2 + j3);
+    st2<NT_ST>(d2 + j0, a0);
+    st2<NT_ST>(d2 + j1, a1);
+    st2<NT_ST>(d2 + j2, a2);
+    st2<NT_ST>(d2 + j3, a3);
   }
   if ((n & 1) && lane == 0) dst[n - 1] = src[n - 1];
 }
+// the stage input: kept in L2 for the neighbours' face traces
 template <int NMAX>
 __device__ __forceinline__ void wave_copy_in(double* lds, const double* g, int n) {
-  wave_copy<NMAX>(lds, g, n);
+  wave_copy<NMAX, false, false>(lds, g, n);
+}
+// u^n and the stage output: streamed
+template <int NMAX>
+__device__ __forceinline__ void wave_stream_in(double* lds, const double* g, int n) {
+  wave_copy<NMAX, true, false>(lds, g, n);
 }
 template <int NMAX>
-__device__ __forceinline__ void wave_copy_out(double* g, const double* lds, int n) {
-  wave_copy<NMAX>(g, lds, n);
+__device__ __forceinline__ void wave_stream_out(double* g, const double* lds, int n) {
+  wave_copy<NMAX, false, true>(g, lds, n);
 }
 
 // logical block index: the hardware deals consecutive blocks round-robin to

@@ -171,6 +171,47 @@ __host__ __device__ inline void elem_coords(const Mesh& M, long long e, int* c) 
   c[2] = (int)z;
 }
 
+// Wavefront ranges of the hexahedron stage kernels: range b is up to NE
+// consecutive elements of one x row, each row cut into ceil(nx / NE) ranges.
+// The ranges are numbered with z fastest inside bands of kWaveBandZ layers
+// (the last band may be thinner), then y, then the band, then the range's
+// position along the row. A range's y and z neighbours are then at most
+// kWaveBandZ ranges away in the order an XCD walks its blocks (z neighbours
+// across a band edge aside), close enough that the face traces find the
+// neighbour's data, fetched by its own wavefront or by this one, still in
+// that XCD's L2; in x-fastest order a z neighbour is a whole element layer
+// (nx ny elements) away and is fetched again.
+constexpr int kWaveBandZ = 16;
+template <int NE>
+__host__ __device__ inline long long wave_ranges(const Mesh& M) {
+  return (long long)((M.nc[0] + NE - 1) / NE) * M.nc[1] * M.nc[2];
+}
+template <int NE>
+__device__ __forceinline__ void wave_range(const Mesh& M, int b, long long& e0, int& ne) {
+  const int nx = M.nc[0], ny = M.nc[1], nz = M.nc[2];
+  const int plane = ny * nz, c = b / plane;
+  int r = b - c * plane;
+  const int w = nz < kWaveBandZ ? nz : kWaveBandZ, full = nz / w, band = ny * w;
+  int y, z;
+  if (r < full * band) {
+    const int t = r / band;
+    r -= t * band;
+    y = r / w;
+    z = t * w + (r - y * w);
+  } else {
+    r -= full * band;
+    const int wl = nz - full * w;
+    y = r / wl;
+    z = full * w + (r - y * wl);
+  }
+  // wave-uniform: kept in scalar registers
+  const long long s = (long long)c * NE + (long long)nx * (y + (long long)ny * z);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)s),
+                 hi = __builtin_amdgcn_readfirstlane((unsigned)(s >> 32));
+  e0 = (long long)(((unsigned long long)hi << 32) | lo);
+  ne = __builtin_amdgcn_readfirstlane(nx - c * NE < NE ? nx - c * NE : NE);
+}
+
 __host__ __device__ inline int subdomain_of(const Mesh& M, const int* c) {
   return (int)(fdiv(c[0], M.dm[0]) + M.parts[0] * (fdiv(c[1], M.dm[1]) + M.parts[1] * fdiv(c[2], M.dm[2])));
 }

@@ -22,7 +22,8 @@
 //           eq. lfflux / lfflux-lambda in canonical (left, right) order, in
 //           place; every lane lifts its variable with BW and adds the column
 //           of M1^{-1} at that face.
-//   stage:  out = a u_n + b (u_in + dt k) in FP64 from the FP64 registers.
+//   stage:  out = a u_n + b (u_in + dt k) in FP64 from the FP64 registers,
+//           written to LDS and stored as one coalesced, streamed range.
 //
 // Both sides of an interior face evaluate the flux with the same instruction
 // stream on identical operands, so their contributions are bitwise opposite.
@@ -63,11 +64,11 @@ __device__ __forceinline__ void load_col(const double* __restrict__ p, double* u
   }
 }
 
+// at least two wavefronts per SIMD (at most 256 VGPRs)
 template <typename T, int P>
-__global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage S, const double* __restrict__ u_in,
-                                                         const double* u_n, double* out, int src,
-                                                         double* __restrict__ ring,
-                                                         const double* __restrict__ ghost) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rhs_stage2d_kernel(
+    Mesh M, Async A, Stage S, const double* __restrict__ u_in, const double* u_n, double* out, int src,
+    double* __restrict__ ring, const double* __restrict__ ghost) {
   constexpr int Q = P + 1, V = 4, NE = kNE2, Pd = P * P, Qd = Q * Q;
   constexpr ops::Ops<P> O = ops::make_ops<P>();
   // per element: the state at the Gauss points [Qd][V], later the face
@@ -76,14 +77,19 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
   // (stride = 4 x odd dwords)
   constexpr int PER0 = Qd * V > 16 * Q ? Qd * V : 16 * Q;
   constexpr int PER = sizeof(T) == 8 ? PER0 + (6 - PER0 % 4) % 4 : PER0 + (12 - PER0 % 8) % 8;
-  __shared__ __align__(16) T sX[NE * PER];
+  // the same LDS stages the wavefront's output (FP64) in the combine
+  constexpr int kXB = NE * PER * (int)sizeof(T), kDB = NE * V * Pd * 8;
+  __shared__ __align__(16) unsigned char sRaw[kXB > kDB ? kXB : kDB];
+  T* sX = reinterpret_cast<T*>(sRaw);
+  double* sD = reinterpret_cast<double*>(sRaw);
   // flux-history modes: per (element, face of the current axis) the
   // face-side offset in the flux ring (or -1) and the delay
   __shared__ long long sFsF[NE * 2];
   __shared__ int sKdF[NE * 2];
 
   const int lane = threadIdx.x, le = lane >> 2, v = lane & 3;
-  const long long e = (long long)xcd_block() * NE + le;
+  const long long e0 = (long long)xcd_block() * NE, e = e0 + le;
+  const int ne = M.E - e0 < NE ? (int)(M.E - e0) : NE;
   const bool valid = e < M.E;
   const long long col = (valid ? e : 0) * (V * Pd) + v * Pd;  // this lane's P^2 values
 
@@ -370,38 +376,51 @@ __global__ __launch_bounds__(64) void rhs_stage2d_kernel(Mesh M, Async A, Stage 
     }
   }
 
-  // ---- the stage combine in FP64
-  if (valid && S.lserk) {
+  // ---- the stage combine in FP64; each output goes through LDS (the lane
+  // writes its column there) and leaves as one coalesced range
+  __syncthreads();  // sX is rewritten
+  double* o = sD + (le * V + v) * Pd;
+  if (S.lserk) {
     // LSERK: u_n holds the accumulator w (read before either write); at the
     // first stage it is the stage input itself, already in registers
     double wv[Pd];
-    if (u_n == u_in) {
+    if (valid) {
+      if (u_n == u_in) {
 #pragma unroll
-      for (int i = 0; i < Pd; ++i) wv[i] = u[i];
-    } else if (kEarlyUn) {
+        for (int i = 0; i < Pd; ++i) wv[i] = u[i];
+      } else if (kEarlyUn) {
 #pragma unroll
-      for (int i = 0; i < Pd; ++i) wv[i] = un[i];
-    } else {
-      load_col<P>(u_n + col, wv);
+        for (int i = 0; i < Pd; ++i) wv[i] = un[i];
+      } else {
+        load_col<P>(u_n + col, wv);
+      }
+#pragma unroll
+      for (int i = 0; i < Pd; ++i) o[i] = wv[i] + S.dt * S.bw * (double)k[i];
     }
-    double* o = out + col;
-#pragma unroll
-    for (int i = 0; i < Pd; ++i) o[i] = wv[i] + S.dt * S.bw * (double)k[i];
+    __syncthreads();
+    wave_stream_out<NE * V * Pd>(out + e0 * V * Pd, sD, ne * V * Pd);
     if (S.out2) {
-      double* o2 = S.out2 + col;
+      __syncthreads();  // the first output has left LDS
+      if (valid) {
 #pragma unroll
-      for (int i = 0; i < Pd; ++i) o2[i] = wv[i] + S.dt * S.ar * (double)k[i];
+        for (int i = 0; i < Pd; ++i) o[i] = wv[i] + S.dt * S.ar * (double)k[i];
+      }
+      __syncthreads();
+      wave_stream_out<NE * V * Pd>(S.out2 + e0 * V * Pd, sD, ne * V * Pd);
     }
-  } else if (valid) {
-    double* o = out + col;
-    if (S.a == 0.0) {
+  } else {
+    if (valid) {
+      if (S.a == 0.0) {
 #pragma unroll
-      for (int i = 0; i < Pd; ++i) o[i] = S.b * (u[i] + S.dt * (double)k[i]);
-    } else {
-      if (!kEarlyUn) load_col<P>(u_n + col, un);
+        for (int i = 0; i < Pd; ++i) o[i] = S.b * (u[i] + S.dt * (double)k[i]);
+      } else {
+        if (!kEarlyUn) load_col<P>(u_n + col, un);
 #pragma unroll
-      for (int i = 0; i < Pd; ++i) o[i] = S.a * un[i] + S.b * (u[i] + S.dt * (double)k[i]);
+        for (int i = 0; i < Pd; ++i) o[i] = S.a * un[i] + S.b * (u[i] + S.dt * (double)k[i]);
+      }
     }
+    __syncthreads();
+    wave_stream_out<NE * V * Pd>(out + e0 * V * Pd, sD, ne * V * Pd);
   }
 }
 

@@ -1,7 +1,8 @@
 // adg_rhs3d.hip — the fused SSP-RK3 stage on hexahedral meshes of degree
 // 1 and 2, with the element data in registers.
 //
-// One wavefront owns 12 consecutive elements (x fastest); lane (e, v) keeps
+// One wavefront owns up to 12 consecutive elements of one x row (wave_range:
+// the wavefronts walk the mesh in z-bands); lane (e, v) keeps
 // the P^3 nodal values of variable v of element e in registers (lanes 60-63
 // idle) and applies the tensor-product operators of that variable there. LDS
 // carries what the nonlinear fluxes need (all V variables at a point) and,
@@ -63,11 +64,12 @@ __device__ __forceinline__ constexpr int node3(int a, int ia, int j0, int j1) {
   return a == 0 ? ia + P * (j0 + P * j1) : (a == 1 ? j0 + P * (ia + P * j1) : j0 + P * (j1 + P * ia));
 }
 
+// at least two wavefronts per SIMD (at most 256 VGPRs): the LDS the degree-2
+// FP64 kernel takes already limits a CU to eight wavefronts
 template <typename T, int P>
-__global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage S, const double* __restrict__ u_in,
-                                                         const double* u_n, double* out, int src,
-                                                         double* __restrict__ ring,
-                                                         const double* __restrict__ ghost) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rhs_stage3d_kernel(
+    Mesh M, Async A, Stage S, const double* __restrict__ u_in, const double* u_n, double* out, int src,
+    double* __restrict__ ring, const double* __restrict__ ghost) {
   constexpr int Q = P + 1, V = 5, NE = kNE3, Pd = P * P * P, Fn = P * P, Fq = Q * Q;
   constexpr ops::Ops<P> O = ops::make_ops<P>();
   const ops::RowOps<P>& OR = ops::kRowOps<P>;  // entries indexed at run time, by Gauss plane
@@ -94,9 +96,11 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
   __shared__ int sItem[2 * NE + 1];   // x pass: the flux items 2 l + side, then their count
 
   const int lane = threadIdx.x, le = lane / V, v = lane - le * V;  // le == NE: idle lane
-  const long long e0 = (long long)xcd_block() * NE, e = e0 + le;
-  const int ne = M.E - e0 < NE ? (int)(M.E - e0) : NE;
-  const bool valid = le < NE && e < M.E;
+  long long e0;
+  int ne;
+  wave_range<NE>(M, xcd_block(), e0, ne);
+  const long long e = e0 + le;
+  const bool valid = le < ne;
 
   double u[Pd];
   wave_copy_in<NE * V * Pd>(sD, u_in + e0 * V * Pd, ne * V * Pd);
@@ -527,7 +531,7 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
   if (S.lserk) {
     // LSERK: u_n holds the accumulator w; the new w to out, the next
     // stage input (if any) to out2
-    wave_copy_in<NE * V * Pd>(sD, u_n + e0 * V * Pd, ne * V * Pd);
+    wave_stream_in<NE * V * Pd>(sD, u_n + e0 * V * Pd, ne * V * Pd);
     __syncthreads();
     double wv[Pd];
 #pragma unroll
@@ -537,7 +541,7 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
       for (int i = 0; i < Pd; ++i) sD[(le * V + v) * Pd + i] = wv[i] + S.dt * S.bw * (double)k[i];
     }
     __syncthreads();
-    wave_copy_out<NE * V * Pd>(out + e0 * V * Pd, sD, ne * V * Pd);
+    wave_stream_out<NE * V * Pd>(out + e0 * V * Pd, sD, ne * V * Pd);
     if (S.out2) {
       __syncthreads();
       if (valid) {
@@ -545,11 +549,11 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
         for (int i = 0; i < Pd; ++i) sD[(le * V + v) * Pd + i] = wv[i] + S.dt * S.ar * (double)k[i];
       }
       __syncthreads();
-      wave_copy_out<NE * V * Pd>(S.out2 + e0 * V * Pd, sD, ne * V * Pd);
+      wave_stream_out<NE * V * Pd>(S.out2 + e0 * V * Pd, sD, ne * V * Pd);
     }
     return;
   }
-  if (S.a != 0.0) wave_copy_in<NE * V * Pd>(sD, u_n + e0 * V * Pd, ne * V * Pd);
+  if (S.a != 0.0) wave_stream_in<NE * V * Pd>(sD, u_n + e0 * V * Pd, ne * V * Pd);
   __syncthreads();
   if (valid) {
     double* o = sD + (le * V + v) * Pd;
@@ -562,13 +566,13 @@ __global__ __launch_bounds__(64) void rhs_stage3d_kernel(Mesh M, Async A, Stage 
     }
   }
   __syncthreads();
-  wave_copy_out<NE * V * Pd>(out + e0 * V * Pd, sD, ne * V * Pd);
+  wave_stream_out<NE * V * Pd>(out + e0 * V * Pd, sD, ne * V * Pd);
 }
 
 template <typename T, int P>
 hipError_t launch3d(const Mesh& M, const Async& A, const Stage& S, const double* u_in, const double* u_n,
                     double* out, int src, double* ring, const double* ghost, hipStream_t st) {
-  const long long nblk = (M.E + kNE3 - 1) / kNE3;
+  const long long nblk = wave_ranges<kNE3>(M);
   hipLaunchKernelGGL((rhs_stage3d_kernel<T, P>), dim3((unsigned)nblk), dim3(64), 0, st, M, A, S, u_in, u_n, out, src,
                      ring, ghost);
   return hipGetLastError();

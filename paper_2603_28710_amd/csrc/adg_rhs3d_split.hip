@@ -29,7 +29,8 @@
 //           lfflux-lambda) in canonical (left, right) order; each lane lifts
 //           its variable with BW along both tangential axes onto the face
 //           nodes of its own rows and adds the column of M1^{-1} at that face.
-//   stage:  out = a u_n + b (u_in + dt k) in FP64 from the FP64 registers.
+//   stage:  out = a u_n + b (u_in + dt k) in FP64, written to LDS and
+//           stored as one coalesced, streamed range.
 //
 // The ring publish (stage 0), the delay schedule, the AT extrapolation, the
 // learned ghosts and the flux history follow the same rules as the other
@@ -80,12 +81,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
   // padded so 16-byte reads of consecutive elements spread over the banks
   constexpr int PER0 = 2 * Fq * V;
   constexpr int PER = sizeof(T) == 8 ? PER0 + (6 - PER0 % 4) % 4 : PER0 + (12 - PER0 % 8) % 8;
-  __shared__ __align__(16) T sX[(NE + 1) * PER];
+  // the same LDS stages the wavefront's output (FP64) in the combine
+  constexpr int kXB = (NE + 1) * PER * (int)sizeof(T), kDB = NE * V * Pd * 8;
+  __shared__ __align__(16) unsigned char sRaw[kXB > kDB ? kXB : kDB];
+  T* sX = reinterpret_cast<T*>(sRaw);
+  double* sD = reinterpret_cast<double*>(sRaw);
   __shared__ long long sFsF[NE + 1];  // flux-history modes: face-side of the current face, or -1
   __shared__ int sKdF[NE + 1];        // and its delay
 
   const int lane = threadIdx.x, le = lane / (2 * V), rem = lane - le * 2 * V, v = rem >> 1, h = rem & 1;
-  const long long e = (long long)xcd_block() * NE + le;
+  const long long e0 = (long long)xcd_block() * NE, e = e0 + le;
+  const int ne = M.E - e0 < NE ? (int)(M.E - e0) : NE;
   const bool valid = le < NE && e < M.E;
   const long long col = (valid ? e : 0) * (V * Pd) + v * Pd;  // this lane's variable
   const bool hi = h != 0;
@@ -478,27 +484,52 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
   face_pass(std::integral_constant<int, 4>{});
   face_pass(std::integral_constant<int, 5>{});
 
-  // ---- SSP-RK3 combine in FP64 (the stage input read again, an L2 hit)
-  if (valid) {
+  // ---- the stage combine in FP64 (the stage input read again, an L2 hit);
+  // each output goes through LDS (the lane writes its rows there) and leaves
+  // as one coalesced range
+  __syncthreads();  // sX is rewritten
+  double* od = sD + (le * V + v) * Pd + 2 * h * P;
+  if (S.lserk) {
+    // LSERK: u_n holds the accumulator w (read before either write)
+    if (valid) {
 #pragma unroll
-    for (int iz = 0; iz < P; ++iz) {
-      double* o = out + col + iz * P * P + 2 * h * P;
-      const double* ui = u_in + col + iz * P * P + 2 * h * P;
-      const double* un = u_n + col + iz * P * P + 2 * h * P;
+      for (int iz = 0; iz < P; ++iz) {
+        const double* un = u_n + col + iz * P * P + 2 * h * P;
 #pragma unroll
-      for (int i = 0; i < 2 * P; ++i) {
-        const int n = iz * 2 * P + i;
-        if (S.lserk) {
-          // LSERK: u_n holds the accumulator w (read before either write)
-          const double w = un[i];
-          o[i] = w + S.dt * S.bw * (double)k[n];
-          if (S.out2) S.out2[col + iz * P * P + 2 * h * P + i] = w + S.dt * S.ar * (double)k[n];
-        } else {
-          o[i] = S.a == 0.0 ? S.b * (ui[i] + S.dt * (double)k[n])
-                            : S.a * un[i] + S.b * (ui[i] + S.dt * (double)k[n]);
+        for (int i = 0; i < 2 * P; ++i) od[iz * P * P + i] = un[i] + S.dt * S.bw * (double)k[iz * 2 * P + i];
+      }
+    }
+    __syncthreads();
+    wave_stream_out<NE * V * Pd>(out + e0 * V * Pd, sD, ne * V * Pd);
+    if (S.out2) {
+      __syncthreads();  // the first output has left LDS
+      if (valid) {
+#pragma unroll
+        for (int iz = 0; iz < P; ++iz) {
+          const double* un = u_n + col + iz * P * P + 2 * h * P;
+#pragma unroll
+          for (int i = 0; i < 2 * P; ++i) od[iz * P * P + i] = un[i] + S.dt * S.ar * (double)k[iz * 2 * P + i];
+        }
+      }
+      __syncthreads();
+      wave_stream_out<NE * V * Pd>(S.out2 + e0 * V * Pd, sD, ne * V * Pd);
+    }
+  } else {
+    if (valid) {
+#pragma unroll
+      for (int iz = 0; iz < P; ++iz) {
+        const double* ui = u_in + col + iz * P * P + 2 * h * P;
+        const double* un = u_n + col + iz * P * P + 2 * h * P;
+#pragma unroll
+        for (int i = 0; i < 2 * P; ++i) {
+          const int n = iz * 2 * P + i;
+          od[iz * P * P + i] = S.a == 0.0 ? S.b * (ui[i] + S.dt * (double)k[n])
+                                          : S.a * un[i] + S.b * (ui[i] + S.dt * (double)k[n]);
         }
       }
     }
+    __syncthreads();
+    wave_stream_out<NE * V * Pd>(out + e0 * V * Pd, sD, ne * V * Pd);
   }
 }
 
