@@ -155,6 +155,32 @@ def test_async_at_uniform_3d(oracle_mod, S, seed):
     assert r <= TOL
 
 
+# The degree <= 2 hexahedron kernel cuts each x row into ranges of 12
+# elements (the last one shorter) and orders them in bands of 16 z layers
+# (the last band thinner): rows of 14 and 26 elements, 18 and 35 layers, PE
+# faces inside a range and at a range's end, and the shared x pass's
+# fallback (more than four outside x face-sides: subdomains 3 elements wide).
+@pytest.mark.parametrize("p,cells,parts,ghost,kind,L,levels", [
+    (2, (14, 3, 18), (2, 1, 3), 2, 1, 3, 3),
+    (1, (14, 3, 18), (2, 1, 3), 2, 1, 3, 2),
+    (2, (26, 2, 35), (2, 2, 5), 5, 2, 3, 3),
+    (2, (24, 2, 17), (8, 1, 1), 2, 1, 2, 3),
+    (2, (14, 3, 18), (1, 1, 1), 0, 0, 0, 3),
+])
+def test_hexahedron_wavefront_ranges(oracle_mod, S, p, cells, parts, ghost, kind, L, levels):
+    O = oracle_mod
+    say(f"case: density wave 3D p={p} {cells} parts {parts} ghost={ghost} kind={kind} L={L} levels={levels}, "
+        f"10 steps")
+    o, s = _pair(O, S, problem=O.DENSITY_WAVE, perturb=1e-3, seed=11, dim=3, p=p, cells=cells, parts=parts,
+                 hi=(1, 1, 1), ghost=ghost, delay_kind=kind, L=L, levels=levels)
+    dt = 0.5 * o.stable_dt(0.1)
+    o.step(10, dt)
+    s.step(10, dt)
+    r = rel_l2(s.download(), o.state(), 3, s=s)
+    say("  rel L2", r)
+    assert r <= TOL
+
+
 @pytest.mark.parametrize("p,cells,ghost,kind,L,levels,precision", [
     (3, (8, 8, 8), 2, 0, 2, 3, 0),   # the 64^3 density-wave settings: AT3, fixed L=2
     (3, (8, 8, 8), 2, 1, 2, 3, 0),
