@@ -3,6 +3,7 @@
 // Lax-Friedrichs flux, and the XCD-aware block order. Internal.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 
 namespace adg {
 
@@ -63,54 +64,90 @@ __device__ __forceinline__ void num_flux(const T* wl, const T* wr, int a, T gamm
 }
 
 // n <= NMAX consecutive doubles between global memory and LDS, by the whole
-// wavefront in 16-byte pieces (both addresses 16-byte aligned), four loads in
-// flight per lane before their stores: a wavefront's elements are one
-// contiguous range, so staging them through LDS turns per-lane strided
-// accesses into coalesced ones. NT_LD / NT_ST mark the global loads / stores
-// non-temporal (streamed past L2 with low retention), for data no other
-// wavefront reads in this launch, so that L2 keeps the stage input the
-// neighbouring wavefronts read their face traces from.
+// wavefront, four loads in flight per lane before their stores: a
+// wavefront's elements are one contiguous range, so staging them through LDS
+// turns per-lane strided accesses into coalesced ones. 16-byte pieces when
+// both addresses are 16-byte aligned, else 8-byte pieces (a range of
+// hexahedra of degree 2 starts at an odd multiple of 8 bytes in rows of odd
+// length). NT_LD / NT_ST mark the global loads / stores non-temporal
+// (streamed past L2 with low retention), for data no other wavefront reads
+// in this launch, so that L2 keeps the stage input the neighbouring
+// wavefronts read their face traces from.
 typedef double dvec2 __attribute__((ext_vector_type(2)));
-template <bool NT>
-__device__ __forceinline__ dvec2 ld2(const dvec2* p) {
+template <bool NT, typename X>
+__device__ __forceinline__ X ldg(const X* p) {
   if constexpr (NT) return __builtin_nontemporal_load(p);
   else return *p;
 }
-template <bool NT>
-__device__ __forceinline__ void st2(dvec2* p, dvec2 x) {
+template <bool NT, typename X>
+__device__ __forceinline__ void stg(X* p, X x) {
   if constexpr (NT) __builtin_nontemporal_store(x, p);
   else *p = x;
 }
-template <int NMAX, bool NT_LD, bool NT_ST>
-__device__ __forceinline__ void wave_copy(double* dst, const double* src, int n) {
-  constexpr int IT = (NMAX / 2 + 63) / 64;
-  const int lane = threadIdx.x, n2 = n >> 1;
-  const dvec2* s2 = reinterpret_cast<const dvec2*>(src);
-  dvec2* d2 = reinterpret_cast<dvec2*>(dst);
+template <int NMAX, bool NT_LD, bool NT_ST, typename X>
+__device__ __forceinline__ void wave_copy_pieces(X* d, const X* s, int np) {
+  constexpr int IT = (NMAX * (int)sizeof(double) / (int)sizeof(X) + 63) / 64;
+  const int lane = threadIdx.x;
   // past the end a lane copies piece 0 again (the same value to the same
   // place), which keeps the loop free of branches
 #pragma unroll 1
   for (int k0 = 0; k0 < IT; k0 += 4) {
     const int i0 = lane + 64 * k0, i1 = i0 + 64, i2 = i0 + 128, i3 = i0 + 192;
-    const int j0 = i0 < n2 ? i0 : 0, j1 = i1 < n2 ? i1 : 0, j2 = i2 < n2 ? i2 : 0, j3 = i3 < n2 ? i3 : 0;
-    const dvec2 a0 = ld2<NT_LD>(s2 + j0), a1 = ld2<NT_LD>(s2 + j1), a2 = ld2<NT_LD>(s2 + j2),
-                a3 = ld2<NT_LD>(s2 + j3);
-    st2<NT_ST>(d2 + j0, a0);
-    st2<NT_ST>(d2 + j1, a1);
-    st2<NT_ST>(d2 + j2, a2);
-    st2<NT_ST>(d2 + j3, a3);
+    const int j0 = i0 < np ? i0 : 0, j1 = i1 < np ? i1 : 0, j2 = i2 < np ? i2 : 0, j3 = i3 < np ? i3 : 0;
+    const X a0 = ldg<NT_LD>(s + j0), a1 = ldg<NT_LD>(s + j1), a2 = ldg<NT_LD>(s + j2), a3 = ldg<NT_LD>(s + j3);
+    stg<NT_ST>(d + j0, a0);
+    stg<NT_ST>(d + j1, a1);
+    stg<NT_ST>(d + j2, a2);
+    stg<NT_ST>(d + j3, a3);
   }
-  if ((n & 1) && lane == 0) dst[n - 1] = src[n - 1];
+}
+__device__ __forceinline__ bool aligned16(const void* a, const void* b) {
+  return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0;
+}
+template <int NMAX, bool NT_LD, bool NT_ST>
+__device__ __forceinline__ void wave_copy(double* dst, const double* src, int n) {
+  if (aligned16(dst, src)) {
+    wave_copy_pieces<NMAX, NT_LD, NT_ST>(reinterpret_cast<dvec2*>(dst), reinterpret_cast<const dvec2*>(src), n >> 1);
+    if ((n & 1) && threadIdx.x == 0) dst[n - 1] = src[n - 1];
+  } else {
+    wave_copy_pieces<NMAX, NT_LD, NT_ST>(dst, src, n);
+  }
+}
+// n <= NMAX consecutive doubles from global memory into LDS with direct
+// global-to-LDS loads: each instruction moves 16 bytes per lane, the
+// wavefront's 64 pieces landing contiguously at the LDS address it names,
+// so every load is in flight at once and no register holds the data. Both
+// addresses 16-byte aligned (else the register copy above); the caller
+// waits for them with a barrier before reading the LDS.
+template <int NMAX, bool NT>
+__device__ __forceinline__ void wave_load_lds(double* lds, const double* g, int n) {
+  if (!aligned16(lds, g)) {
+    wave_copy_pieces<NMAX, NT, false>(lds, g, n);
+    return;
+  }
+  constexpr int IT = (NMAX / 2 + 63) / 64;
+  const int lane = threadIdx.x, n2 = n >> 1;
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int i = lane + 64 * k;
+    // a lane past the end would still write its LDS slot: masked off
+    if (i < n2)
+      __builtin_amdgcn_global_load_lds(
+          reinterpret_cast<const void*>(g + 2 * i),
+          reinterpret_cast<__attribute__((address_space(3))) void*>(reinterpret_cast<uintptr_t>(lds + 128 * k)),
+          16, 0, NT ? 2 : 0);
+  }
+  if ((n & 1) && lane == 0) lds[n - 1] = g[n - 1];
 }
 // the stage input: kept in L2 for the neighbours' face traces
 template <int NMAX>
-__device__ __forceinline__ void wave_copy_in(double* lds, const double* g, int n) {
-  wave_copy<NMAX, false, false>(lds, g, n);
+__device__ __forceinline__ void wave_load_in(double* lds, const double* g, int n) {
+  wave_load_lds<NMAX, false>(lds, g, n);
 }
 // u^n and the stage output: streamed
 template <int NMAX>
 __device__ __forceinline__ void wave_stream_in(double* lds, const double* g, int n) {
-  wave_copy<NMAX, true, false>(lds, g, n);
+  wave_load_lds<NMAX, true>(lds, g, n);
 }
 template <int NMAX>
 __device__ __forceinline__ void wave_stream_out(double* g, const double* lds, int n) {

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
   const bool valid = le < ne;
 
   double u[Pd];
-  wave_copy_in<NE * V * Pd>(sD, u_in + e0 * V * Pd, ne * V * Pd);
+  wave_load_in<NE * V * Pd>(sD, u_in + e0 * V * Pd, ne * V * Pd);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < Pd; ++i) u[i] = valid ? sD[(le * V + v) * Pd + i] : 0.0;
