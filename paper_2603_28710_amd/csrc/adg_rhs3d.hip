@@ -6,11 +6,11 @@
 // the P^3 nodal values of variable v of element e in registers (lanes 60-63
 // idle) and applies the tensor-product operators of that variable there. LDS
 // carries what the nonlinear fluxes need (all V variables at a point) and,
-// at the start and in the combine, the wavefront's element data: its 12
-// elements are one contiguous range, moved between global memory and LDS by
-// coalesced 16-byte accesses of the whole wavefront (a lane's own values lie
-// P^3 doubles from the next lane's, so direct per-lane accesses would touch
-// one cache line per lane and instruction).
+// at the start and in the combine, the wavefront's element data: its
+// elements are one contiguous range, moved into LDS by direct global-to-LDS
+// loads and out of it by coalesced 16-byte stores of the whole wavefront (a
+// lane's own values lie P^3 doubles from the next lane's, so direct per-lane
+// accesses would touch one cache line per lane and instruction).
 //
 //   volume: one Gauss plane q_z at a time. The lane combines its nodal
 //           planes along z (B), interpolates the result in x and y, and
@@ -30,9 +30,9 @@
 //           consecutive in x, so each lane interpolates its own traces on both
 //           x faces, and a face between two of its elements (same row, not a
 //           PE face of an asynchronous run) gets its LLF flux once for both
-//           sides; only the other x face-sides (the wavefront's two ends, a
-//           row break, PE faces; at most four, else the per-face passes
-//           below) take a neighbour trace. Then one pass per y and z face:
+//           sides; only the other x face-sides (the wavefront's two ends, PE
+//           faces; at most four, else the per-face passes below) take a
+//           neighbour trace. Then one pass per y and z face:
 //           each lane interpolates its own and the neighbour's face traces
 //           (live values; the delayed / AT / learned trace at a PE-boundary
 //           face; or, in the flux-history modes, the stored flux) to the
@@ -431,8 +431,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
   // lane interpolates its own traces on both x faces, a face between two
   // elements of the wavefront (same row, not a PE face of an asynchronous
   // run) takes its flux once for both sides, and only the other face-sides
-  // (the wavefront's ends, a row break, PE faces) take a neighbour trace,
-  // from up to kExtX outside slots; otherwise the two per-face passes
+  // (the wavefront's ends, PE faces) take a neighbour trace, from up to
+  // kExtX outside slots; otherwise the two per-face passes
   bool x_shared = false;
   if (!flux_mode) {
     // bit l: the +x face of element l is shared with element l + 1
