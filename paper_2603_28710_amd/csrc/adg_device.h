@@ -117,8 +117,10 @@ __device__ __forceinline__ void wave_copy(double* dst, const double* src, int n)
 // global-to-LDS loads: each instruction moves 16 bytes per lane, the
 // wavefront's 64 pieces landing contiguously at the LDS address it names,
 // so every load is in flight at once and no register holds the data. Both
-// addresses 16-byte aligned (else the register copy above); the caller
-// waits for them with a barrier before reading the LDS.
+// addresses 16-byte aligned (else the register copy above). The loads are
+// complete when it returns (the LDS is written behind the compiler's view,
+// so the wait is explicit); the caller's barrier then publishes them to the
+// workgroup.
 template <int NMAX, bool NT>
 __device__ __forceinline__ void wave_load_lds(double* lds, const double* g, int n) {
   if (!aligned16(lds, g)) {
@@ -137,6 +139,7 @@ __device__ __forceinline__ void wave_load_lds(double* lds, const double* g, int 
           reinterpret_cast<__attribute__((address_space(3))) void*>(reinterpret_cast<uintptr_t>(lds + 128 * k)),
           16, 0, NT ? 2 : 0);
   }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   if ((n & 1) && lane == 0) lds[n - 1] = g[n - 1];
 }
 // the stage input: kept in L2 for the neighbours' face traces

@@ -204,8 +204,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
   // u^n for the combine (SSP stages 2 and 3; the accumulator w of the LSERK
   // stages after the first), loaded at the start of the last face pass so
   // that its latency hides behind the y faces (FP64, degree <= 3: elsewhere
-  // the registers would cost occupancy). Only this element reads its column
-  // of u_n, and it writes it only in the combine.
+  // the registers would cost occupancy, and the SSP combine moves u^n into
+  // LDS with direct loads instead). Only this element reads its column of
+  // u_n, and it writes it only in the combine.
   constexpr bool kEarlyUn = sizeof(T) == 8 && P <= 4;
   double un[Pd];
   const bool need_un = kEarlyUn && valid && (S.lserk ? u_n != u_in : S.a != 0.0);
@@ -409,12 +410,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
       wave_stream_out<NE * V * Pd>(S.out2 + e0 * V * Pd, sD, ne * V * Pd);
     }
   } else {
+    if (!kEarlyUn && S.a != 0.0) {
+      wave_stream_in<NE * V * Pd>(sD, u_n + e0 * V * Pd, ne * V * Pd);
+      __syncthreads();
+    }
     if (valid) {
       if (S.a == 0.0) {
 #pragma unroll
         for (int i = 0; i < Pd; ++i) o[i] = S.b * (u[i] + S.dt * (double)k[i]);
+      } else if (!kEarlyUn) {
+#pragma unroll
+        for (int i = 0; i < Pd; ++i) o[i] = S.a * o[i] + S.b * (u[i] + S.dt * (double)k[i]);
       } else {
-        if (!kEarlyUn) load_col<P>(u_n + col, un);
 #pragma unroll
         for (int i = 0; i < Pd; ++i) o[i] = S.a * un[i] + S.b * (u[i] + S.dt * (double)k[i]);
       }
