@@ -30,6 +30,8 @@
  * Readings where the paper is silent (time integrator SSP-RK3, what is delayed,
  * delay draws, warm-up, learned correction) are the ones listed in the design
  * notes; each is marked "reading" below.
+ * Parity unpinned: orc_stable_dt (a reading of the CFL number with nothing
+ * in the paper to pin it against; the tests pass the same dt to both sides).
  */
 #include "adg_oracle.h"
 

@@ -82,6 +82,8 @@ void orc_error_norms(void* s, int problem, const double* params, double t, doubl
 void orc_integrals(void* s, double* out);
 int orc_delay(void* s, int64_t n, int64_t sub, int dir);
 int64_t orc_subdomain(void* s, int64_t e);
+/* dt from a CFL number: a reading (the paper gives no step-size rule), so
+ * parity unpinned; every parity test hands the same dt to both sides */
 double orc_stable_dt(void* s, double cfl);
 /* n.F^ of the configured flux for n = sigma e_a, seen from the side holding wm
  * (Sec. 2.2, eq. lfflux, lfflux-lambda) */
