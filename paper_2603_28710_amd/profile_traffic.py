@@ -121,7 +121,20 @@ def summarize(fetch_csv, write_csv, workload, out):
     print(json.dumps(res, indent=1))
 
 
-def kstats(stats_csv, command, out):
+def first_dispatches(trace_csv, match, n):
+    """(count, average us) of the first n dispatches, in launch order, of the
+    kernel whose name contains match, from a rocprofv3 kernel-trace CSV"""
+    d = []
+    with open(trace_csv) as f:
+        for r in csv.DictReader(f):
+            if match in r["Kernel_Name"]:
+                d.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    d.sort()
+    d = d[:n]
+    return len(d), (sum(x[1] for x in d) / len(d) / 1e3 if d else 0.0)
+
+
+def kstats(stats_csv, command, out, trace_csv=None, match=None, first=None):
     rows = []
     with open(stats_csv) as f:
         for r in csv.DictReader(f):
@@ -134,6 +147,12 @@ def kstats(stats_csv, command, out):
              f"{'kernel':72s} {'calls':>6s} {'total_us':>11s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'pct':>6s}"]
     for n, c, t, a, lo, hi, pct in rows:
         lines.append(f"{n:72s} {c:6d} {t:11.1f} {a:9.2f} {lo:9.2f} {hi:9.2f} {pct:6.2f}")
+    if trace_csv and match and first:
+        # the command's own timed run launches first: its launches alone,
+        # apart from those of the comparison runs that follow
+        cnt, avg = first_dispatches(trace_csv, match, first)
+        lines += ["", f"# first {cnt} dispatches of {match} (the command's first, timed run; from the kernel "
+                      f"trace): avg_us {avg:.2f}"]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -195,6 +214,9 @@ def main():
     k.add_argument("--stats", required=True)
     k.add_argument("--command", required=True)
     k.add_argument("--out", required=True)
+    k.add_argument("--trace", default=None, help="kernel-trace CSV of the same run")
+    k.add_argument("--match", default=None, help="kernel name substring for --first")
+    k.add_argument("--first", type=int, default=None, help="average the first N such dispatches")
     q = sub.add_parser("sqstats")
     q.add_argument("--csv", nargs="+", required=True)
     q.add_argument("--workload", default="vortex256_p3_at3_uniformL3")
@@ -207,7 +229,7 @@ def main():
     elif a.cmd == "sqstats":
         sqstats(a.csv, a.workload, a.out)
     else:
-        kstats(a.stats, a.command, a.out)
+        kstats(a.stats, a.command, a.out, a.trace, a.match, a.first)
 
 
 if __name__ == "__main__":
