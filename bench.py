@@ -21,6 +21,8 @@ from paper_2603_28710_amd import profile_traffic  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+MLP_HIDDEN, MLP_LEVELS = 64, 4  # the learned predictor's hidden width and ring levels read
 
 # Workloads (synthetic, analytic initial states). The default is the 3D
 # density wave rho = 1 + 0.2 sin(2 pi (x+y+z-3t)) on the periodic unit cube,
@@ -445,6 +447,19 @@ def main():
         rate, judged, te, ta = s.predictor_stats(trace_errors=True)
         out["ghost_kernel"].update({"faces_judged": judged, "accept_rate": rate, "mean_trace_err_used": te,
                                     "mean_trace_err_at": ta})
+        # its roofs: per face node it reads MLP_LEVELS ring levels and writes
+        # the ghost (V doubles each); the network is 2 (nin H + H V) flops
+        # on the BF16 matrix cores, nin = 2 V + 2 features
+        nodes = nfs * Fn
+        g_bytes = nodes * s.V * 8.0 * (MLP_LEVELS + 1)
+        g_flops = nodes * 2.0 * ((2 * s.V + 2) * MLP_HIDDEN + MLP_HIDDEN * s.V)
+        g_s = gh_ms / max(gh_n, 1) / 1e3
+        if g_s > 0:
+            out["ghost_kernel"]["roofline"] = {
+                "bound": "hbm", "achieved": g_bytes / g_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": g_bytes / g_s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": g_bytes,
+                "face_nodes": nodes, "mfma_bf16_tflops": g_flops / g_s / 1e12,
+                "mfma_frac": g_flops / g_s / 1e12 / BF16_MFMA_PEAK_TFLOPS}
     main_run = (s.download(), sec, list(err) if err is not None else None)
     s.close()
     del s
