@@ -166,16 +166,17 @@ SQ_PASSES = {
 }
 
 
-def sqstats(csvs, workload, out):
-    """per-wavefront averages of the SQ counters of the stage kernel, from
-    one counter CSV per pass (rocprofv3 collects each pass in its own run)"""
+def sqstats(csvs, workload, out, match="rhs_stage"):
+    """per-wavefront averages of the SQ counters of the kernel whose name
+    contains match (the stage kernel by default), from one counter CSV per
+    pass (rocprofv3 collects each pass in its own run)"""
     per = {}
     kname = None
     for path in csvs:
         disp = {}
         with open(path) as f:
             for row in csv.DictReader(f):
-                if "rhs_stage" not in row["Kernel_Name"]:
+                if match not in row["Kernel_Name"]:
                     continue
                 kname = kname or _short(row["Kernel_Name"])
                 d = disp.setdefault(row["Dispatch_Id"], {})
@@ -221,13 +222,14 @@ def main():
     q.add_argument("--csv", nargs="+", required=True)
     q.add_argument("--workload", default="vortex256_p3_at3_uniformL3")
     q.add_argument("--out", required=True)
+    q.add_argument("--match", default="rhs_stage", help="kernel name substring")
     a = ap.parse_args()
     if a.cmd == "run":
         run(a.workload, a.steps)
     elif a.cmd == "summarize":
         summarize(a.fetch, a.write, a.workload, a.out)
     elif a.cmd == "sqstats":
-        sqstats(a.csv, a.workload, a.out)
+        sqstats(a.csv, a.workload, a.out, a.match)
     else:
         kstats(a.stats, a.command, a.out, a.trace, a.match, a.first)
 
