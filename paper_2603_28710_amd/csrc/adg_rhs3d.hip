@@ -76,13 +76,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
   // per element: the state at the points of one Gauss plane [Fq][V] during
   // the volume, the own and neighbour traces of one face [2][Fq][V] during
   // the faces; one spare element slot for the idle lanes; the stride is
-  // padded so 16-byte reads of consecutive elements spread over the banks
+  // padded against LDS bank conflicts
   constexpr int PER0 = 2 * Fq * V;
   // during the volume: the plane's state [Fq][V], then from kPre the
   // scaled velocity and pressure [Fq][4] (16-byte aligned)
   constexpr int kPre = (Fq * V + 3) / 4 * 4;
   static_assert(kPre + 4 * Fq <= PER0, "volume data exceed the element's LDS block");
-  constexpr int PER = sizeof(T) == 8 ? PER0 + (6 - PER0 % 4) % 4 : PER0 + (12 - PER0 % 8) % 8;
+  // (FP64 degree 2: 164 doubles, = 4 mod 16, keeps the blocks 16-byte
+  // aligned and halves the bank-conflict cycles of the 162 that the rule
+  // below gives, 1750 against 3270 per wavefront; measured over 160-169.
+  // Elsewhere 16-byte reads of consecutive elements spread over the banks.)
+  constexpr int PER = sizeof(T) == 8 ? (P == 3 ? 164 : PER0 + (6 - PER0 % 4) % 4) : PER0 + (12 - PER0 % 8) % 8;
+  static_assert(PER >= PER0, "element block too small");
   // the same LDS stages the wavefront's element data (FP64) at the start and
   // the end of the stage
   // the x pass adds kExtX outside traces [Fq][V] after the element slots
