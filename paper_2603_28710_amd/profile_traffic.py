@@ -163,6 +163,7 @@ SQ_PASSES = {
          "SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64",
     "B": "SQ_WAVES SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY SQ_ACTIVE_INST_VALU "
          "SQ_ACTIVE_INST_SCA SQ_ACTIVE_INST_LDS",
+    "C": "SQ_WAVES SQ_LDS_IDX_ACTIVE SQ_LDS_BANK_CONFLICT",
 }
 
 
