@@ -344,6 +344,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed runs of the K steps on the same solver (the first gives the value)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the matched-error comparisons of the FP32 and learned variants")
     ap.add_argument("--cpu-only", action="store_true",
@@ -461,6 +463,22 @@ def main():
                 "face_nodes": nodes, "mfma_bf16_tflops": g_flops / g_s / 1e12,
                 "mfma_frac": g_flops / g_s / 1e12 / BF16_MFMA_PEAK_TFLOPS}
     main_run = (s.download(), sec, list(err) if err is not None else None)
+    # further timed runs of the same K steps, continuing on the same solver
+    # after the first (which gives the line's value and the state the
+    # comparisons use): the spread of the measurement
+    secs = [sec]
+    for _ in range(max(args.repeats, 1) - 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st_ = s.step_status(args.steps, dt)
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t0)
+        if st_ != 0:
+            raise RuntimeError(B.adg_last_error())
+    vals = sorted(s.ndof * stages / x for x in secs)
+    out["repeats"] = {"n": len(secs), "values": [s.ndof * stages / x for x in secs],
+                      "median": vals[len(vals) // 2] if len(vals) % 2 else 0.5 * (vals[len(vals) // 2 - 1] + vals[len(vals) // 2]),
+                      "mean": sum(vals) / len(vals)}
     s.close()
     del s
     torch.cuda.empty_cache()
