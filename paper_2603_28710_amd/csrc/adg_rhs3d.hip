@@ -455,15 +455,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
     if (__popc(ext) <= kExtX) {
       x_shared = true;
       __syncthreads();  // sX is rewritten
-      // flux items in order: (l, -x) if it takes an outside trace, (l, +x)
-      if (lane == 0) {
-        int n = 0;
-        for (int l = 0; l < ne; ++l) {
-          if ((ext >> (2 * l)) & 1u) sItem[n++] = l * 2;
-          sItem[n++] = l * 2 + 1;
-        }
-        sItem[2 * NE] = n;
+      // flux items in order: (l, -x) if it takes an outside trace, (l, +x);
+      // lane l writes element l's, after the l +x items and the outside -x
+      // items of the elements before it
+      if (lane < ne) {
+        const bool mx = (ext >> (2 * lane)) & 1u;
+        const int at = lane + __popc(ext & 0x55555555u & ((1u << (2 * lane)) - 1u));
+        if (mx) sItem[at] = lane * 2;
+        sItem[at + (mx ? 1 : 0)] = lane * 2 + 1;
       }
+      if (lane == 0) sItem[2 * NE] = ne + __popc(ext & 0x55555555u);
       T* outside = sX + (NE + 1) * PER;  // kExtX traces [Fq][V]
       interp_face([&](int j0, int j1) { return u[node3<P>(0, 0, j0, j1)]; }, mine + v);
       interp_face([&](int j0, int j1) { return u[node3<P>(0, P - 1, j0, j1)]; }, mine + Fq * V + v);
