@@ -250,7 +250,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
   // f: live values, the delayed / AT / learned trace at a PE-boundary face
   // (whose own trace is published at stage 0), nothing in a flux-history
   // silent step; fs and kd receive the face-side and its delay
-  auto gather = [&](auto fc, double* g, long long& fs, int& kd) {
+  auto gather = [&](auto fc, auto at_together, double* g, long long& fs, int& kd) {
     constexpr int f = decltype(fc)::value;
     constexpr int a = f >> 1, s = f & 1, ia = s ? P - 1 : 0;
 #pragma unroll
@@ -288,11 +288,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
       } else {
         // AT extrapolation to the stage time, tau = kd + c_m (eq. at-flux)
         const double tau = kd + A.c_m;
-        for (int l = 0; l < A.levels; ++l) {
-          const double wl = at_weight(l, A.levels, tau);
-          const double* gp = ring + ring_slot(A, kd + l) * ring_level + fs * V * Fn + v * Fn;
+        if constexpr (decltype(at_together)::value) {
+          // the x pass: at most kMaxLevels levels, past A.levels the newest
+          // is read again with weight 0, so every level's loads are in
+          // flight together (in the y and z passes the extra registers
+          // would spill)
 #pragma unroll
-          for (int j = 0; j < Fn; ++j) g[j] = fma(wl, gp[j], g[j]);
+          for (int l = 0; l < kMaxLevels; ++l) {
+            const bool on = l < A.levels;
+            const double wl = on ? at_weight(l, A.levels, tau) : 0.0;
+            const double* gp = ring + ring_slot(A, kd + (on ? l : 0)) * ring_level + fs * V * Fn + v * Fn;
+#pragma unroll
+            for (int j = 0; j < Fn; ++j) g[j] = fma(wl, gp[j], g[j]);
+          }
+        } else {
+          for (int l = 0; l < A.levels; ++l) {
+            const double wl = at_weight(l, A.levels, tau);
+            const double* gp = ring + ring_slot(A, kd + l) * ring_level + fs * V * Fn + v * Fn;
+#pragma unroll
+            for (int j = 0; j < Fn; ++j) g[j] = fma(wl, gp[j], g[j]);
+          }
         }
       }
     }
@@ -362,7 +377,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
     double g[Fn];
     long long fs;
     int kd;
-    gather(fc, g, fs, kd);
+    gather(fc, std::false_type{}, g, fs, kd);
     if (flux_mode && v == 0) {
       sFsF[le] = fs;
       sKdF[le] = kd;
@@ -475,14 +490,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
         double g[Fn];
         long long fs;
         int kd;
-        gather(std::integral_constant<int, 0>{}, g, fs, kd);
+        gather(std::integral_constant<int, 0>{}, std::true_type{}, g, fs, kd);
         interp_face([&](int j0, int j1) { return g[j0 + P * j1]; }, outside + __popc(ext & below) * Fq * V + v);
       }
       if (valid && ((ext >> (2 * le + 1)) & 1u)) {
         double g[Fn];
         long long fs;
         int kd;
-        gather(std::integral_constant<int, 1>{}, g, fs, kd);
+        gather(std::integral_constant<int, 1>{}, std::true_type{}, g, fs, kd);
         interp_face([&](int j0, int j1) { return g[j0 + P * j1]; },
                     outside + __popc(ext & (below | (1u << (2 * le)))) * Fq * V + v);
       }

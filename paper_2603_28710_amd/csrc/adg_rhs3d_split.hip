@@ -311,11 +311,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rh
       } else {
         // AT extrapolation to the stage time, tau = kd + c_m (eq. at-flux)
         const double tau = kd + A.c_m;
-        for (int l = 0; l < A.levels; ++l) {
-          const double wl = at_weight(l, A.levels, tau);
-          const double* gp = ring + ring_slot(A, kd + l) * ring_level + fs * V * Fn + v * Fn;
+        if constexpr (a == 0) {
+          // the x faces: at most kMaxLevels levels, past A.levels the newest
+          // is read again with weight 0, so every level's loads are in
+          // flight together (in the y and z passes the extra registers
+          // would spill)
 #pragma unroll
-          for (int j = 0; j < Fn; ++j) g[j] = fma(wl, gp[j], g[j]);
+          for (int l = 0; l < kMaxLevels; ++l) {
+            const bool on = l < A.levels;
+            const double wl = on ? at_weight(l, A.levels, tau) : 0.0;
+            const double* gp = ring + ring_slot(A, kd + (on ? l : 0)) * ring_level + fs * V * Fn + v * Fn;
+#pragma unroll
+            for (int j = 0; j < Fn; ++j) g[j] = fma(wl, gp[j], g[j]);
+          }
+        } else {
+          for (int l = 0; l < A.levels; ++l) {
+            const double wl = at_weight(l, A.levels, tau);
+            const double* gp = ring + ring_slot(A, kd + l) * ring_level + fs * V * Fn + v * Fn;
+#pragma unroll
+            for (int j = 0; j < Fn; ++j) g[j] = fma(wl, gp[j], g[j]);
+          }
         }
       }
     }
