@@ -172,7 +172,7 @@ def load_traffic(workload):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_sha256_16") != profile_traffic.source_hash():
+    if d.get("source_sha256_16") != profile_traffic.source_hash(d.get("kernel")):
         return None
     return d.get("hbm_bytes_per_launch")
 

@@ -26,12 +26,24 @@ COPY_DOUBLES = 32 * 1024 * 1024  # 256 MiB read + 256 MiB written per copy
 
 KERNEL_SOURCES = ("adg_rhs.hip", "adg_rhs2d.hip", "adg_rhs3d.hip", "adg_rhs3d_split.hip", "adg_device.h",
                   "adg_internal.h", "adg_tables.h")
+SHARED_HEADERS = ("adg_device.h", "adg_internal.h", "adg_tables.h")
+# each stage kernel and its launcher live in one translation unit of their own
+KERNEL_FILES = {"rhs_stage2d_kernel": "adg_rhs2d.hip", "rhs_stage3d_kernel": "adg_rhs3d.hip",
+                "rhs_stage3d_split_kernel": "adg_rhs3d_split.hip", "rhs_stage_kernel": "adg_rhs.hip"}
 
 
-def source_hash():
-    """first 16 hex digits of the SHA-256 of the stage kernel's sources"""
+def kernel_base(name):
+    """'void adg::rhs_stage3d_kernel<double, 3>' -> 'rhs_stage3d_kernel'"""
+    return _short(name).replace("void ", "").split("<")[0].split("::")[-1].strip()
+
+
+def source_hash(kernel=None):
+    """first 16 hex digits of the SHA-256 of a stage kernel's sources: its own
+    translation unit and the shared device headers (every stage kernel's
+    sources when kernel is None)"""
+    files = KERNEL_SOURCES if kernel is None else (KERNEL_FILES[kernel_base(kernel)],) + SHARED_HEADERS
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2603_28710_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -107,7 +119,7 @@ def summarize(fetch_csv, write_csv, workload, out):
     cmd = ("rocprofv3 --pmc {c} --output-format csv -d <dir> -o p -- python3 "
            "paper_2603_28710_amd/profile_traffic.py run --steps 2 --workload " + workload)
     res = {
-        "kernel": kname, "workload": workload, "source_sha256_16": source_hash(),
+        "kernel": kname, "workload": workload, "source_sha256_16": source_hash(kname),
         "fetch_command": cmd.format(c="FETCH_SIZE"), "write_command": cmd.format(c="WRITE_SIZE"),
         "summary_command": "python3 paper_2603_28710_amd/profile_traffic.py summarize --fetch <fetch csv> "
                            "--write <write csv> --workload " + workload + " --out <this file>",
@@ -142,7 +154,10 @@ def kstats(stats_csv, command, out, trace_csv=None, match=None, first=None):
                          float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
                          float(r["Percentage"])))
     rows.sort(key=lambda x: -x[2])
-    lines = [f"# rocprofv3 kernel statistics (kernel sources sha256/16 {source_hash()})",
+    # the stage kernel that takes the most time names the sources hashed
+    stage = next((r[0] for r in rows if "rhs_stage" in r[0]), None)
+    lines = [f"# rocprofv3 kernel statistics ({kernel_base(stage) + ' ' if stage else ''}kernel sources "
+             f"sha256/16 {source_hash(stage)})",
              f"# command: {command}", "",
              f"{'kernel':72s} {'calls':>6s} {'total_us':>11s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'pct':>6s}"]
     for n, c, t, a, lo, hi, pct in rows:
@@ -189,7 +204,8 @@ def sqstats(csvs, workload, out, match="rhs_stage"):
                     per.setdefault(c, []).append(val / w)
     cmd = ("rocprofv3 --pmc {counters} --output-format csv -d <dir> -o p -- python3 "
            "paper_2603_28710_amd/profile_traffic.py run --steps 2 --workload " + workload)
-    lines = [f"# rocprofv3 SQ counters of {kname}, per wavefront (kernel sources sha256/16 {source_hash()})",
+    lines = [f"# rocprofv3 SQ counters of {kname}, per wavefront (kernel sources sha256/16 "
+             f"{source_hash(kname if kname and 'rhs_stage' in kname else None)})",
              f"# workload {workload}; one run per pass:"]
     lines += [f"#   pass {k}: " + cmd.format(counters=v) for k, v in SQ_PASSES.items()]
     lines += ["# (the cycle counters SQ_WAVE_CYCLES, SQ_WAIT_* and SQ_ACTIVE_* tick once per 4 clocks)", ""]

@@ -62,7 +62,23 @@ def test_traffic_summary_scales_by_the_copy(tmp_path):
     # mean fetch 2000 KiB counted (x2 true), write 500 KiB
     assert d["hbm_bytes_per_launch"] == pytest.approx((2000 * 2 + 500) * 1024.0)
     assert d["kernel"] == "void adg::rhs_stage2d_kernel<double, 4>"
-    assert d["source_sha256_16"] == PT.source_hash()
+    assert d["source_sha256_16"] == PT.source_hash(d["kernel"])
+
+
+def test_source_hash_per_stage_kernel():
+    # a profile stays valid while its own kernel's translation unit and the
+    # shared device headers are unchanged; the other kernels' files do not count
+    import hashlib
+    import os
+    d = os.path.join(PT.ROOT, "paper_2603_28710_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("adg_rhs2d.hip", "adg_device.h", "adg_internal.h", "adg_tables.h"):
+        h.update(open(os.path.join(d, f), "rb").read())
+    assert PT.source_hash("void adg::rhs_stage2d_kernel<float, 5>") == h.hexdigest()[:16]
+    assert PT.kernel_base("void adg::rhs_stage3d_split_kernel<double, 4>(adg::Mesh, int)") == \
+        "rhs_stage3d_split_kernel"
+    hashes = {PT.source_hash(k) for k in PT.KERNEL_FILES}
+    assert len(hashes) == len(PT.KERNEL_FILES) and PT.source_hash() not in hashes
 
 
 def test_sq_summary_is_per_wavefront(tmp_path):
