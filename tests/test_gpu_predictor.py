@@ -310,7 +310,7 @@ def test_learned_judge_matches_oracle(oracle_mod, bias, tol, expect, judge):
     assert r <= 1e-11
 
 
-@pytest.mark.parametrize("kind,cfl,max_resid", [(2, 0.1, 0.4), (1, 0.05, 0.85)])
+@pytest.mark.parametrize("kind,cfl,max_resid", [(2, 0.1, 0.3), (1, 0.05, 0.75)])
 def test_train_on_solver_traces_beats_at(oracle_mod, kind, cfl, max_resid):
     """Collect (features, live-minus-AT) pairs from the solver, train on the
     GPU, then measure on fresh pairs how much of AT's trace error remains,
@@ -319,8 +319,11 @@ def test_train_on_solver_traces_beats_at(oracle_mod, kind, cfl, max_resid):
     steps, then delays 1..4) the neighbour's trajectory is deterministic and
     most of AT's error is predictable; with uniform random delays (kind 1)
     the neighbour's own random switching is noise the history cannot
-    predict, so only a gain is required. (Uniform delays up to 4 need
-    CFL 0.05 to stay stable over hundreds of steps.)"""
+    predict, so the network need only remove a quarter of AT's squared
+    trace error there (measured: 0.26 of it remains with the CAA schedule,
+    0.68 with uniform delays; collection and training are deterministic).
+    (Uniform delays up to 4 need CFL 0.05 to stay stable over hundreds of
+    steps.)"""
     O = oracle_mod
     say(f"case: collect / train / evaluate, 3D density wave 16^3 p=2, parts 4^3, L=4, delay kind {kind}")
     cfg = dict(dim=3, degree=2, cells=(16, 16, 16), parts=(4, 4, 4), hi=(1, 1, 1), delay_kind=kind, L=4, levels=3,
