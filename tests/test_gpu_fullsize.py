@@ -14,6 +14,10 @@ configuration bench.py times.
   whole mesh step by step past the warm-up until the largest delay L has been
   used (levels + L + 1 steps or more), relative L2 <= 1e-11; the delays of
   the run are read back through the C ABI and must include every value 1..L.
+- The learned mode of the 128^3 workload (accept bound 1e-6, the default
+  judge) with fixed seeded weights, the whole-mesh oracle running the same
+  weights, 9 steps: relative L2 <= 1e-11 and the same accept decisions
+  (both sides decide in BF16/FP32 alike; 5 % of 9.4 M judged faces accepted).
 - The FP32-contraction variant at 1024^2, degree 4, against the FP64 path of
   the same configuration (itself oracle-pinned above): relative L2 <= 1e-6
   after 100 and after 200 steps.
@@ -185,6 +189,46 @@ def test_full_size_async_whole_mesh(oracle_mod, name, cfg, problem, steps, cfl):
     say("  delays used", sorted(delays), " rel L2", r)
     assert set(range(cfg["L"] + 1)) <= delays
     assert r <= 1e-11
+
+
+@pytest.mark.timeout(900)
+def test_learned_full_size_whole_mesh(oracle_mod):
+    """the learned ghosts of the 128^3 density-wave workload (degree 2, 8^3
+    subdomains, uniform delays up to 4, CFL 0.05, accept bound 1e-6, the
+    default judge) with fixed seeded weights, against the whole-mesh oracle
+    running the same weights: 9 steps, past the warm-up, so delays 1..4
+    reach the network"""
+    from paper_2603_28710_amd import binding as B
+    from tests import inputs
+    O = oracle_mod
+    say("case: learned ghosts, fixed weights, density wave 128^3 p=2, parts 8^3, uniform L=4, 9 steps, "
+        "whole-mesh oracle")
+    cfg = dict(dim=3, cells=(128, 128, 128), parts=(8, 8, 8), hi=(1, 1, 1), ghost=3, delay_kind=1, L=4, levels=3,
+               seed=0, learned_tol=1e-6, learned_judge=1)
+    o = O.Oracle(p=2, **cfg)
+    o.init_problem(O.DENSITY_WAVE)
+    from paper_2603_28710_amd.solver import Solver
+    s = Solver(degree=2, **cfg)
+    w = inputs.mlp_weights(s.predictor_nparams(), 8, 0.05).astype(np.float32)
+    s.predictor_set(w)
+    o.set_predictor(w)
+    s.upload(o.state())
+    dt = o.stable_dt(0.05)
+    delays = set()
+    for n in range(9):
+        for sub in range(512):
+            for d in range(6):
+                delays.add(B.adg_delay(s.h, n, sub, d)[0])
+        s.step(1, dt)
+        o.step(1, dt)
+        say(f"  step {n + 1} of 9")
+    r = rel_l2_groups(s.download().reshape(-1, 5, 27), o.state().reshape(-1, 5, 27), 5)
+    acc_o, rej_o = o.learned_stats()
+    rate, judged = s.predictor_stats()
+    say("  delays used", sorted(delays), " rel L2", r, " gpu accept", rate, judged, " oracle", acc_o, rej_o)
+    assert set(range(5)) <= delays
+    assert r <= 1e-11
+    assert judged == acc_o + rej_o and judged > 0 and abs(rate * judged - acc_o) < 0.5
 
 
 def test_fp32_contractions_full_size_vs_fp64():
