@@ -239,7 +239,7 @@ def test_learned_mode_parity_with_oracle(oracle_mod):
     rate, judged = s.predictor_stats()
     say("  rel L2", r, "gpu accept", rate, judged, "oracle", acc_o, rej_o)
     assert r <= 1e-11
-    assert judged == acc_o + rej_o and abs(rate * judged - acc_o) <= max(1, 1e-3 * judged)
+    assert judged == acc_o + rej_o and abs(rate * judged - acc_o) < 0.5
 
 
 @pytest.mark.parametrize("judge", [0, 1])
@@ -268,7 +268,7 @@ def test_learned_mode_parity_larger_mesh(oracle_mod, judge):
     rate, judged = s.predictor_stats()
     say("  rel L2", r, "gpu accept", rate, judged, "oracle", acc_o, rej_o)
     assert r <= 1e-11
-    assert judged == acc_o + rej_o and judged > 0 and abs(rate * judged - acc_o) <= max(1, 1e-3 * judged)
+    assert judged == acc_o + rej_o and judged > 0 and abs(rate * judged - acc_o) < 0.5
 
 
 @pytest.mark.parametrize("bias,tol,expect,judge", [(1e20, 1e-6, "reject", 0), (1.0, 1e-6, "mixed", 0),
@@ -412,7 +412,7 @@ def test_learned_mode_in_a_dirichlet_box(oracle_mod):
     rate, judged = s.predictor_stats()
     say("  rel L2", r, "gpu accept", rate, judged, "oracle", acc_o, rej_o)
     assert r <= 1e-11
-    assert judged == acc_o + rej_o and judged > 0 and abs(rate * judged - acc_o) <= max(1, 1e-3 * judged)
+    assert judged == acc_o + rej_o and judged > 0 and abs(rate * judged - acc_o) < 0.5
 
 
 def test_trained_predictor_at_the_configured_workload(oracle_mod):
