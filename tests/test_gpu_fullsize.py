@@ -3,6 +3,8 @@ configuration bench.py times.
 
 - 2D vortex 256x256, degree 3, 8x8 subdomains, AT3 with uniform delays in
   {0..3}: the oracle runs the whole mesh, 60 steps; relative L2 <= 1e-11.
+  The same mesh with stale or AT3 ghosts, fixed delays 1..3 or uniform
+  delays, seeds 0-2: 100 steps each.
 - The paper's vortex in its Dirichlet box, 256x256, degree 2, 16x16
   subdomains, Alg. caa-at with L = 4, LSERK(3,3): whole mesh, 60 steps.
 - 3D density wave 64^3 (degree 3), 3D density wave 128^3 (degree 2), 2D vortex
@@ -59,6 +61,41 @@ def cone(cells, dim, samples, radius):
                     x, y, z = (c[0] + dx) % nc[0], (c[1] + dy) % nc[1], (c[2] + dz) % nc[2]
                     out.add(x + nc[0] * (y + nc[1] * z))
     return np.array(sorted(out), dtype=np.int64)
+
+
+C2_RUNS = [
+    # ghost (1 stale, 2 AT3), delay kind (0 fixed L, 1 uniform 0..L), L, seed, CFL
+    (1, 0, 1, 0, 0.1), (1, 0, 3, 0, 0.1), (2, 0, 1, 0, 0.1), (2, 0, 2, 0, 0.05), (2, 0, 3, 0, 0.05),
+    (1, 1, 3, 0, 0.1), (2, 1, 3, 1, 0.1), (2, 1, 3, 2, 0.1),
+]
+
+
+@pytest.mark.parametrize("ghost,kind,L,seed,cfl", C2_RUNS)
+def test_vortex256_p3_modes_100_steps(oracle_mod, ghost, kind, L, seed, cfl):
+    """the 256^2, degree-3 vortex in 8x8 subdomains with stale or AT3 ghosts,
+    fixed delays L or uniform delays in 0..L, seeds 0-2: 100 steps against
+    the whole-mesh oracle, relative L2 <= 1e-11. AT3 with every face delayed
+    by a fixed 2 or 3 steps is past its stability limit at CFL 0.1 (the
+    oracle alone grows a 1e-15 perturbation of the initial state to 9e-12 in
+    100 steps at L = 2 and ends in NaN at L = 3; the limit shrinks with the
+    delay, Sec. 5.3), so those two runs take CFL 0.05, where the same
+    perturbation stays below 5e-15."""
+    from paper_2603_28710_amd.solver import Solver
+    O = oracle_mod
+    cfg = dict(dim=2, cells=(256, 256, 1), parts=(8, 8, 1), hi=(10, 10, 1), ghost=ghost, delay_kind=kind, L=L,
+               levels=3, seed=seed)
+    say(f"case: vortex 256^2 p=3, ghost {ghost}, delay kind {kind}, L={L}, seed {seed}, CFL {cfl}, 100 steps, "
+        "full oracle")
+    o = O.Oracle(p=3, **cfg)
+    o.init_problem(O.VORTEX)
+    s = Solver(degree=3, **cfg)
+    s.upload(o.state())
+    dt = o.stable_dt(cfl)
+    s.step(100, dt)
+    o.step(100, dt)
+    r = rel_l2_groups(s.download().reshape(-1, 4, 16), o.state().reshape(-1, 4, 16), 4)
+    say("  rel L2", r)
+    assert r <= 1e-11
 
 
 def test_vortex256_p3_at3_uniform_60_steps(oracle_mod):
