@@ -192,6 +192,8 @@ ASYNC_FULL = [
                                          ghost=2, delay_kind=1, L=3, levels=3, seed=0), 0, 9, 0.1),
     ("wave64_p3_at3_fixedL2", dict(dim=3, p=3, cells=(64, 64, 64), parts=(4, 4, 4), hi=(1, 1, 1), ghost=2,
                                    delay_kind=0, L=2, levels=3, seed=0), 1, 6, 0.1),
+    ("wave64_p3_at3_uniformL2", dict(dim=3, p=3, cells=(64, 64, 64), parts=(4, 4, 4), hi=(1, 1, 1), ghost=2,
+                                     delay_kind=1, L=2, levels=3, seed=1), 1, 6, 0.1),
     ("wave128_p2_at3_uniformL4", dict(dim=3, p=2, cells=(128, 128, 128), parts=(8, 8, 8), hi=(1, 1, 1), ghost=2,
                                       delay_kind=1, L=4, levels=3, seed=0), 1, 9, 0.05),
 ]
