@@ -152,14 +152,21 @@ def algorithmic_flops_per_element(dim, P, Q):
 
 
 def cpu_model():
-    """model name of the host CPU (Linux /proc/cpuinfo), or the platform's"""
+    """model name of the host CPU with its family and model numbers (Linux
+    /proc/cpuinfo, first processor; a virtual machine may report a generic
+    name), or the platform's"""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for ln in f:
-                if ln.startswith("model name"):
-                    return ln.split(":", 1)[1].strip()
+                if not ln.strip():
+                    break
+                k, _, v = ln.partition(":")
+                info[k.strip()] = v.strip()
     except OSError:
         pass
+    if "model name" in info:
+        return "{} (family {}, model {})".format(info["model name"], info.get("cpu family", "?"), info.get("model", "?"))
     import platform
     return platform.processor() or platform.machine()
 
