@@ -12,7 +12,9 @@ configuration bench.py times.
   a seeded sample of elements one by one through their dependency cone
   (face-distance 2, 1, 0 for the three stages). At step 0 the warm-up makes
   every delay zero, so the asynchronous run equals the synchronous scheme.
-- The same three workloads through the asynchronous path: the oracle runs the
+- The same three workloads through the asynchronous path (and the 64^3
+  mesh with uniform delays, and with the paper's Alg. caa-at on stored
+  fluxes and its schedule): the oracle runs the
   whole mesh step by step past the warm-up until the largest delay L has been
   used (levels + L + 1 steps or more), relative L2 <= 1e-11; the delays of
   the run are read back through the C ABI and must include every value 1..L.
@@ -196,6 +198,11 @@ ASYNC_FULL = [
                                      delay_kind=1, L=2, levels=3, seed=1), 1, 6, 0.1),
     ("wave128_p2_at3_uniformL4", dict(dim=3, p=2, cells=(128, 128, 128), parts=(8, 8, 8), hi=(1, 1, 1), ghost=2,
                                       delay_kind=1, L=4, levels=3, seed=0), 1, 9, 0.05),
+    # the paper's Alg. caa-at with stored fluxes (ghost 5) on its schedule
+    # (delay kind 2): three communicating steps, silent steps with delays
+    # 1..4, then communicating again at step 7
+    ("wave64_p3_fluxat_caaL4", dict(dim=3, p=3, cells=(64, 64, 64), parts=(4, 4, 4), hi=(1, 1, 1), ghost=5,
+                                    delay_kind=2, L=4, levels=3, seed=0), 1, 8, 0.05),
 ]
 
 
