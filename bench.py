@@ -57,6 +57,11 @@ WORKLOADS = {
     "wave128_p2_at3_uniformL4": dict(
         cfg=dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1)),
         asy=dict(ghost=2, delay_kind=1, L=4, levels=3, seed=0), problem=1, precision=0, cfl=0.05, cpu_cells=32),
+    # the same workload with FP32 contractions (FP64 state, AT weights and
+    # combine)
+    "wave128_p2_at3_uniformL4_fp32": dict(
+        cfg=dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1)),
+        asy=dict(ghost=2, delay_kind=1, L=4, levels=3, seed=0), problem=1, precision=1, cfl=0.05, cpu_cells=32),
     "wave128_p2_sync": dict(
         cfg=dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1)),
         asy=dict(ghost=0, delay_kind=0, L=0, levels=3, seed=0), problem=1, precision=0, cfl=0.05, cpu_cells=32),
@@ -91,6 +96,7 @@ DEFAULT = "wave128_p2_at3_uniformL4"
 # default workload: (variant, its FP64 reference, synchronous run or None)
 COMPARISONS = [
     ("wave128_p2_learned_uniformL4", "wave128_p2_at3_uniformL4", "wave128_p2_sync"),
+    ("wave128_p2_at3_uniformL4_fp32", "wave128_p2_at3_uniformL4", None),
     ("vortex1024_p4_at3_uniformL3_fp32", "vortex1024_p4_at3_uniformL3_fp64", None),
 ]
 PROFILE_EVERY = 8

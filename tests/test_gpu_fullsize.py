@@ -22,9 +22,9 @@ configuration bench.py times.
   judge) with fixed seeded weights, the whole-mesh oracle running the same
   weights, 9 steps: relative L2 <= 1e-11 and the same accept decisions
   (both sides decide in BF16/FP32 alike; 5 % of 9.4 M judged faces accepted).
-- The FP32-contraction variant at 1024^2, degree 4, against the FP64 path of
-  the same configuration (itself oracle-pinned above): relative L2 <= 1e-6
-  after 100 and after 200 steps.
+- The FP32-contraction variant at 1024^2, degree 4, and at 128^3, degree 2,
+  against the FP64 path of the same configuration (itself oracle-pinned
+  above): relative L2 <= 1e-6 after 100 and after 200 steps.
 """
 import sys
 
@@ -277,20 +277,29 @@ def test_learned_full_size_whole_mesh(oracle_mod):
     assert judged == acc_o + rej_o and judged > 0 and abs(rate * judged - acc_o) < 0.5
 
 
-def test_fp32_contractions_full_size_vs_fp64():
+FP32_RUNS = [
+    # name, config, problem, CFL
+    ("vortex1024_p4_at3_uniformL3", dict(dim=2, degree=4, cells=(1024, 1024, 1), parts=(8, 8, 1), hi=(10, 10, 1),
+                                         ghost=2, delay_kind=1, L=3, levels=3, seed=0), 0, 0.1),
+    ("wave128_p2_at3_uniformL4", dict(dim=3, degree=2, cells=(128, 128, 128), parts=(8, 8, 8), hi=(1, 1, 1),
+                                      ghost=2, delay_kind=1, L=4, levels=3, seed=0), 1, 0.05),
+]
+
+
+@pytest.mark.parametrize("name,cfg,problem,cfl", FP32_RUNS)
+def test_fp32_contractions_full_size_vs_fp64(name, cfg, problem, cfl):
     """the FP32-contraction variant of the 1024^2, degree-4 vortex (AT3,
-    uniform delays up to 3) stays within 1e-6 (relative L2 per group) of the
+    uniform delays up to 3) and of the 128^3, degree-2 density wave (AT3,
+    uniform delays up to 4) stays within 1e-6 (relative L2 per group) of the
     FP64 path every 100 steps"""
     from paper_2603_28710_amd.solver import Solver
-    say("case: vortex 1024^2 p=4 AT3 uniform L=3, FP32 contractions vs FP64, 200 steps")
-    cfg = dict(dim=2, degree=4, cells=(1024, 1024, 1), parts=(8, 8, 1), hi=(10, 10, 1), ghost=2, delay_kind=1, L=3,
-               levels=3, seed=0)
+    say(f"case: {name}, FP32 contractions vs FP64, 200 steps")
     a = Solver(precision=0, **cfg)
     b = Solver(precision=1, **cfg)
-    a.init_problem(0)
-    b.init_problem(0)
-    dt = a.stable_dt(0.1)
-    assert dt == b.stable_dt(0.1)
+    a.init_problem(problem)
+    b.init_problem(problem)
+    dt = a.stable_dt(cfl)
+    assert dt == b.stable_dt(cfl)
     worst = 0.0
     for k in range(2):
         a.step(100, dt)
