@@ -27,9 +27,14 @@ COPY_DOUBLES = 32 * 1024 * 1024  # 256 MiB read + 256 MiB written per copy
 KERNEL_SOURCES = ("adg_rhs.hip", "adg_rhs2d.hip", "adg_rhs3d.hip", "adg_rhs3d_split.hip", "adg_device.h",
                   "adg_internal.h", "adg_tables.h")
 SHARED_HEADERS = ("adg_device.h", "adg_internal.h", "adg_tables.h")
-# each stage kernel and its launcher live in one translation unit of their own
-KERNEL_FILES = {"rhs_stage2d_kernel": "adg_rhs2d.hip", "rhs_stage3d_kernel": "adg_rhs3d.hip",
-                "rhs_stage3d_split_kernel": "adg_rhs3d_split.hip", "rhs_stage_kernel": "adg_rhs.hip"}
+# each stage kernel and its launcher live in one translation unit of their
+# own, with the shared device headers; the learned predictor's kernel lives
+# with the network's code and headers
+KERNEL_FILES = {"rhs_stage2d_kernel": ("adg_rhs2d.hip",) + SHARED_HEADERS,
+                "rhs_stage3d_kernel": ("adg_rhs3d.hip",) + SHARED_HEADERS,
+                "rhs_stage3d_split_kernel": ("adg_rhs3d_split.hip",) + SHARED_HEADERS,
+                "rhs_stage_kernel": ("adg_rhs.hip",) + SHARED_HEADERS,
+                "ghost_learned_kernel": ("adg_mlp.hip", "adg_mlp.h", "adg_ctx.h", "adg_internal.h")}
 
 
 def kernel_base(name):
@@ -38,10 +43,10 @@ def kernel_base(name):
 
 
 def source_hash(kernel=None):
-    """first 16 hex digits of the SHA-256 of a stage kernel's sources: its own
-    translation unit and the shared device headers (every stage kernel's
+    """first 16 hex digits of the SHA-256 of a kernel's sources: its own
+    translation unit and the headers it includes (every stage kernel's
     sources when kernel is None)"""
-    files = KERNEL_SOURCES if kernel is None else (KERNEL_FILES[kernel_base(kernel)],) + SHARED_HEADERS
+    files = KERNEL_SOURCES if kernel is None else KERNEL_FILES[kernel_base(kernel)]
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, "paper_2603_28710_amd", "csrc", f), "rb") as fh:
@@ -205,7 +210,7 @@ def sqstats(csvs, workload, out, match="rhs_stage"):
     cmd = ("rocprofv3 --pmc {counters} --output-format csv -d <dir> -o p -- python3 "
            "paper_2603_28710_amd/profile_traffic.py run --steps 2 --workload " + workload)
     lines = [f"# rocprofv3 SQ counters of {kname}, per wavefront (kernel sources sha256/16 "
-             f"{source_hash(kname if kname and 'rhs_stage' in kname else None)})",
+             f"{source_hash(kname if kname and kernel_base(kname) in KERNEL_FILES else None)})",
              f"# workload {workload}; one run per pass:"]
     lines += [f"#   pass {k}: " + cmd.format(counters=v) for k, v in SQ_PASSES.items()]
     lines += ["# (the cycle counters SQ_WAVE_CYCLES, SQ_WAIT_* and SQ_ACTIVE_* tick once per 4 clocks)", ""]
